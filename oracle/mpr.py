@@ -1,0 +1,507 @@
+"""FP64 oracle of Memetic Phase Retrieval: operators, memetic steps, drivers.
+
+Test infrastructure only: a plain, slow reference for the HIP library.  Only
+``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline`` leg
+may import it.  Everything is NumPy complex128/float64; NumPy's FFT serves as
+the library primitive for the discrete Fourier transform.
+
+Conventions (shared with the GPU path by specification, not by code):
+
+* Arrays are N x N.  Fourier-domain arrays (M, the mask, spectra) are in FFT
+  order (zero frequency at [0, 0]); ``to_fft_order`` converts a detector-style
+  centred image.  Real-space arrays use natural indices (origin at [0, 0]).
+* ``known`` is the boolean mask Xi (True = measured) of the appendix on missing
+  intensities.
+* Supports are boolean N x N arrays.
+
+Readings of passages that are silent or ambiguous are stated at each function;
+the same list is kept in the design notes.
+"""
+
+import numpy as np
+
+from . import philox
+
+# ----------------------------------------------------------------------------
+# Fourier transform (appendix "phase problem as an optimisation problem",
+# Eq. pm; initialisation appendix, Parseval and Eq. norm)
+# ----------------------------------------------------------------------------
+
+
+def fft2(x):
+    """Unitary forward 2D DFT, X[k,l] = N^-1 sum x[m,n] exp(-2 pi i (km+ln)/N).
+
+    The paper fixes neither sign nor normalisation; it uses Parseval without
+    factors (initialisation appendix), which reads as the unitary transform.
+    """
+    return np.fft.fft2(np.asarray(x, dtype=np.complex128), norm="ortho")
+
+
+def ifft2(X):
+    """Unitary inverse 2D DFT (exp(+2 pi i ...), factor 1/N)."""
+    return np.fft.ifft2(np.asarray(X, dtype=np.complex128), norm="ortho")
+
+
+def to_fft_order(img):
+    """Centred detector layout (DC at [N/2, N/2]) -> FFT order (DC at [0, 0])."""
+    return np.fft.ifftshift(np.asarray(img))
+
+
+# ----------------------------------------------------------------------------
+# Projectors
+# ----------------------------------------------------------------------------
+
+
+def modulus_fourier(X, M, known):
+    """Masked modulus replacement in the Fourier domain (Eq. pm_full).
+
+    Where known: M * X / |X|; where |X| = 0 every phase is equally near, and
+    the reading taken is phase 0, i.e. the value M.  Elsewhere X is kept.
+    """
+    X = np.asarray(X, dtype=np.complex128)
+    out = X.copy()
+    absX = np.abs(X)
+    nz = known & (absX > 0)
+    out[nz] = M[nz] * (X[nz] / absX[nz])
+    z = known & (absX == 0)
+    out[z] = M[z]
+    return out
+
+
+def proj_modulus(x, M, known):
+    """P_M of Eq. pm with the mask of Eq. pm_full: F^-1[modulus_fourier(F[x])]."""
+    return ifft2(modulus_fourier(fft2(x), M, known))
+
+
+def phase_off(chi):
+    """True when chi leaves the phase unconstrained.
+
+    The real-space constraints appendix limits arg(rho) to [-chi pi, chi pi]
+    with chi in (0, 1]; the complex-density section asks for chi = 0 when
+    positivity must not be enforced.  Reading: chi >= 1 and chi <= 0 both mean
+    "no phase constraint".
+    """
+    return chi >= 1.0 or chi <= 0.0
+
+
+def proj_phase(z, chi):
+    """Nearest-point projection onto {z : |arg z| <= chi*pi} (real-space
+    constraints appendix).  chi = 0.5 (positivity) is (max(Re z, 0), Im z)."""
+    z = np.asarray(z, dtype=np.complex128)
+    if phase_off(chi):
+        return z.copy()
+    if chi == 0.5:
+        return np.maximum(z.real, 0.0) + 1j * z.imag
+    theta = chi * np.pi
+    c, s = np.cos(theta), np.sin(theta)
+    re, im = z.real, z.imag
+    aim = np.abs(im)
+    inside = aim * c <= re * s
+    sgn = np.where(im < 0, -1.0, 1.0)
+    p = np.maximum(re * c + aim * s, 0.0)   # component along the nearer edge ray
+    edge = p * c + 1j * sgn * p * s
+    return np.where(inside, z, edge)
+
+
+def proj_constraint(x, S, chi):
+    """P_C = support projector (Eq. ps) combined with the phase constraint."""
+    return np.where(S, proj_phase(x, chi), 0.0)
+
+
+# ----------------------------------------------------------------------------
+# Iterative algorithms (phase-problem section; appendix on ER)
+# ----------------------------------------------------------------------------
+
+
+def er(x, S, M, known, chi):
+    """Error Reduction, x' = P_M P_C x (optimisation-problem appendix)."""
+    return proj_modulus(proj_constraint(x, S, chi), M, known)
+
+
+def hio(x, S, M, known, chi, beta):
+    """Hybrid Input-Output (cited, not written out, in the paper).
+
+    Fienup's rule with y = P_M x: x' = y where y satisfies the real-space
+    constraints (inside S and P_C y = y), otherwise x - beta*y.
+    """
+    y = proj_modulus(x, M, known)
+    feasible = S & (proj_phase(y, chi) == y)
+    return np.where(feasible, y, x - beta * y)
+
+
+def raar(x, S, M, known, chi, beta):
+    """Relaxed Averaged Alternating Reflections (cited, not written out).
+
+    Luke's form beta/2 (R_C R_M + I) x + (1 - beta) P_M x with R = 2P - I,
+    i.e. x' = beta*P_C(2y - x) + beta*x + (1 - 2 beta)*y, y = P_M x.
+    """
+    y = proj_modulus(x, M, known)
+    return beta * proj_constraint(2.0 * y - x, S, chi) + beta * x + (1.0 - 2.0 * beta) * y
+
+
+def sequence(x, S, M, known, chi, alg, beta, n_ia, n_er):
+    """Eq. sequence: n_ia iterations of the IA (HIO or RAAR), then n_er of ER."""
+    step = {"HIO": hio, "RAAR": raar}[alg]
+    for _ in range(n_ia):
+        x = step(x, S, M, known, chi, beta)
+    for _ in range(n_er):
+        x = er(x, S, M, known, chi)
+    return x
+
+
+def schedule_at(g, G, j, j_er, j_end, sigma, sigma_end, tau, tau_end):
+    """Linear parameter changes over generations (appendix "changing values").
+
+    Interpolation and rounding are not given; reading: t = (g-1)/(G-1) (t = 0
+    when G = 1), j(g) = floor(j + t (j_end - j) + 1/2), the ER count keeps the
+    sequence length constant (j + j_ER), sigma and tau interpolate linearly.
+    """
+    t = 0.0 if G <= 1 else (g - 1) / (G - 1)
+    jg = int(np.floor(j + t * (j_end - j) + 0.5))
+    jer = j + j_er - jg
+    return jg, jer, sigma + t * (sigma_end - sigma), tau + t * (tau_end - tau)
+
+
+# ----------------------------------------------------------------------------
+# Fitness (Eq. error_calc)
+# ----------------------------------------------------------------------------
+
+
+def get_error(x, S, M, known):
+    """E = sqrt( sum Xi (|F[S x]| - M)^2 / sum Xi M^2 ), Eq. error_calc.
+
+    The support alone multiplies x (no phase constraint), as the equation is
+    written.  A pattern with sum Xi M^2 = 0 is invalid input.
+    """
+    den = float(np.sum(M[known] ** 2))
+    if not den > 0:
+        raise ValueError("sum of known M^2 must be positive")
+    A = np.abs(fft2(np.where(S, x, 0.0)))
+    num = float(np.sum((A[known] - M[known]) ** 2))
+    return float(np.sqrt(num / den))
+
+
+# ----------------------------------------------------------------------------
+# Shrink-wrap (Eq. shrinkwrap) and the modified shrink-wrap (UpdateSupportSize)
+# ----------------------------------------------------------------------------
+
+
+def gauss_taps(sigma):
+    """1D Gaussian taps w_k ~ exp(-k^2 / 2 sigma^2), |k| <= ceil(4 sigma), sum 1.
+
+    The kernel support and normalisation are not given; reading: radius
+    ceil(4 sigma), unit sum, periodic boundary.  sigma = 0 means no smoothing.
+    """
+    if sigma <= 0:
+        return np.array([1.0])
+    r = int(np.ceil(4.0 * sigma))
+    k = np.arange(-r, r + 1, dtype=np.float64)
+    w = np.exp(-(k * k) / (2.0 * sigma * sigma))
+    return w / w.sum()
+
+
+def smooth(a, sigma):
+    """Circular separable Gaussian smoothing of a real image (rows, then columns)."""
+    w = gauss_taps(sigma)
+    r = (len(w) - 1) // 2
+    a = np.asarray(a, dtype=np.float64)
+    rows = np.zeros_like(a)
+    for i, k in enumerate(range(-r, r + 1)):
+        rows += w[i] * np.roll(a, -k, axis=1)      # out[., j] += w_k a[., j+k]
+    out = np.zeros_like(a)
+    for i, k in enumerate(range(-r, r + 1)):
+        out += w[i] * np.roll(rows, -k, axis=0)
+    return out
+
+
+def update_support(x, S, sigma, tau):
+    """Shrink-wrap UpdateSupport: S' = {a_sigma > tau * max a_sigma}, a = |x|.
+
+    Reading: the modulus |x| is smoothed (complex smoothing is not implied by
+    the text).  If max a_sigma = 0 the support is left unchanged.
+    """
+    a = smooth(np.abs(x), sigma)
+    m = a.max()
+    if not m > 0:
+        return S.copy()
+    return a > tau * m
+
+
+def area_count(alpha, n_pix):
+    """Support size used by UpdateSupportSize: round half up, clamped to [1, N^2]."""
+    return int(min(max(np.floor(alpha + 0.5), 1), n_pix))
+
+
+def update_support_size(x, sigma, alpha):
+    """Modified shrink-wrap: the round(alpha) largest smoothed values form S'.
+
+    Ties at the threshold go to the lower linear index.
+    """
+    a = smooth(np.abs(x), sigma).ravel()
+    k = area_count(alpha, a.size)
+    order = np.lexsort((np.arange(a.size), -a))   # descending value, then index
+    S = np.zeros(a.size, dtype=bool)
+    S[order[:k]] = True
+    return S.reshape(x.shape)
+
+
+# ----------------------------------------------------------------------------
+# Population statistics (self-improvement appendix; oversampling Eq.)
+# ----------------------------------------------------------------------------
+
+
+def generation_stats(E_par, S_par, g, G):
+    """alpha_best, alpha_all, alpha_eval of Alg. improve from the parents.
+
+    best = lowest error, ties to the lowest index; alpha_all = area of the union
+    of the parents' supports; alpha_eval = (g/G) alpha_best + (1 - g/G) alpha_all.
+    """
+    b = int(np.argmin(np.asarray(E_par, dtype=np.float64)))
+    a_best = int(np.count_nonzero(S_par[b]))
+    union = np.zeros_like(S_par[0], dtype=bool)
+    for S in S_par:
+        union |= S
+    a_all = int(np.count_nonzero(union))
+    a_eval = (g / G) * a_best + (1.0 - g / G) * a_all
+    n2 = S_par[0].size
+    return {"best": b, "alpha_best": a_best, "alpha_all": a_all,
+            "alpha_eval": a_eval, "oversampling": n2 / max(a_best, 1)}
+
+
+# ----------------------------------------------------------------------------
+# Crossover appendix: RandomChoice, Reshift, CrossoverMap, mixing
+# ----------------------------------------------------------------------------
+
+
+def random_choice(p, P, seed, g):
+    """Three distinct parents, all different from p (RandomChoice).
+
+    The method is not given; reading: uniform draws over the remaining indices
+    by skip-mapping (draw in [0, P-1-n) and step past the excluded indices in
+    ascending order), which needs no rejection loop.
+    """
+    chosen = []
+    excluded = [p]
+    for i in range(3):
+        r = philox.uniform_int(philox.draw(seed, philox.PURPOSE_CHOICE, g, p, i),
+                               P - 1 - i)
+        for e in sorted(excluded):
+            if r >= e:
+                r += 1
+        chosen.append(r)
+        excluded.append(r)
+    return tuple(chosen)
+
+
+def reshift(Xq, Sq, Xref, known):
+    """Align parent q to the reference (Reshift; Eq. crosscorr).
+
+    Cross-correlations through the masked convolution theorem:
+    C1 = F^-1[Xi conj(Xq) Xref] (parent as is) and C2 = F^-1[Xi Xq Xref]
+    (the twin rho*(-x), whose transform is conj(Xq)).  d = argmax |C| (ties to
+    the lowest FFT-order index), the twin is kept iff its peak is strictly
+    higher, phi = arg C(d).  Result: X' = e^{i phi} e^{-2 pi i k.d/N} (Xq or
+    conj Xq), S'(y) = S(y - d) or S(d - y).
+    """
+    N = Xq.shape[0]
+    C1 = ifft2(known * np.conj(Xq) * Xref)
+    C2 = ifft2(known * Xq * Xref)
+    m1, m2 = np.abs(C1).ravel(), np.abs(C2).ravel()
+    d1, d2 = int(np.argmax(m1)), int(np.argmax(m2))
+    twin = bool(m2[d2] > m1[d1])
+    d = d2 if twin else d1
+    val = (C2 if twin else C1).ravel()[d]
+    phase = np.exp(1j * np.angle(val)) if abs(val) > 0 else 1.0 + 0j
+    dr, dc = divmod(d, N)
+    k = np.arange(N)
+    ramp_idx = (k[:, None] * dr + k[None, :] * dc) % N
+    ramp = np.exp(-2j * np.pi * ramp_idx / N)
+    Xb = np.conj(Xq) if twin else Xq
+    Xout = phase * ramp * Xb
+    if twin:
+        St = np.roll(Sq[::-1, ::-1], 1, axis=(0, 1))   # S(-y)
+        Sout = np.roll(St, (dr, dc), axis=(0, 1))       # S(d - y)
+    else:
+        Sout = np.roll(Sq, (dr, dc), axis=(0, 1))       # S(y - d)
+    info = {"shift": (dr, dc), "twin": twin, "phase": complex(phase),
+            "peak1": float(m1[d1]), "peak2": float(m2[d2]),
+            "second1": float(np.partition(m1, -2)[-2]) if m1.size > 1 else 0.0,
+            "second2": float(np.partition(m2, -2)[-2]) if m2.size > 1 else 0.0}
+    return Xout, Sout, info
+
+
+# Integer rotations (a, b, h) with a^2 + b^2 = h^2: cos = a/h, sin = b/h.
+# Angles 0, 16.3, 22.6, 28.1, 36.9, 53.1, 61.9, 67.4, 73.7 degrees; rotating a
+# rectangular tiling by 90 degrees only swaps the tile sides, so [0, 90) covers
+# the distinct grids.
+ROTATIONS = ((1, 0, 1), (24, 7, 25), (12, 5, 13), (15, 8, 17), (4, 3, 5),
+             (3, 4, 5), (8, 15, 17), (5, 12, 13), (7, 24, 25))
+
+
+def map_params(N, seed, g, p, t_min, t_max):
+    """Tile sides, grid shift and rotation of one crossover map.
+
+    Reading: one (t_x, t_y) per map drawn uniformly from [t_min, t_max], a
+    shift uniform in [0, t) per axis, and a rotation from ROTATIONS.
+    """
+    d = [philox.draw(seed, philox.PURPOSE_MAPPARAM, g, p, i) for i in range(5)]
+    span = t_max - t_min + 1
+    tx = t_min + philox.uniform_int(d[0], span)
+    ty = t_min + philox.uniform_int(d[1], span)
+    sx = philox.uniform_int(d[2], tx)
+    sy = philox.uniform_int(d[3], ty)
+    rot = philox.uniform_int(d[4], len(ROTATIONS))
+    return tx, ty, sx, sy, rot
+
+
+def tile_key(qx, qy):
+    return ((qx & 0xFFFF) << 16) | (qy & 0xFFFF)
+
+
+def crossover_map(N, seed, g, p, c_p, t_min, t_max):
+    """Binary crossover map of the Fourier domain (CrossoverMap, Fig. crossmap).
+
+    The domain (signed frequencies u for rows, v for columns) is tiled by
+    t_x x t_y rectangles, rotated by an integer Pythagorean rotation and
+    shifted; each tile is elected with probability C_p.
+    """
+    return crossover_map_with(N, map_params(N, seed, g, p, t_min, t_max), seed, g, p, c_p)
+
+
+def crossover_map_with(N, params, seed, g, p, c_p):
+    """Crossover map for given (t_x, t_y, s_x, s_y, rotation index)."""
+    tx, ty, sx, sy, rot = params
+    a, b, h = ROTATIONS[rot]
+    thr = philox.bernoulli_threshold(c_p)
+    cache = {}
+    out = np.zeros((N, N), dtype=bool)
+    for i in range(N):
+        u = i if i < N // 2 else i - N
+        for j in range(N):
+            v = j if j < N // 2 else j - N
+            ur = a * u + b * v
+            vr = -b * u + a * v
+            qx = (ur + h * sx) // (h * tx)
+            qy = (vr + h * sy) // (h * ty)
+            key = tile_key(qx, qy)
+            if key not in cache:
+                w = philox.philox4x32_10((key, p, g, philox.PURPOSE_TILE),
+                                         philox.seed_key(seed))[0]
+                cache[key] = w < thr
+            out[i, j] = cache[key]
+    return out
+
+
+def default_t_max(N, t_min=4):
+    """Example value t_max = N/8 of the crossover appendix, kept >= t_min."""
+    return max(t_min, N // 8)
+
+
+def crossover(xs, Ss, known, g, seed, c_p, c_w, t_min, t_max):
+    """Alg. crossover: one child per parent p from three aligned parents.
+
+    Non-map Fourier pixels keep the child's own parent p ("Copy"); map pixels
+    take X_a + C_w (X_b - X_c); the support is S_a OR (S_b AND S_c AND S_p);
+    the child density is the inverse transform of the mixed spectrum.
+    """
+    P = len(xs)
+    N = xs[0].shape[0]
+    Xs = [fft2(x) for x in xs]
+    kids_x, kids_S, infos = [], [], []
+    for p in range(P):
+        abc = random_choice(p, P, seed, g)
+        aligned = [reshift(Xs[q], Ss[q], Xs[p], known) for q in abc]
+        cmap = crossover_map(N, seed, g, p, c_p, t_min, t_max)
+        (Xa, Sa, ia), (Xb, Sb, ib), (Xc, Sc, ic) = aligned
+        Xn = np.where(cmap, Xa + c_w * (Xb - Xc), Xs[p])
+        Sn = Sa | (Sb & Sc & Ss[p])
+        kids_x.append(ifft2(Xn))
+        kids_S.append(Sn)
+        infos.append({"abc": abc, "align": (ia, ib, ic), "map": cmap})
+    return kids_x, kids_S, infos
+
+
+def select(E_old, E_new):
+    """Alg. select: child p replaces parent p iff E_new < E_old (strict)."""
+    return [bool(en < eo) for eo, en in zip(E_old, E_new)]
+
+
+# ----------------------------------------------------------------------------
+# Drivers: Alg. randomsearch + normalimprove (plain) and Alg. mpr + improve
+# ----------------------------------------------------------------------------
+
+
+def _bcast_supports(S0, P):
+    S0 = np.asarray(S0, dtype=bool)
+    if S0.ndim == 2:
+        return [S0.copy() for _ in range(P)]
+    return [s.copy() for s in S0]
+
+
+def run_plain(M, known, x0, S0, prm):
+    """Plain multi-start reconstruction (Alg. randomsearch with normalimprove).
+
+    ``prm`` keys: alg, beta, chi, G, j, j_er, j_end, sigma, sigma_end, tau,
+    tau_end.  Each generation runs Sequence then UpdateSupport on every member;
+    the error of every member is evaluated at the end and Best is the lowest
+    (ties to the lowest index).
+    """
+    xs = [np.asarray(x, dtype=np.complex128).copy() for x in x0]
+    Ss = _bcast_supports(S0, len(xs))
+    for g in range(1, prm["G"] + 1):
+        jg, jer, sg, tg = schedule_at(g, prm["G"], prm["j"], prm["j_er"], prm.get("j_end", 0),
+                                      prm["sigma"], prm["sigma_end"], prm["tau"], prm["tau_end"])
+        for m in range(len(xs)):
+            xs[m] = sequence(xs[m], Ss[m], M, known, prm["chi"], prm["alg"], prm["beta"], jg, jer)
+            Ss[m] = update_support(xs[m], Ss[m], sg, tg)
+    E = [get_error(x, S, M, known) for x, S in zip(xs, Ss)]
+    return {"x": xs, "S": Ss, "E": E, "best": int(np.argmin(E))}
+
+
+def improve_member(x, S, M, known, prm, g, stats):
+    """Alg. improve for one reconstruction (both populations run this)."""
+    jg, jer, sg, tg = schedule_at(g, prm["G"], prm["j"], prm["j_er"], prm.get("j_end", 0),
+                                  prm["sigma"], prm["sigma_end"], prm["tau"], prm["tau_end"])
+    chi, alg, beta = prm["chi"], prm["alg"], prm["beta"]
+    for _ in range(prm["R"] - 2):
+        x = sequence(x, S, M, known, chi, alg, beta, jg, jer)
+        S = update_support(x, S, sg, tg)
+    x = sequence(x, S, M, known, chi, alg, beta, jg, jer)
+    S = update_support_size(x, sg, stats["alpha_best"])
+    x = sequence(x, S, M, known, chi, alg, beta, jg, jer)
+    S = update_support_size(x, sg, stats["alpha_eval"])
+    x = sequence(x, S, M, known, chi, alg, beta, 0, prm["j_eval"])
+    E = get_error(x, S, M, known)
+    S = update_support(x, S, sg, tg)
+    return x, S, E
+
+
+def run_mpr(M, known, x0, S0, prm, seed, gen_offset=0, generations=None):
+    """Alg. mpr without the final Average: crossover, improve both, select.
+
+    ``prm`` adds R, j_eval, c_p, c_w, t_min, t_max to the plain keys.  The
+    errors of the initial population are evaluated first (GetError), since the
+    first generation's statistics need them.  Generations gen_offset+1 ..
+    gen_offset+generations are run (all G by default).
+    """
+    xs = [np.asarray(x, dtype=np.complex128).copy() for x in x0]
+    P = len(xs)
+    Ss = _bcast_supports(S0, P)
+    E = [get_error(x, S, M, known) for x, S in zip(xs, Ss)]
+    G = prm["G"]
+    n_gen = G - gen_offset if generations is None else generations
+    history = []
+    for g in range(gen_offset + 1, gen_offset + n_gen + 1):
+        kx, kS, infos = crossover(xs, Ss, known, g, seed, prm["c_p"], prm["c_w"],
+                                  prm["t_min"], prm["t_max"])
+        stats = generation_stats(E, Ss, g, G)
+        new_par = [improve_member(xs[p], Ss[p], M, known, prm, g, stats) for p in range(P)]
+        new_kid = [improve_member(kx[p], kS[p], M, known, prm, g, stats) for p in range(P)]
+        repl = select([e for _, _, e in new_par], [e for _, _, e in new_kid])
+        xs, Ss, E = [], [], []
+        for p in range(P):
+            src = new_kid[p] if repl[p] else new_par[p]
+            xs.append(src[0]); Ss.append(src[1]); E.append(src[2])
+        history.append({"g": g, "stats": stats, "replaced": repl, "crossover": infos,
+                        "E_par": [e for _, _, e in new_par], "E_kid": [e for _, _, e in new_kid]})
+    return {"x": xs, "S": Ss, "E": E, "history": history}

@@ -1,0 +1,268 @@
+"""Pins of the oracle's memetic operators and drivers (CPU only)."""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mpr, philox
+from paper_2409_07413_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        assert philox.philox4x32_10(v[0:4], v[4:6]) == v[6:10]
+
+
+def test_uniform_int_and_bernoulli_edges():
+    assert philox.uniform_int(0, 7) == 0
+    assert philox.uniform_int(0xFFFFFFFF, 7) == 6
+    assert philox.bernoulli_threshold(1.0) == 1 << 32
+    assert philox.bernoulli_threshold(0.0) == 0
+    assert philox.bernoulli_threshold(0.5) == 1 << 31
+
+
+def test_random_choice_distinct_and_uniform():
+    P = 6
+    counts = np.zeros((P, P), int)
+    for g in range(1, 400):
+        for p in range(P):
+            abc = mpr.random_choice(p, P, 1234, g)
+            assert len(set(abc)) == 3 and p not in abc
+            assert all(0 <= q < P for q in abc)
+            counts[p, abc[0]] += 1
+    # each parent a is uniform over the other P-1 indices (chi-square, 5 dof)
+    for p in range(P):
+        obs = np.delete(counts[p], p)
+        exp = obs.sum() / (P - 1)
+        chi2 = np.sum((obs - exp) ** 2 / exp)
+        assert chi2 < 25.0
+    # minimum population P = 4 uses every other index exactly once
+    for p in range(4):
+        assert sorted(mpr.random_choice(p, 4, 9, 1)) == [q for q in range(4) if q != p]
+
+
+def brute_corr(x, r, known=None):
+    """Cross-correlation sum_x conj(x(y)) r(y + d) by explicit sums (no mask)."""
+    n = x.shape[0]
+    out = np.zeros((n, n), complex)
+    for d0 in range(n):
+        for d1 in range(n):
+            out[d0, d1] = np.sum(np.conj(x) * np.roll(r, (-d0, -d1), axis=(0, 1)))
+    return out
+
+
+def test_masked_correlation_bruteforce_8():
+    n = 8
+    x = synth.random_complex((n, n), 1)
+    r = synth.random_complex((n, n), 2)
+    known = np.ones((n, n), bool)
+    C = mpr.ifft2(known * np.conj(mpr.fft2(x)) * mpr.fft2(r))
+    np.testing.assert_allclose(C * n, brute_corr(x, r), atol=1e-11)
+
+
+@pytest.mark.parametrize("twin", [False, True])
+def test_reshift_recovers_known_transform(twin):
+    n = 32
+    rng = np.random.default_rng(5)
+    x = np.zeros((n, n), complex)
+    x[10:20, 12:19] = rng.uniform(0.5, 1.5, size=(10, 7)) * np.exp(0.3j * rng.standard_normal((10, 7)))
+    S = np.abs(x) > 0
+    d0 = (7, 29)
+    phi0 = 1.1
+    base = np.conj(np.roll(x[::-1, ::-1], 1, axis=(0, 1))) if twin else x
+    ref = np.exp(1j * phi0) * np.roll(base, d0, axis=(0, 1))
+    known = np.ones((n, n), bool)
+    Xo, So, info = mpr.reshift(mpr.fft2(x), S, mpr.fft2(ref), known)
+    assert info["twin"] == twin
+    assert info["shift"] == d0
+    assert abs(info["phase"] - np.exp(1j * phi0)) < 1e-10
+    np.testing.assert_allclose(mpr.ifft2(Xo), ref, atol=1e-10)
+    np.testing.assert_array_equal(So, np.abs(ref) > 0)
+
+
+def test_reshift_with_mask_still_aligns():
+    n = 32
+    obj = synth.ellipses(n, 3, count=2, semi=(2.0, 4.0), disk_diameter=14.0)
+    known = mpr.to_fft_order(synth.beamstop_gap_mask(n, 4, 2))
+    ref = np.roll(obj, (5, 3), axis=(0, 1)).astype(complex)
+    Xo, So, info = mpr.reshift(mpr.fft2(obj), obj > 0, mpr.fft2(ref), known)
+    assert info["shift"] == (5, 3) and not info["twin"]
+    np.testing.assert_allclose(mpr.ifft2(Xo), ref, atol=1e-10)
+
+
+def test_crossover_map_extremes_and_axis_aligned_tiles():
+    n = 64
+    assert mpr.crossover_map(n, 7, 1, 0, 1.0, 4, 8).all()
+    assert not mpr.crossover_map(n, 7, 1, 0, 0.0, 4, 8).any()
+    # identity rotation: tiles are t_x by t_y rectangles on the signed-frequency grid
+    tx, ty, sx, sy = 5, 7, 2, 3
+    m = mpr.crossover_map_with(n, (tx, ty, sx, sy, 0), 99, 2, 3, 0.5)
+    u = np.array([i if i < n // 2 else i - n for i in range(n)])
+    # reorder rows/cols into increasing signed frequency; the map is then piecewise
+    # constant on blocks whose boundaries sit where (u + s) is a multiple of t
+    order = np.argsort(u)
+    mm = m[np.ix_(order, order)]
+    us = u[order]
+    qx = np.floor_divide(us + sx, tx)
+    qy = np.floor_divide(us + sy, ty)
+    for i in range(n):
+        for j in range(n):
+            same = (qx == qx[i])[:, None] & (qy == qy[j])[None, :]
+            assert np.all(mm[same] == mm[i, j])
+    # interior block sizes are exactly t_x and t_y
+    _, cx = np.unique(qx, return_counts=True)
+    _, cy = np.unique(qy, return_counts=True)
+    assert set(cx[1:-1]) == {tx} and set(cy[1:-1]) == {ty}
+    # about half the tiles are elected at C_p = 0.5 over many maps
+    frac = np.mean([mpr.crossover_map(n, 5, g, 0, 0.5, 4, 8).mean() for g in range(1, 40)])
+    assert 0.4 < frac < 0.6
+
+
+def test_crossover_map_rotation_is_exact_integer_rotation():
+    # with rotation (4, 3, 5) the map is constant along the rotated tile cells
+    n = 64
+    params = (6, 9, 1, 4, 4)
+    m = mpr.crossover_map_with(n, params, 11, 1, 0, 0.5)
+    a, b, h = mpr.ROTATIONS[4]
+    assert (a, b, h) == (4, 3, 5) and a * a + b * b == h * h
+    for i in range(n):
+        for j in range(n):
+            u = i if i < n // 2 else i - n
+            v = j if j < n // 2 else j - n
+            qx = (a * u + b * v + h * params[2]) // (h * params[0])
+            qy = (-b * u + a * v + h * params[3]) // (h * params[1])
+            key = ((qx & 0xFFFF) << 16) | (qy & 0xFFFF)
+            w = philox.philox4x32_10((key, 0, 1, philox.PURPOSE_TILE), philox.seed_key(11))[0]
+            assert m[i, j] == (w < philox.bernoulli_threshold(0.5))
+
+
+def _small_population(n=32, P=4, seed=3):
+    sh = synth.shot(n, "ellipses", seed, 1e6, beamstop=4, count=3, semi=(2.0, 5.0),
+                    disk_diameter=14.0)
+    M = mpr.to_fft_order(sh["amp"])
+    known = mpr.to_fft_order(sh["mask"])
+    x0 = synth.random_phase_starts(sh["amp"], sh["mask"], P, seed + 1)
+    S0 = synth.centred_square(n, 16)
+    return M, known, x0, S0
+
+
+def test_crossover_special_cases():
+    M, known, x0, S0 = _small_population()
+    P = len(x0)
+    Ss = [S0.copy() for _ in range(P)]
+    # C_p = 0: children are copies of their parents
+    kx, kS, infos = mpr.crossover(list(x0), Ss, known, 1, 77, 0.0, 0.4, 4, 4)
+    for p in range(P):
+        np.testing.assert_allclose(kx[p], x0[p], atol=1e-12)
+    # map all ones and C_w = 0: children are the aligned parent a
+    kx, kS, infos = mpr.crossover(list(x0), Ss, known, 2, 77, 1.0, 0.0, 4, 4)
+    for p in range(P):
+        a = infos[p]["abc"][0]
+        Xa, Sa, _ = mpr.reshift(mpr.fft2(x0[a]), Ss[a], mpr.fft2(x0[p]), known)
+        np.testing.assert_allclose(kx[p], mpr.ifft2(Xa), atol=1e-12)
+    # the support logic S_a | (S_b & S_c & S_p) on aligned supports
+    for p in range(P):
+        a, b, c = infos[p]["abc"]
+        Xa, Sa, _ = mpr.reshift(mpr.fft2(x0[a]), Ss[a], mpr.fft2(x0[p]), known)
+        Xb, Sb, _ = mpr.reshift(mpr.fft2(x0[b]), Ss[b], mpr.fft2(x0[p]), known)
+        Xc, Sc, _ = mpr.reshift(mpr.fft2(x0[c]), Ss[c], mpr.fft2(x0[p]), known)
+        np.testing.assert_array_equal(kS[p], Sa | (Sb & Sc & Ss[p]))
+
+
+def test_crossover_mix_formula_on_map():
+    M, known, x0, S0 = _small_population(seed=8)
+    P = len(x0)
+    Ss = [S0.copy() for _ in range(P)]
+    kx, kS, infos = mpr.crossover(list(x0), Ss, known, 3, 5, 0.6, 0.4, 4, 4)
+    for p in range(P):
+        a, b, c = infos[p]["abc"]
+        Xp = mpr.fft2(x0[p])
+        Xq = [mpr.reshift(mpr.fft2(x0[q]), Ss[q], Xp, known)[0] for q in (a, b, c)]
+        cmap = infos[p]["map"]
+        K = mpr.fft2(kx[p])
+        np.testing.assert_allclose(K[cmap], (Xq[0] + 0.4 * (Xq[1] - Xq[2]))[cmap], atol=1e-11)
+        np.testing.assert_allclose(K[~cmap], Xp[~cmap], atol=1e-11)
+
+
+def test_select_bruteforce():
+    old = [0.5, 0.2, 0.3, 0.3]
+    new = [0.4, 0.2, 0.31, 0.1]
+    assert mpr.select(old, new) == [True, False, False, True]
+
+
+def _plain_prm(**kw):
+    prm = dict(alg="HIO", beta=0.9, chi=0.5, G=3, j=6, j_er=4, j_end=0,
+               sigma=2.0, sigma_end=1.0, tau=0.1, tau_end=0.1)
+    prm.update(kw)
+    return prm
+
+
+def test_plain_driver_counts_and_best(monkeypatch):
+    M, known, x0, S0 = _small_population()
+    calls = {"hio": 0, "er": 0, "sw": 0}
+    hio, er, sw = mpr.hio, mpr.er, mpr.update_support
+
+    def c_hio(*a, **k):
+        calls["hio"] += 1
+        return hio(*a, **k)
+
+    def c_er(*a, **k):
+        calls["er"] += 1
+        return er(*a, **k)
+
+    def c_sw(*a, **k):
+        calls["sw"] += 1
+        return sw(*a, **k)
+
+    monkeypatch.setattr(mpr, "hio", c_hio)
+    monkeypatch.setattr(mpr, "er", c_er)
+    monkeypatch.setattr(mpr, "update_support", c_sw)
+    out = mpr.run_plain(M, known, x0, S0, _plain_prm())
+    P = len(x0)
+    # j(g) = 6, 3, 0 -> IA 9 per member, ER 30 - 9 = 21 per member
+    assert calls["hio"] == 9 * P and calls["er"] == 21 * P and calls["sw"] == 3 * P
+    assert out["best"] == int(np.argmin(out["E"]))
+    assert all(0 <= e < 2 for e in out["E"])
+
+
+def test_mpr_driver_counts_and_selection(monkeypatch):
+    M, known, x0, S0 = _small_population(P=4)
+    prm = _plain_prm(alg="RAAR", G=2, R=3, j=4, j_er=2, j_eval=3, c_p=0.6, c_w=0.4,
+                     t_min=4, t_max=4, sigma_end=0.5, tau_end=0.1 * 2 / 3)
+    counts = {"it": 0}
+    raar, er = mpr.raar, mpr.er
+
+    def c_raar(*a, **k):
+        counts["it"] += 1
+        return raar(*a, **k)
+
+    def c_er(*a, **k):
+        counts["it"] += 1
+        return er(*a, **k)
+
+    monkeypatch.setattr(mpr, "raar", c_raar)
+    monkeypatch.setattr(mpr, "er", c_er)
+    out = mpr.run_mpr(M, known, x0, S0, prm, seed=3002)
+    # R (j + j_ER) + j_eval iterations per member, 2P members, G generations
+    assert counts["it"] == 2 * 4 * 2 * (3 * 6 + 3)
+    h = out["history"]
+    assert len(h) == 2
+    for rec in h:
+        exp = [en < eo for eo, en in zip(rec["E_par"], rec["E_kid"])]
+        assert rec["replaced"] == exp
+        for p in range(4):
+            assert rec["stats"]["alpha_best"] >= 1
+    # errors of the survivors are the min of the pair
+    last = h[-1]
+    for p in range(4):
+        assert out["E"][p] == min(last["E_par"][p], last["E_kid"][p]) or \
+            (last["E_par"][p] == last["E_kid"][p] and out["E"][p] == last["E_par"][p])
+    # every member has the evaluation support size alpha_eval... then the final SW
+    assert all(S.dtype == bool for S in out["S"])
