@@ -1,0 +1,217 @@
+"""Benchmark of the MPR hot path on one MI355X.
+
+Workload (the headline configuration): 512 x 512 detector, clustered projected
+spheres (150-px extent), 1e8 photons with Poisson noise, 24 x 24 beamstop plus
+a 4-px horizontal gap; P = 64 parents (128 members with the children); the MPR
+generation schedule of Alg. mpr / Alg. improve with RAAR (beta 0.9), R = 3
+sequences of 20 iterations plus 40 ER evaluation iterations, i.e. 100
+member-iterations per member per generation, shrink-wrap sigma 2 -> 0.5,
+tau 0.10 -> 2/3 tau, crossover C_p 0.6, C_w 0.4, tiles 4..64.
+
+One step = one full generation (crossover, statistics, self-improvement of all
+128 members with shrink-wrap / support-area updates and fitness, selection).
+Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: member-iterations/s, the roofline of the dominant kernel
+(algorithmic bytes per launch / average launch time from HIP events on the
+launch stream) and the FP64 oracle timed on the host cores on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+N, P = 512, 64
+R, J, J_ER, J_EVAL = 3, 16, 4, 40
+G_SCHEDULE = 20
+
+
+def make_inputs():
+    from paper_2409_07413_amd import synth
+    sh = synth.shot(N, "spheres", 1004, 1e8, beamstop=24, gap=4)
+    rho0 = synth.sphere_starts(sh["amp"], sh["mask"], P, 2004, sigma_init=180)
+    supp0 = synth.centred_square(N, 180).astype(np.uint8)
+    return sh, rho0.astype(np.complex64), supp0
+
+
+def mpr_params(g, G, init):
+    return dict(alg=2, G=G, R=R, j=J, j_er=J_ER, j_end=0, j_eval=J_EVAL, t_min=4, t_max=N // 8,
+                gen_first=g, gen_count=1, init_error=1 if init else 0, beta=0.9, chi=0.5,
+                sigma=2.0, sigma_end=0.5, tau=0.10, tau_end=0.10 * 2.0 / 3.0, c_p=0.6, c_w=0.4)
+
+
+def algorithmic_bytes_per_px(kernel, members_sharing_m):
+    """Bytes the method must move per pixel per launch of each iteration kernel.
+
+    col_proj: read rowFFT(x) 8 + write rowFFT(P_M x) 8, plus the measured modulus
+    (4 B) read once per launch for all members.  row_update (HIO/RAAR): read
+    rowFFT(P_M x) 8 + rowFFT(x) 8 + support bits 1/8, write 8.  row_update (ER):
+    read 8 + support 1/8, write 8.
+    """
+    if kernel == 1:
+        return 16.0 + 4.0 / members_sharing_m
+    if kernel == 3:
+        return 24.125
+    if kernel == 2:
+        return 16.125
+    return 16.125
+
+
+def cpu_baseline(sh, rho0, supp0, seconds_target=15.0):
+    """FP64 oracle RAAR iterations at 512^2 on the host cores (bounded sample)."""
+    import multiprocessing as mp
+    from oracle import mpr
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    M = mpr.to_fft_order(sh["amp"])
+    known = mpr.to_fft_order(sh["mask"])
+    S = supp0.astype(bool)
+    # calibrate: one member, 2 iterations
+    t0 = time.perf_counter()
+    mpr.sequence(rho0[0].astype(np.complex128), S, M, known, 0.5, "RAAR", 0.9, 2, 0)
+    per_it = (time.perf_counter() - t0) / 2
+    iters = int(max(2, min(40, seconds_target / max(per_it, 1e-3))))
+    members = workers
+    args = [(rho0[p % P], S, M, known, iters) for p in range(members)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        pool.map(_oracle_member, args)
+    dt = time.perf_counter() - t0
+    return {"value": members * iters / dt, "unit": "member-iterations/s", "cores": workers,
+            "kind": "oracle",
+            "sample": f"{members} members x {iters} RAAR iterations (beta 0.9, chi 0.5) at 512x512, "
+                      f"FP64 NumPy oracle, one process per member over {workers} host cores"}
+
+
+def _oracle_member(a):
+    from oracle import mpr
+    x, S, M, known, iters = a
+    mpr.sequence(x.astype(np.complex128), S, M, known, 0.5, "RAAR", 0.9, iters, 0)
+    return 0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus above 1 is not "
+                                   "supported (the population loop shards by member, see the design notes)"}))
+        sys.exit(2)
+
+    sh, rho0, supp0 = make_inputs()
+    # the oracle leg runs first, in forked worker processes, before anything
+    # touches the GPU in this process
+    base = None if args.no_cpu_baseline else cpu_baseline(sh, rho0, supp0)
+
+    import torch
+    from paper_2409_07413_amd import binding as B
+
+    ctx = B.Context(0)
+    shot = ctx.shot(sh["amp"].astype(np.float32), sh["mask"].astype(np.uint8))
+    pop = shot.population(rho0, supp0, memetic=True, seed=3004)
+    total = args.warmup + args.steps
+    G = max(G_SCHEDULE, total)
+    scheds = [B.sched_mpr(ctx, **mpr_params(g, G, g == 1)) for g in range(1, total + 1)]
+    stream = torch.cuda.current_stream()
+
+    for i in range(args.warmup):
+        pop.run(scheds[i], stream)
+    pop.sync()
+    torch.cuda.synchronize()
+
+    pop.timing(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.warmup, total):
+        pop.run(scheds[i], stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pop.sync()
+    gpu_ms = ev0.elapsed_time(ev1)
+
+    member_its = 2 * P * (R * (J + J_ER) + J_EVAL) * args.steps
+    value = member_its / wall
+    # per-kernel live timing (HIP events on the launch stream)
+    kern = {}
+    for k in range(4):
+        n_l, ms = pop.timing_read(k)
+        if n_l:
+            kern[k] = (n_l, ms)
+    dom = max(kern, key=lambda k: kern[k][1])
+    n_l, ms = kern[dom]
+    bpp = algorithmic_bytes_per_px(dom, 2 * P)
+    bytes_per_launch = bpp * N * N * 2 * P
+    achieved = bytes_per_launch / (ms / n_l * 1e-3) / 1e9
+    traffic = None
+    prof_note = os.path.join(ROOT, "profiles", "traffic_512_pop64.json")
+    if os.path.exists(prof_note):
+        try:
+            t = json.load(open(prof_note))
+            traffic = t.get(B.KERNEL_NAMES[dom].split("(")[0])
+        except Exception:
+            traffic = None
+    # whole-step algorithmic bytes: iterations only (ingest/shrink-wrap/fitness/crossover excluded)
+    ia_its = er_its = 0
+    for i in range(args.warmup, total):
+        for o in scheds[i].ops():
+            if o.kind in (B.OP_HIO, B.OP_RAAR):
+                ia_its += o.count
+            elif o.kind == B.OP_ER:
+                er_its += o.count
+    step_bytes = 2 * P * N * N * (ia_its * (40.125 + 4.0 / (2 * P)) + er_its * (32.125 + 4.0 / (2 * P)))
+    pct_hbm = step_bytes / wall / (HBM_PEAK_GBS * 1e9)
+
+    out = {
+        "metric": "member-iterations/s at 512^2 pop 64 (% HBM peak)",
+        "value": value,
+        "unit": "member-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "gpu_ms_per_step": gpu_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "iteration_pixels_per_s": value * N * N,
+        "pct_hbm_peak_iterations": pct_hbm,
+        "config": {"workload": "MPR generation, 512x512 clustered spheres (1e8 photons, 24x24 beamstop, "
+                               "4-px gap), P=64 parents + 64 children, RAAR beta 0.9, "
+                               "R=3 x 20 + 40 ER = 100 iterations per member per generation",
+                   "n": N, "P": P, "members": 2 * P, "generations_timed": args.steps,
+                   "schedule_G": G},
+        "roofline": {"bound": "hbm", "kernel": B.KERNEL_NAMES[dom], "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "launches": n_l, "avg_launch_us": ms / n_l * 1e3,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "kernels": {B.KERNEL_NAMES[k]: {"launches": v[0], "avg_us": v[1] / v[0] * 1e3,
+                                        "GBps": algorithmic_bytes_per_px(k, 2 * P) * N * N * 2 * P
+                                        / (v[1] / v[0] * 1e-3) / 1e9}
+                    for k, v in kern.items()},
+    }
+    pop.close()
+    shot.close()
+    if base is not None:
+        out["cpu_baseline"] = base
+        out["gpu_over_oracle"] = value / base["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

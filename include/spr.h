@@ -1,0 +1,250 @@
+/*
+ * spr.h -- C ABI of the MI355X (gfx950) hot path of Memetic Phase Retrieval
+ * (MPR), the reconstruction method of SPRING (Colombo et al., arXiv 2409.07413).
+ *
+ * The problem (section "The phase problem and conventional approaches"): recover
+ * a complex density rho (N x N) from the measured Fourier modulus M = sqrt(I),
+ * known only where the mask Xi = 1 (beamstop and detector gaps are left free,
+ * appendix "Dealing with missing intensities", Eq. pm_full).  A population of
+ * candidate reconstructions R = (rho, S, E) -- density, boolean support and
+ * error -- is improved by iterative projection algorithms (ER, HIO, RAAR),
+ * shrink-wrap support updates, the Eq. error_calc fitness, and, for MPR, the
+ * memetic crossover and selection operators (appendix "Memetic operators").
+ *
+ * Conventions
+ * -----------
+ * - Every call returns spr_status: SPR_OK (0) or a negative error code; the
+ *   message of the last error is kept per context (spr_ctx_last_error).  No
+ *   C++ exception crosses this boundary.
+ * - Sizes: N must be 2^a 3^b with 8 <= N <= 1024 from the compiled set
+ *   (spr_supported_size); other sizes give SPR_E_UNSUPPORTED_SIZE.
+ * - Complex arrays are interleaved float32 pairs (re, im), row-major
+ *   [member][row][col].  Supports are uint8 (0/1) [member][row][col].
+ * - Amplitudes and masks are taken in the centred detector layout (zero
+ *   frequency at [N/2][N/2]) unless SPR_LAYOUT_FFT is given.  Densities and
+ *   supports are real-space arrays with natural indices.
+ * - Pointers are host memory unless SPR_DEVICE_PTRS is given, in which case they
+ *   are device pointers on the context's device (e.g. torch data_ptr()).
+ * - Inputs are copied at create/write time: the caller keeps ownership of every
+ *   buffer it passes.  The library owns all device state until the matching
+ *   destroy call.  Outputs go only into caller buffers.
+ * - Work is enqueued asynchronously on a HIP stream (NULL = the context's
+ *   stream); spr_sync and the read calls wait for it.
+ * - A handle may be used by one thread at a time; distinct handles may be used
+ *   from distinct threads.
+ */
+#ifndef SPR_H
+#define SPR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t spr_status;
+
+#define SPR_OK 0
+#define SPR_E_INVALID_ARG (-1)      /* null pointer, bad count or parameter, wrong handle state */
+#define SPR_E_UNSUPPORTED_SIZE (-2) /* N not in the compiled set */
+#define SPR_E_OOM (-3)              /* device allocation failed */
+#define SPR_E_HIP (-4)              /* a HIP runtime call or kernel launch failed */
+#define SPR_E_NOT_READY (-5)        /* serving: result not finished */
+#define SPR_E_BUSY (-6)             /* destroy of a shot that still has populations */
+#define SPR_E_NUMERIC (-7)          /* NaN/Inf in the inputs or in a fitness value */
+#define SPR_E_ADMISSION (-8)        /* serving: request can never fit the memory budget */
+
+/* flags */
+#define SPR_DEVICE_PTRS 0x1u   /* pointer arguments are device memory */
+#define SPR_LAYOUT_FFT 0x2u    /* amplitude/mask already in FFT order (DC at [0][0]) */
+#define SPR_POP_MEMETIC 0x4u   /* population also holds P children (needed by crossover/select) */
+#define SPR_READ_CHILDREN 0x8u /* spr_read/spr_pop_write act on the child population */
+
+typedef struct spr_ctx spr_ctx;
+typedef struct spr_shot spr_shot;
+typedef struct spr_pop spr_pop;
+typedef struct spr_sched spr_sched;
+
+/* ------------------------------------------------------------------------- */
+/* Context: one per device; owns a stream and the per-size twiddle tables.   */
+/* ------------------------------------------------------------------------- */
+spr_status spr_ctx_create(int32_t hip_device, spr_ctx** out);
+void spr_ctx_destroy(spr_ctx* ctx);
+/* Message of the last failed call on this context ("" if none). Owned by ctx. */
+const char* spr_ctx_last_error(const spr_ctx* ctx);
+/* 1 if N is a supported detector size, else 0. */
+int32_t spr_supported_size(int32_t n);
+
+/* ------------------------------------------------------------------------- */
+/* Shot: the measured modulus M = sqrt(I) and mask Xi (1 = measured) of one    */
+/* diffraction pattern (section "The phase problem...", Eq. pm_full).         */
+/* amp: N*N float32, finite, >= 0 where measured.  mask: N*N uint8.            */
+/* The sum of Xi M^2 must be positive (it normalises Eq. error_calc).          */
+/* Errors: SPR_E_INVALID_ARG, SPR_E_NUMERIC (non-finite or negative measured   */
+/* amplitude), SPR_E_UNSUPPORTED_SIZE, SPR_E_OOM, SPR_E_HIP.                   */
+/* ------------------------------------------------------------------------- */
+spr_status spr_shot_create(spr_ctx* ctx, int32_t n, const float* amp, const uint8_t* mask,
+                           uint32_t flags, spr_shot** out);
+/* SPR_E_BUSY while populations created on the shot are alive. */
+spr_status spr_shot_destroy(spr_shot* shot);
+
+/* ------------------------------------------------------------------------- */
+/* Population: P reconstructions (Alg. mpr / Alg. randomsearch, D1-D2 of the   */
+/* memetic-operators appendix).                                               */
+/* rho0: P*N*N complex (interleaved float32).  supp0: N*N (broadcast, when     */
+/* supp_per_member = 0) or P*N*N uint8.  seed keys the Philox4x32-10 stream of */
+/* the memetic operators; gen_offset is the number of generations already run  */
+/* (resume).  SPR_POP_MEMETIC reserves the P children of Alg. crossover.       */
+/* Crossover needs P >= 4 (three distinct other parents).                      */
+/* ------------------------------------------------------------------------- */
+spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const uint8_t* supp0,
+                          int32_t supp_per_member, uint32_t flags, uint64_t seed,
+                          int32_t gen_offset, spr_pop** out);
+spr_status spr_pop_destroy(spr_pop* pop);
+/* Overwrite the state of the parents (or children with SPR_READ_CHILDREN):    */
+/* any of rho (P*N*N complex), supp (P*N*N uint8), err (P doubles) may be NULL. */
+spr_status spr_pop_write(spr_pop* pop, const float* rho, const uint8_t* supp, const double* err,
+                         uint32_t flags);
+
+/* ------------------------------------------------------------------------- */
+/* Schedules: a flat list of operations applied in order to a population.     */
+/* ------------------------------------------------------------------------- */
+#define SPR_OP_ER 1           /* count iterations of x <- P_M P_C x (Error Reduction) */
+#define SPR_OP_HIO 2          /* count iterations of HIO, beta */
+#define SPR_OP_RAAR 3         /* count iterations of RAAR, beta */
+#define SPR_OP_SHRINKWRAP 4   /* UpdateSupport (Eq. shrinkwrap): sigma, tau */
+#define SPR_OP_SUPPORT_AREA 5 /* UpdateSupportSize: sigma, area from `which` */
+#define SPR_OP_GET_ERROR 6    /* E <- Eq. error_calc */
+#define SPR_OP_STATS 7        /* alpha_best, alpha_all, alpha_eval of Alg. improve, for gen/gens */
+#define SPR_OP_CROSSOVER 8    /* Alg. crossover into the children: c_p, c_w, t_min, t_max, gen */
+#define SPR_OP_SELECT 9       /* Alg. select, gen */
+
+#define SPR_ALG_HIO 1
+#define SPR_ALG_RAAR 2
+
+#define SPR_AREA_BEST 0 /* alpha_best of the last STATS */
+#define SPR_AREA_EVAL 1 /* alpha_eval of the last STATS */
+#define SPR_AREA_ABS 2  /* the op's alpha */
+
+#define SPR_SCOPE_ALL 0      /* every member (parents and children) */
+#define SPR_SCOPE_PARENTS 1
+#define SPR_SCOPE_CHILDREN 2
+
+typedef struct spr_op {
+  int32_t kind;   /* SPR_OP_* */
+  int32_t count;  /* ER/HIO/RAAR: iterations */
+  int32_t scope;  /* SPR_SCOPE_* (iterations, support updates, GET_ERROR) */
+  int32_t which;  /* SUPPORT_AREA: SPR_AREA_* */
+  int32_t gen;    /* STATS/CROSSOVER/SELECT: generation g (1-based, absolute) */
+  int32_t gens;   /* STATS: total generations G */
+  int32_t t_min;  /* CROSSOVER: tile side range [t_min, t_max] */
+  int32_t t_max;
+  double beta;    /* HIO/RAAR feedback parameter */
+  double chi;     /* ER/HIO/RAAR: phase range [-chi pi, chi pi]; chi <= 0 or >= 1: none */
+  double sigma;   /* SHRINKWRAP/SUPPORT_AREA: Gaussian width in pixels (0: no smoothing, <= 8) */
+  double tau;     /* SHRINKWRAP: threshold fraction of the smoothed maximum */
+  double alpha;   /* SUPPORT_AREA with SPR_AREA_ABS: target area in pixels */
+  double c_p;     /* CROSSOVER: tile election probability */
+  double c_w;     /* CROSSOVER: differential weight */
+} spr_op;
+
+/* Parameters of Table tab:params and the linear schedules ("Changing values  */
+/* over generations"): j decays linearly from j to j_end over G, the ER count  */
+/* keeps j + j_er constant, sigma and tau interpolate to their end values.     */
+typedef struct spr_plain_params {
+  int32_t alg;               /* SPR_ALG_HIO or SPR_ALG_RAAR */
+  int32_t G;                 /* blocks (Alg. randomsearch generations) */
+  int32_t j, j_er, j_end;    /* IA iterations at g = 1, ER iterations at g = 1, IA at g = G */
+  double beta, chi;
+  double sigma, sigma_end, tau, tau_end;
+} spr_plain_params;
+
+typedef struct spr_mpr_params {
+  int32_t alg;
+  int32_t G, R;              /* generations, sequences per self-improvement (R >= 2) */
+  int32_t j, j_er, j_end, j_eval;
+  int32_t t_min, t_max;      /* crossover tile sides */
+  int32_t gen_first;         /* first generation to emit (1 = start) */
+  int32_t gen_count;         /* generations to emit (0 = through G) */
+  int32_t init_error;        /* 1: evaluate the parents' errors before the first generation */
+  double beta, chi;
+  double sigma, sigma_end, tau, tau_end;
+  double c_p, c_w;
+} spr_mpr_params;
+
+/* Schedule calls run on the host only; ctx (for error messages) may be NULL. */
+spr_status spr_sched_create(spr_ctx* ctx, const spr_op* ops, int32_t nops, spr_sched** out);
+/* Alg. randomsearch with Alg. normalimprove: per block Sequence then           */
+/* UpdateSupport on every member, then GET_ERROR on every member.               */
+spr_status spr_sched_plain(spr_ctx* ctx, const spr_plain_params* prm, spr_sched** out);
+/* Alg. mpr (without the final Average): per generation CROSSOVER, STATS, the  */
+/* Alg. improve operations on every member, SELECT.                            */
+spr_status spr_sched_mpr(spr_ctx* ctx, const spr_mpr_params* prm, spr_sched** out);
+spr_status spr_sched_destroy(spr_sched* sched);
+/* Copy out the expanded op list (ops may be NULL to query the count). */
+spr_status spr_sched_ops(const spr_sched* sched, spr_op* ops, int32_t max_ops, int32_t* n_ops);
+
+/* ------------------------------------------------------------------------- */
+/* Execution.                                                                 */
+/* ------------------------------------------------------------------------- */
+/* Enqueue the schedule on `hip_stream` (a hipStream_t; NULL = context stream). */
+spr_status spr_run(spr_pop* pop, const spr_sched* sched, void* hip_stream);
+/* Wait for the population's work; SPR_E_NUMERIC if a fitness value was NaN/Inf. */
+spr_status spr_sync(spr_pop* pop);
+
+typedef struct spr_gen_stats {
+  int32_t gen;          /* generation g (0: record unused) */
+  int32_t best;         /* parent index of the lowest error before self-improvement */
+  int32_t alpha_best;   /* support area of that parent */
+  int32_t alpha_all;    /* area of the union of the parents' supports */
+  double alpha_eval;    /* (g/G) alpha_best + (1 - g/G) alpha_all */
+  double err_best;      /* after Select: lowest, mean and highest parent error */
+  double err_mean;
+  double err_worst;
+  int32_t replaced;     /* children that replaced their parent (replacement factor * P) */
+  int32_t pad;
+} spr_gen_stats;
+
+/* Read the parents (or children with SPR_READ_CHILDREN) into caller buffers:  */
+/* rho P*N*N complex, supp P*N*N uint8, err P doubles; any may be NULL.         */
+/* With SPR_DEVICE_PTRS the buffers are device memory.  Waits for the work.     */
+spr_status spr_read(spr_pop* pop, float* rho, uint8_t* supp, double* err, uint32_t flags);
+/* Generation records, oldest first; at most max_n; *n_out gets the count. */
+spr_status spr_read_stats(spr_pop* pop, spr_gen_stats* out, int32_t max_n, int32_t* n_out);
+
+typedef struct spr_xover_info {
+  int32_t a, b, c;      /* parents chosen by RandomChoice for this child */
+  int32_t tx, ty, sx, sy, rot; /* crossover-map tile sides, shift, rotation index */
+  int32_t dr[3], dc[3]; /* Reshift translation of a, b, c */
+  int32_t twin[3];      /* 1 where the twin image was taken */
+  float phase[3][2];    /* e^{i phi} applied to a, b, c */
+  float peak[3][2];     /* squared correlation maxima (direct, twin) */
+} spr_xover_info;
+
+/* Decisions of the last CROSSOVER (P records, host memory). */
+spr_status spr_read_xover(spr_pop* pop, spr_xover_info* out, int32_t max_n);
+
+/* ------------------------------------------------------------------------- */
+/* Kernel timing: when enabled, HIP events are recorded on the launch stream   */
+/* around every launch of the iteration kernels; spr_timing_read returns the   */
+/* number of launches and their summed event time since enabling (it waits    */
+/* for the population's work).  Enabling resets the totals.                    */
+/* ------------------------------------------------------------------------- */
+#define SPR_KERNEL_ROW_INGEST 0    /* real-space density -> row FFT (sequence start) */
+#define SPR_KERNEL_COL_PROJ 1      /* column FFT, masked modulus projection, column IFFT */
+#define SPR_KERNEL_ROW_UPDATE_ER 2 /* row IFFT, ER step, row FFT */
+#define SPR_KERNEL_ROW_UPDATE_IA 3 /* row IFFTs, HIO/RAAR step, row FFT */
+#define SPR_KERNEL_COUNT 4
+spr_status spr_timing_enable(spr_pop* pop, int32_t enable);
+spr_status spr_timing_read(spr_pop* pop, int32_t kernel, int64_t* launches, double* total_ms);
+
+/* Unitary 2D DFT of `batch` N x N complex images (device pointers, in != out */
+/* allowed to alias): forward exp(-2 pi i ...) / N, inverse exp(+...) / N.     */
+spr_status spr_fft2(spr_ctx* ctx, int32_t n, int32_t batch, const float* in, float* out,
+                    int32_t inverse, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPR_H */

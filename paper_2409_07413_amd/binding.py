@@ -1,0 +1,385 @@
+"""ctypes binding of libspr.so (include/spr.h): argument marshalling only.
+
+Every computation runs in the HIP library.  Host arrays are NumPy arrays; device
+arrays are torch tensors on the context's device (passed by data pointer with
+SPR_DEVICE_PTRS).  Loading fails loudly when the library has not been built.
+"""
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspr.so")
+
+SPR_OK = 0
+STATUS = {0: "SPR_OK", -1: "SPR_E_INVALID_ARG", -2: "SPR_E_UNSUPPORTED_SIZE", -3: "SPR_E_OOM",
+          -4: "SPR_E_HIP", -5: "SPR_E_NOT_READY", -6: "SPR_E_BUSY", -7: "SPR_E_NUMERIC",
+          -8: "SPR_E_ADMISSION"}
+
+DEVICE_PTRS = 0x1
+LAYOUT_FFT = 0x2
+POP_MEMETIC = 0x4
+READ_CHILDREN = 0x8
+
+OP_ER, OP_HIO, OP_RAAR, OP_SHRINKWRAP, OP_SUPPORT_AREA, OP_GET_ERROR, OP_STATS, OP_CROSSOVER, OP_SELECT = range(1, 10)
+ALG_HIO, ALG_RAAR = 1, 2
+AREA_BEST, AREA_EVAL, AREA_ABS = 0, 1, 2
+SCOPE_ALL, SCOPE_PARENTS, SCOPE_CHILDREN = 0, 1, 2
+
+
+class SprError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Op(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("count", C.c_int32), ("scope", C.c_int32), ("which", C.c_int32),
+                ("gen", C.c_int32), ("gens", C.c_int32), ("t_min", C.c_int32), ("t_max", C.c_int32),
+                ("beta", C.c_double), ("chi", C.c_double), ("sigma", C.c_double), ("tau", C.c_double),
+                ("alpha", C.c_double), ("c_p", C.c_double), ("c_w", C.c_double)]
+
+
+class PlainParams(C.Structure):
+    _fields_ = [("alg", C.c_int32), ("G", C.c_int32), ("j", C.c_int32), ("j_er", C.c_int32),
+                ("j_end", C.c_int32), ("beta", C.c_double), ("chi", C.c_double), ("sigma", C.c_double),
+                ("sigma_end", C.c_double), ("tau", C.c_double), ("tau_end", C.c_double)]
+
+
+class MprParams(C.Structure):
+    _fields_ = [("alg", C.c_int32), ("G", C.c_int32), ("R", C.c_int32), ("j", C.c_int32),
+                ("j_er", C.c_int32), ("j_end", C.c_int32), ("j_eval", C.c_int32), ("t_min", C.c_int32),
+                ("t_max", C.c_int32), ("gen_first", C.c_int32), ("gen_count", C.c_int32),
+                ("init_error", C.c_int32), ("beta", C.c_double), ("chi", C.c_double),
+                ("sigma", C.c_double), ("sigma_end", C.c_double), ("tau", C.c_double),
+                ("tau_end", C.c_double), ("c_p", C.c_double), ("c_w", C.c_double)]
+
+
+class GenStats(C.Structure):
+    _fields_ = [("gen", C.c_int32), ("best", C.c_int32), ("alpha_best", C.c_int32),
+                ("alpha_all", C.c_int32), ("alpha_eval", C.c_double), ("err_best", C.c_double),
+                ("err_mean", C.c_double), ("err_worst", C.c_double), ("replaced", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class XoverInfo(C.Structure):
+    _fields_ = [("a", C.c_int32), ("b", C.c_int32), ("c", C.c_int32), ("tx", C.c_int32),
+                ("ty", C.c_int32), ("sx", C.c_int32), ("sy", C.c_int32), ("rot", C.c_int32),
+                ("dr", C.c_int32 * 3), ("dc", C.c_int32 * 3), ("twin", C.c_int32 * 3),
+                ("phase", (C.c_float * 2) * 3), ("peak", (C.c_float * 2) * 3)]
+
+
+EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_supported_size",
+           "spr_shot_create", "spr_shot_destroy", "spr_pop_create", "spr_pop_destroy", "spr_pop_write",
+           "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
+           "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
+           "spr_timing_enable", "spr_timing_read"]
+
+KERNEL_ROW_INGEST, KERNEL_COL_PROJ, KERNEL_ROW_UPDATE_ER, KERNEL_ROW_UPDATE_IA = range(4)
+KERNEL_NAMES = {0: "k_row_ingest", 1: "k_col_proj", 2: "k_row_update(ER)", 3: "k_row_update(HIO/RAAR)"}
+
+_lib = None
+
+
+def _proto(lib):
+    vp, i32, u32, u64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64
+    pp = C.POINTER(C.c_void_p)
+    sig = {
+        "spr_ctx_create": (i32, [i32, pp]),
+        "spr_ctx_destroy": (None, [vp]),
+        "spr_ctx_last_error": (C.c_char_p, [vp]),
+        "spr_supported_size": (i32, [i32]),
+        "spr_shot_create": (i32, [vp, i32, vp, vp, u32, pp]),
+        "spr_shot_destroy": (i32, [vp]),
+        "spr_pop_create": (i32, [vp, i32, vp, vp, i32, u32, u64, i32, pp]),
+        "spr_pop_destroy": (i32, [vp]),
+        "spr_pop_write": (i32, [vp, vp, vp, vp, u32]),
+        "spr_sched_create": (i32, [vp, C.POINTER(Op), i32, pp]),
+        "spr_sched_plain": (i32, [vp, C.POINTER(PlainParams), pp]),
+        "spr_sched_mpr": (i32, [vp, C.POINTER(MprParams), pp]),
+        "spr_sched_destroy": (i32, [vp]),
+        "spr_sched_ops": (i32, [vp, C.POINTER(Op), i32, C.POINTER(i32)]),
+        "spr_run": (i32, [vp, vp, vp]),
+        "spr_sync": (i32, [vp]),
+        "spr_read": (i32, [vp, vp, vp, vp, u32]),
+        "spr_read_stats": (i32, [vp, C.POINTER(GenStats), i32, C.POINTER(i32)]),
+        "spr_read_xover": (i32, [vp, C.POINTER(XoverInfo), i32]),
+        "spr_fft2": (i32, [vp, i32, i32, vp, vp, i32, vp]),
+        "spr_timing_enable": (i32, [vp, i32]),
+        "spr_timing_read": (i32, [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def load():
+    """Load libspr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run python -m paper_2409_07413_amd.build)")
+        lib = C.CDLL(LIB_PATH)
+        _proto(lib)
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    """(pointer, is_device) for a NumPy array or torch tensor (None -> null)."""
+    if a is None:
+        return None, False
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays must be C-contiguous")
+        return a.ctypes.data, False
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return a.data_ptr(), a.is_cuda
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def check(st, ctx_handle=None):
+    """Raise SprError for a non-zero status, with the context's message."""
+    if st != SPR_OK:
+        msg = ""
+        if ctx_handle:
+            raw = load().spr_ctx_last_error(ctx_handle)
+            msg = raw.decode() if raw else ""
+        raise SprError(st, msg)
+
+
+def sched_ops(ops, ctx=None):
+    """Schedule from a list of Op (host-only call)."""
+    lib = load()
+    arr = (Op * len(ops))(*ops)
+    h = C.c_void_p()
+    check(lib.spr_sched_create(ctx.h if ctx else None, arr, len(ops), C.byref(h)), ctx.h if ctx else None)
+    return Schedule(ctx, h)
+
+
+def sched_plain(ctx=None, **kw):
+    """Alg. randomsearch/normalimprove schedule (host-only call)."""
+    lib = load()
+    prm = PlainParams(**kw)
+    h = C.c_void_p()
+    check(lib.spr_sched_plain(ctx.h if ctx else None, C.byref(prm), C.byref(h)), ctx.h if ctx else None)
+    return Schedule(ctx, h)
+
+
+def sched_mpr(ctx=None, **kw):
+    """Alg. mpr schedule (host-only call)."""
+    lib = load()
+    prm = MprParams(**kw)
+    h = C.c_void_p()
+    check(lib.spr_sched_mpr(ctx.h if ctx else None, C.byref(prm), C.byref(h)), ctx.h if ctx else None)
+    return Schedule(ctx, h)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return getattr(stream, "cuda_stream", stream)
+
+
+class Context:
+    def __init__(self, device=0):
+        self.lib = load()
+        h = C.c_void_p()
+        self._check(self.lib.spr_ctx_create(int(device), C.byref(h)), ctx=None)
+        self.h = h
+
+    def _check(self, st, ctx="self"):
+        check(st, self.h if ctx == "self" else ctx)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.spr_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def supported(self, n):
+        return bool(self.lib.spr_supported_size(int(n)))
+
+    def shot(self, amp, mask, fft_order=False):
+        """amp: N x N float32 (centred unless fft_order); mask: N x N uint8 (1 = measured)."""
+        return Shot(self, amp, mask, fft_order)
+
+    def sched_ops(self, ops):
+        return sched_ops(ops, self)
+
+    def sched_plain(self, **kw):
+        return sched_plain(self, **kw)
+
+    def sched_mpr(self, **kw):
+        return sched_mpr(self, **kw)
+
+    def fft2(self, x_in, x_out, inverse=False, stream=None):
+        """Unitary 2D DFT of a batch of N x N complex64 device tensors."""
+        n = x_in.shape[-1]
+        batch = x_in.numel() // (n * n)
+        pi, di = _ptr(x_in)
+        po, do = _ptr(x_out)
+        if not (di and do):
+            raise ValueError("fft2 takes device tensors")
+        self._check(self.lib.spr_fft2(self.h, n, batch, pi, po, 1 if inverse else 0, _stream_ptr(stream)))
+
+
+class Shot:
+    def __init__(self, ctx, amp, mask, fft_order=False):
+        self.ctx = ctx
+        self.n = int(amp.shape[-1])
+        pa, da = _ptr(amp)
+        pm, dm = _ptr(mask)
+        if da != dm:
+            raise ValueError("amp and mask must both be host or both be device arrays")
+        flags = (DEVICE_PTRS if da else 0) | (LAYOUT_FFT if fft_order else 0)
+        h = C.c_void_p()
+        ctx._check(ctx.lib.spr_shot_create(ctx.h, self.n, pa, pm, flags, C.byref(h)))
+        self.h = h
+        self._keep = (amp, mask)
+
+    def close(self):
+        if getattr(self, "h", None):
+            st = self.ctx.lib.spr_shot_destroy(self.h)
+            self.ctx._check(st)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def population(self, rho0, supp0, memetic=False, seed=0, gen_offset=0):
+        return Population(self, rho0, supp0, memetic, seed, gen_offset)
+
+
+class Schedule:
+    def __init__(self, ctx, h):
+        self.ctx = ctx
+        self.h = h
+
+    def ops(self):
+        lib = load()
+        n = C.c_int32()
+        check(lib.spr_sched_ops(self.h, None, 0, C.byref(n)))
+        arr = (Op * n.value)()
+        check(lib.spr_sched_ops(self.h, arr, n.value, C.byref(n)))
+        return list(arr)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().spr_sched_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Population:
+    def __init__(self, shot, rho0, supp0, memetic, seed, gen_offset):
+        self.shot = shot
+        self.ctx = shot.ctx
+        self.P = int(rho0.shape[0])
+        self.n = shot.n
+        pr, dr = _ptr(rho0)
+        ps, ds = _ptr(supp0)
+        if dr != ds:
+            raise ValueError("rho0 and supp0 must both be host or both be device arrays")
+        per_member = 1 if supp0.ndim == 3 else 0
+        flags = (DEVICE_PTRS if dr else 0) | (POP_MEMETIC if memetic else 0)
+        h = C.c_void_p()
+        self.ctx._check(self.ctx.lib.spr_pop_create(shot.h, self.P, pr, ps, per_member, flags,
+                                                    int(seed) & 0xFFFFFFFFFFFFFFFF, int(gen_offset),
+                                                    C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.spr_pop_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, sched, stream=None):
+        self.ctx._check(self.ctx.lib.spr_run(self.h, sched.h, _stream_ptr(stream)))
+
+    def sync(self):
+        self.ctx._check(self.ctx.lib.spr_sync(self.h))
+
+    def read(self, children=False):
+        """Host copies: rho (P,N,N) complex64, supp (P,N,N) bool, err (P,) float64."""
+        n, P = self.n, self.P
+        rho = np.empty((P, n, n), dtype=np.complex64)
+        supp = np.empty((P, n, n), dtype=np.uint8)
+        err = np.empty(P, dtype=np.float64)
+        flags = READ_CHILDREN if children else 0
+        self.ctx._check(self.ctx.lib.spr_read(self.h, rho.ctypes.data, supp.ctypes.data,
+                                              err.ctypes.data, flags))
+        return rho, supp.astype(bool), err
+
+    def read_into(self, rho=None, supp=None, err=None, children=False):
+        """Read into caller tensors/arrays (all host or all device)."""
+        ptrs = [_ptr(a) for a in (rho, supp, err)]
+        devs = {d for (p, d) in ptrs if p is not None}
+        if len(devs) > 1:
+            raise ValueError("mix of host and device outputs")
+        flags = (READ_CHILDREN if children else 0) | (DEVICE_PTRS if devs == {True} else 0)
+        self.ctx._check(self.ctx.lib.spr_read(self.h, ptrs[0][0], ptrs[1][0], ptrs[2][0], flags))
+
+    def write(self, rho=None, supp=None, err=None, children=False):
+        ptrs = [_ptr(a) for a in (rho, supp, err)]
+        devs = {d for (p, d) in ptrs if p is not None}
+        if len(devs) > 1:
+            raise ValueError("mix of host and device inputs")
+        flags = (READ_CHILDREN if children else 0) | (DEVICE_PTRS if devs == {True} else 0)
+        self.ctx._check(self.ctx.lib.spr_pop_write(self.h, ptrs[0][0], ptrs[1][0], ptrs[2][0], flags))
+
+    def stats(self, max_n=4096):
+        arr = (GenStats * max_n)()
+        n = C.c_int32()
+        self.ctx._check(self.ctx.lib.spr_read_stats(self.h, arr, max_n, C.byref(n)))
+        return [arr[i] for i in range(n.value)]
+
+    def timing(self, enable=True):
+        self.ctx._check(self.ctx.lib.spr_timing_enable(self.h, 1 if enable else 0))
+
+    def timing_read(self, kernel):
+        """(launches, total event milliseconds) of one kernel since timing was enabled."""
+        n = C.c_int64()
+        ms = C.c_double()
+        self.ctx._check(self.ctx.lib.spr_timing_read(self.h, int(kernel), C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    def xover(self):
+        arr = (XoverInfo * self.P)()
+        self.ctx._check(self.ctx.lib.spr_read_xover(self.h, arr, self.P))
+        return [arr[i] for i in range(self.P)]
+
+
+def op(kind, **kw):
+    """Build an spr_op; unspecified fields are zero (chi defaults to 0.5)."""
+    o = Op()
+    o.kind = kind
+    o.chi = 0.5
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o

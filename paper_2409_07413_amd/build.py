@@ -1,0 +1,69 @@
+"""Build libspr.so (HIP for gfx950) in-tree.
+
+Every per-size kernel object is compiled from kernels_n.hip with -DSPR_N=<n>;
+objects are compiled in parallel and linked with hipcc into
+paper_2409_07413_amd/libspr.so.  Run ``python -m paper_2409_07413_amd.build``.
+"""
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libspr.so")
+
+SIZES = (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024)
+ARCH = os.environ.get("SPR_OFFLOAD_ARCH", "gfx950")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # keep the compiler from emitting packed-FP32 instructions
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", CSRC, "-I", os.path.join(ROOT, "include"),
+    "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
+]
+
+
+def _jobs():
+    jobs = []
+    for n in SIZES:
+        jobs.append((os.path.join(CSRC, "kernels_n.hip"), os.path.join(OBJ, f"kernels_{n}.o"), [f"-DSPR_N={n}"]))
+    jobs.append((os.path.join(CSRC, "kernels_common.hip"), os.path.join(OBJ, "kernels_common.o"), []))
+    jobs.append((os.path.join(CSRC, "runtime.cpp"), os.path.join(OBJ, "runtime.o"), ["-x", "hip"]))
+    return jobs
+
+
+def _compile(job):
+    src, obj, extra = job
+    cmd = [HIPCC] + FLAGS + extra + ["-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def build(jobs_parallel=None, verbose=False):
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = _jobs()
+    workers = jobs_parallel or min(8, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(_compile, jobs))
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB}")
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,224 @@
+// Stockham radix-2/3/4/8/16 FFT engine for one transform held across T lanes.
+//
+// A length-N transform (N = 2^a 3^b) is spread over T = N/E threads; thread t
+// holds the E elements at positions t + T*m (m = 0..E-1) in registers, both
+// before and after the transform (natural order, coalesced in global memory).
+// Each Stockham pass of radix R computes butterflies j = t + k*T; the last pass
+// writes back into the registers it read, every other pass exchanges through a
+// caller-provided LDS region addressed as lds[pos * ES] (ES = element stride,
+// so several transforms can interleave in one tile).
+//
+// Transform definition: X[k] = sum_n x[n] exp(DIR * 2 pi i n k / N) with
+// DIR = -1 (forward) or +1 (inverse), unnormalised; callers apply 1/N per 2D
+// round trip where needed.  Twiddles come from a table tw[e] = exp(-2 pi i e/N)
+// computed in double on the host and rounded once to float.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace spr {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by DIR * i
+template <int DIR> __device__ __forceinline__ float2 mul_i(float2 a) {
+  return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+// ---------------------------------------------------------------------------
+// Per-size plans: radices of the passes, elements per thread E (a common
+// multiple of every radix), threads per transform T = N/E, columns per
+// column-pass tile C and rows per row-pass workgroup RW.
+// ---------------------------------------------------------------------------
+template <int N> struct Plan;
+
+#define SPR_DEFINE_PLAN(N_, E_, C_, ...)                                         \
+  template <> struct Plan<N_> {                                                  \
+    static constexpr int n = N_;                                                 \
+    static constexpr int E = E_;                                                 \
+    static constexpr int T = N_ / E_;                                            \
+    static constexpr int C = C_;                                                 \
+    static constexpr int RW = (256 / T) > 0 ? (256 / T) : 1;                     \
+    __host__ __device__ static constexpr int radix(int i) {                      \
+      constexpr int r[] = {__VA_ARGS__};                                         \
+      return r[i];                                                               \
+    }                                                                            \
+    __host__ __device__ static constexpr int passes() {                          \
+      constexpr int r[] = {__VA_ARGS__};                                         \
+      return (int)(sizeof(r) / sizeof(int));                                     \
+    }                                                                            \
+  };
+
+SPR_DEFINE_PLAN(8, 8, 8, 8)
+SPR_DEFINE_PLAN(12, 12, 4, 3, 4)
+SPR_DEFINE_PLAN(16, 4, 16, 4, 4)
+SPR_DEFINE_PLAN(24, 24, 8, 3, 8)
+SPR_DEFINE_PLAN(32, 8, 16, 4, 8)
+SPR_DEFINE_PLAN(48, 12, 16, 3, 4, 4)
+SPR_DEFINE_PLAN(64, 8, 16, 8, 8)
+SPR_DEFINE_PLAN(96, 24, 16, 3, 4, 8)
+SPR_DEFINE_PLAN(128, 8, 16, 2, 8, 8)
+SPR_DEFINE_PLAN(192, 24, 16, 3, 8, 8)
+SPR_DEFINE_PLAN(256, 8, 16, 4, 8, 8)
+SPR_DEFINE_PLAN(384, 24, 16, 3, 2, 8, 8)
+SPR_DEFINE_PLAN(512, 8, 16, 8, 8, 8)
+SPR_DEFINE_PLAN(768, 24, 8, 3, 4, 8, 8)
+SPR_DEFINE_PLAN(1024, 16, 8, 16, 8, 8)
+
+// ---------------------------------------------------------------------------
+// Small DFT butterflies, in place: a[k] <- sum_r a[r] exp(DIR 2 pi i r k / R)
+// ---------------------------------------------------------------------------
+template <int DIR> __device__ __forceinline__ void dft2(float2& a0, float2& a1) {
+  float2 t = a0;
+  a0 = cadd(t, a1);
+  a1 = csub(t, a1);
+}
+
+template <int DIR> __device__ __forceinline__ void dft3(float2& a0, float2& a1, float2& a2) {
+  const float h = 0.86602540378443864676f;  // sin(2 pi / 3)
+  float2 s = cadd(a1, a2), d = csub(a1, a2);
+  float2 m = make_float2(a0.x - 0.5f * s.x, a0.y - 0.5f * s.y);
+  float2 r = mul_i<DIR>(cscale(d, h));
+  a0 = cadd(a0, s);
+  a1 = cadd(m, r);
+  a2 = csub(m, r);
+}
+
+template <int DIR> __device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  float2 t2 = cadd(a1, a3), t3 = mul_i<DIR>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <int DIR> __device__ __forceinline__ void dft8(float2* a) {
+  // even/odd split: X[k] = E[k] + w^k O[k], X[k+4] = E[k] - w^k O[k]
+  const float c = 0.70710678118654752440f;
+  float2 e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  float2 o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+  dft4<DIR>(e0, e1, e2, e3);
+  dft4<DIR>(o0, o1, o2, o3);
+  // w = exp(DIR i pi/4)
+  float2 w1o1 = make_float2(c * (o1.x - DIR * o1.y), c * (o1.y + DIR * o1.x));
+  float2 w2o2 = mul_i<DIR>(o2);
+  float2 w3o3 = make_float2(c * (-o3.x - DIR * o3.y), c * (-o3.y + DIR * o3.x));
+  a[0] = cadd(e0, o0);
+  a[4] = csub(e0, o0);
+  a[1] = cadd(e1, w1o1);
+  a[5] = csub(e1, w1o1);
+  a[2] = cadd(e2, w2o2);
+  a[6] = csub(e2, w2o2);
+  a[3] = cadd(e3, w3o3);
+  a[7] = csub(e3, w3o3);
+}
+
+template <int DIR> __device__ __forceinline__ void dft16(float2* a) {
+  // n = 4 n1 + n2, k = k1 + 4 k2
+  float2 b[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    float2 x0 = a[n2], x1 = a[4 + n2], x2 = a[8 + n2], x3 = a[12 + n2];
+    dft4<DIR>(x0, x1, x2, x3);
+    b[n2][0] = x0;
+    b[n2][1] = x1;
+    b[n2][2] = x2;
+    b[n2][3] = x3;
+  }
+  // twiddles exp(DIR 2 pi i m / 16), m = n2 * k1
+  const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
+  const float c2 = 0.70710678118654752440f;
+  const float2 w[10] = {
+      make_float2(1.f, 0.f),        make_float2(c1, DIR * s1),    make_float2(c2, DIR * c2),
+      make_float2(s1, DIR * c1),    make_float2(0.f, (float)DIR), make_float2(-s1, DIR * c1),
+      make_float2(-c2, DIR * c2),   make_float2(-c1, DIR * s1),   make_float2(-1.f, 0.f),
+      make_float2(-c1, -DIR * s1)};
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) b[n2][k1] = cmul(b[n2][k1], w[n2 * k1]);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 x0 = b[0][k1], x1 = b[1][k1], x2 = b[2][k1], x3 = b[3][k1];
+    dft4<DIR>(x0, x1, x2, x3);
+    a[k1] = x0;
+    a[k1 + 4] = x1;
+    a[k1 + 8] = x2;
+    a[k1 + 12] = x3;
+  }
+}
+
+template <int R, int DIR> __device__ __forceinline__ void butterfly(float2* a) {
+  if constexpr (R == 2) dft2<DIR>(a[0], a[1]);
+  else if constexpr (R == 3) dft3<DIR>(a[0], a[1], a[2]);
+  else if constexpr (R == 4) dft4<DIR>(a[0], a[1], a[2], a[3]);
+  else if constexpr (R == 8) dft8<DIR>(a);
+  else if constexpr (R == 16) dft16<DIR>(a);
+}
+
+// Twiddle exp(DIR 2 pi i e / N) from the forward table.
+template <int DIR> __device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int e) {
+  float2 w = tw[e];
+  return DIR < 0 ? w : cconj(w);
+}
+
+// Barrier among the threads that share the exchange buffer.
+__device__ __forceinline__ void lds_sync() { __syncthreads(); }
+
+// One Stockham pass (and, recursively, the following ones).
+template <int N, int DIR, int PASS, int NS, int ES>
+__device__ __forceinline__ void fft_passes(float2 (&v)[Plan<N>::E], float2* lds, int t,
+                                           const float2* __restrict__ tw) {
+  using P = Plan<N>;
+  if constexpr (PASS < P::passes()) {
+    constexpr int R = P::radix(PASS);
+    constexpr int E = P::E, T = P::T;
+    constexpr int NB = E / R;
+    constexpr bool LAST = (PASS == P::passes() - 1);
+    static_assert(E % R == 0, "plan: E must be a multiple of every radix");
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int j = t + k * T;
+      float2 a[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r] = v[k + r * NB];
+      if constexpr (NS > 1) {
+        const int jm = j % NS;
+        constexpr int step = N / (NS * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) a[r] = cmul(a[r], twiddle<DIR>(tw, jm * r * step));
+      }
+      butterfly<R, DIR>(a);
+      if constexpr (LAST) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[k + r * NB] = a[r];
+      } else {
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[(base + r * NS) * ES] = a[r];
+      }
+    }
+    if constexpr (!LAST) {
+      lds_sync();
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = lds[(t + T * m) * ES];
+      lds_sync();
+      fft_passes<N, DIR, PASS + 1, NS * R, ES>(v, lds, t, tw);
+    }
+  }
+}
+
+// Transform the E register elements of thread t (positions t + T*m).
+// Every thread of the workgroup must call this (it contains barriers).
+template <int N, int DIR, int ES>
+__device__ __forceinline__ void fft(float2 (&v)[Plan<N>::E], float2* lds, int t,
+                                    const float2* __restrict__ tw) {
+  fft_passes<N, DIR, 0, 1, ES>(v, lds, t, tw);
+}
+
+}  // namespace spr

@@ -1,0 +1,501 @@
+// Size-independent kernels: fitness finalisation, shrink-wrap smoothing and
+// thresholds, the exact top-k support (UpdateSupportSize), population
+// statistics, RandomChoice / crossover-map parameters, Reshift decisions,
+// support mixing, Select, and support packing.
+#include "common.hpp"
+#include "kernels_common.hpp"
+
+namespace spr {
+namespace {
+
+__device__ __forceinline__ bool bit_at(const uint32_t* __restrict__ S, long idx) {
+  return (S[idx >> 5] >> (idx & 31)) & 1u;
+}
+
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum of ints (fixed order).  All threads must call it.
+__device__ int block_sum_int(int v, int* sh) {
+  v = wave_sum_int(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  int s = 0;
+  for (int i = 0; i < nw; ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+// Block-wide exclusive scan of ints in thread order; returns the prefix and
+// writes the block total to *total.  All threads must call it.
+__device__ int block_exclusive_scan(int v, int* sh, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int u = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += u;
+  }
+  __syncthreads();
+  if (lane == 63 || threadIdx.x == blockDim.x - 1) sh[w] = incl;
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int i = 0; i < nw; ++i) {
+    if (i < w) before += sh[i];
+    all += sh[i];
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
+}
+
+// ---------------------------------------------------------------------------
+// Fitness: E = sqrt(sum partials / sum Xi M^2) per member (Eq. error_calc).
+// ---------------------------------------------------------------------------
+__global__ void k_err_final(ErrFinalArgs a) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= a.nm) return;
+  double s = 0.0;
+  for (int i = 0; i < a.ntiles; ++i) s += a.partial[(size_t)m * a.ntiles + i];
+  const double e = sqrt(s / a.den);
+  a.E[a.slots[m]] = e;
+  if (!isfinite(e)) atomicOr(a.flags, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Shrink-wrap: |x| smoothed by a circular separable Gaussian (rows, columns).
+// ---------------------------------------------------------------------------
+__global__ void k_smooth_rows(SmoothArgs a) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nn = (long)a.n * a.n;
+  if (gid >= (long)a.nm * nn) return;
+  const int m = (int)(gid / nn);
+  const long p = gid % nn;
+  const int i = (int)(p / a.n), j = (int)(p % a.n);
+  const float2* xr = a.X + (size_t)a.slots[m] * nn + (size_t)i * a.n;
+  float acc = 0.f;
+  for (int k = -a.r; k <= a.r; ++k) {
+    int jj = j + k;
+    jj = jj < 0 ? jj + a.n : (jj >= a.n ? jj - a.n : jj);
+    const float2 z = xr[jj];
+    acc += a.w[k + a.r] * sqrtf(z.x * z.x + z.y * z.y);
+  }
+  a.out[gid] = acc;
+}
+
+__global__ void k_smooth_cols(SmoothColArgs a) {
+  __shared__ float sh[16];
+  const long nn = (long)a.n * a.n;
+  const int m = blockIdx.y;
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  float v = 0.f;
+  if (p < nn) {
+    const int i = (int)(p / a.n), j = (int)(p % a.n);
+    const float* src = a.in + (size_t)m * nn;
+    float acc = 0.f;
+    for (int k = -a.r; k <= a.r; ++k) {
+      int ii = i + k;
+      ii = ii < 0 ? ii + a.n : (ii >= a.n ? ii - a.n : ii);
+      acc += a.w[k + a.r] * src[(size_t)ii * a.n + j];
+    }
+    a.out[(size_t)m * nn + p] = acc;
+    v = acc;
+  }
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float mx = sh[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mx = fmaxf(mx, sh[w]);
+    a.block_max[(size_t)m * gridDim.x + blockIdx.x] = mx;
+  }
+}
+
+__global__ void k_member_max(MemberMaxArgs a) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= a.nm) return;
+  float mx = 0.f;
+  for (int i = 0; i < a.blocks_per_member; ++i) mx = fmaxf(mx, a.block_max[(size_t)m * a.blocks_per_member + i]);
+  a.maxv[m] = mx;
+}
+
+// S' = {a_sigma > tau * max a_sigma}, compared in double; unchanged if max = 0.
+__global__ void k_threshold(ThresholdArgs a) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)a.nm * a.W) return;
+  const int m = (int)(gid / a.W);
+  const int w = (int)(gid % a.W);
+  const float mx = a.maxv[m];
+  if (!(mx > 0.f)) return;
+  const double thr = a.tau * (double)mx;
+  const long nn = (long)a.n * a.n;
+  const float* src = a.in + (size_t)m * nn;
+  uint32_t bits = 0;
+  for (int b = 0; b < 32; ++b) {
+    const long idx = (long)w * 32 + b;
+    if (idx < nn && (double)src[idx] > thr) bits |= 1u << b;
+  }
+  a.S[(size_t)a.slots[m] * a.W + w] = bits;
+}
+
+// ---------------------------------------------------------------------------
+// UpdateSupportSize: exact top-k of the smoothed modulus, ties to the lower
+// linear index.  One workgroup per member: MSB-first radix select on the
+// float bit patterns (order-preserving for values >= 0), then an index-ordered
+// pass that takes the remaining ties first-come.
+// ---------------------------------------------------------------------------
+constexpr int TOPK_THREADS = 1024;
+
+__global__ __launch_bounds__(TOPK_THREADS) void k_topk(TopkArgs a) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t sh_prefix, sh_rem;
+  __shared__ int scan_sh[TOPK_THREADS / 64];
+  const int m = blockIdx.x;
+  const long nn = (long)a.n * a.n;
+  const uint32_t* keys = reinterpret_cast<const uint32_t*>(a.in + (size_t)m * nn);
+  uint32_t* Sm = a.S + (size_t)a.slots[m] * a.W;
+  const double alpha = a.alpha_src ? a.alpha_src[a.alpha_index] : a.alpha_abs;
+  double kd = floor(alpha + 0.5);
+  if (!(kd >= 1.0)) kd = 1.0;
+  if (kd > (double)nn) kd = (double)nn;
+  const uint32_t k = (uint32_t)kd;
+
+  uint32_t prefix = 0, pmask = 0, rem = k;
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 24 - 8 * pass;
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    for (long i = threadIdx.x; i < nn; i += blockDim.x) {
+      const uint32_t key = keys[i];
+      if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t cum = 0;
+      int digit = 0;
+      for (int b = 255; b >= 0; --b) {
+        if (cum + hist[b] >= rem) {
+          digit = b;
+          break;
+        }
+        cum += hist[b];
+      }
+      sh_prefix = prefix | ((uint32_t)digit << shift);
+      sh_rem = rem - cum;
+    }
+    __syncthreads();
+    prefix = sh_prefix;
+    rem = sh_rem;
+    pmask |= 255u << shift;
+    __syncthreads();
+  }
+  // prefix = k-th largest key; rem = how many keys equal to it are taken
+  int taken_before = 0;
+  for (int wb = 0; wb < a.W; wb += blockDim.x) {
+    const int w = wb + threadIdx.x;
+    int ties = 0;
+    if (w < a.W) {
+      for (int b = 0; b < 32; ++b) {
+        const long idx = (long)w * 32 + b;
+        if (idx < nn && keys[idx] == prefix) ++ties;
+      }
+    }
+    int total;
+    const int before = block_exclusive_scan(ties, scan_sh, &total);
+    if (w < a.W) {
+      uint32_t bits = 0;
+      int rank = taken_before + before;
+      for (int b = 0; b < 32; ++b) {
+        const long idx = (long)w * 32 + b;
+        if (idx >= nn) break;
+        const uint32_t key = keys[idx];
+        if (key > prefix) bits |= 1u << b;
+        else if (key == prefix) {
+          if ((uint32_t)rank < rem) bits |= 1u << b;
+          ++rank;
+        }
+      }
+      Sm[w] = bits;
+    }
+    taken_before += total;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Generation statistics of Alg. improve (parents only): best = lowest error
+// (ties to the lowest index), alpha_best, alpha_all (union), alpha_eval.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_stats(StatsArgs a) {
+  __shared__ int sh[16];
+  __shared__ int sh_best;
+  if (threadIdx.x == 0) {
+    int best = 0;
+    double be = a.E[a.table[0]];
+    for (int p = 1; p < a.P; ++p) {
+      const double e = a.E[a.table[p]];
+      if (e < be) {
+        be = e;
+        best = p;
+      }
+    }
+    sh_best = best;
+  }
+  __syncthreads();
+  const int best = sh_best;
+  const uint32_t* Sb = a.S + (size_t)a.table[best] * a.W;
+  int cb = 0, ca = 0;
+  for (int w = threadIdx.x; w < a.W; w += blockDim.x) {
+    cb += __popc(Sb[w]);
+    uint32_t u = 0;
+    for (int p = 0; p < a.P; ++p) u |= a.S[(size_t)a.table[p] * a.W + w];
+    ca += __popc(u);
+  }
+  cb = block_sum_int(cb, sh);
+  ca = block_sum_int(ca, sh);
+  if (threadIdx.x == 0) {
+    const double fr = (double)a.gen / (double)a.gens;
+    const double ev = fr * (double)cb + (1.0 - fr) * (double)ca;
+    a.scal->alpha[0] = (double)cb;
+    a.scal->alpha[1] = ev;
+    a.scal->alpha_all = (double)ca;
+    a.scal->best = best;
+    GenStatsDev* rec = a.rec;
+    rec->gen = a.gen;
+    rec->best = best;
+    rec->alpha_best = cb;
+    rec->alpha_all = ca;
+    rec->alpha_eval = ev;
+  }
+}
+
+// Alg. select: child p replaces parent p iff E_child < E_parent (strict); the
+// slot table entries are swapped instead of copying the reconstructions.
+__global__ void k_select(SelectArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int repl = 0;
+  for (int p = 0; p < a.P; ++p) {
+    const int sp = a.table[p], sc = a.table[a.P + p];
+    if (a.E[sc] < a.E[sp]) {
+      a.table[p] = sc;
+      a.table[a.P + p] = sp;
+      ++repl;
+    }
+  }
+  double lo = a.E[a.table[0]], hi = lo, sum = 0.0;
+  for (int p = 0; p < a.P; ++p) {
+    const double e = a.E[a.table[p]];
+    lo = e < lo ? e : lo;
+    hi = e > hi ? e : hi;
+    sum += e;
+  }
+  GenStatsDev* rec = a.rec;
+  rec->gen = a.gen;
+  rec->replaced = repl;
+  rec->err_best = lo;
+  rec->err_mean = sum / a.P;
+  rec->err_worst = hi;
+}
+
+// RandomChoice (three distinct parents other than p, by skip-mapping uniform
+// draws past the excluded indices) and the crossover-map parameters.
+__global__ void k_choice(ChoiceArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.P) return;
+  int ex[4] = {p, 0, 0, 0};
+  int nex = 1;
+  for (int i = 0; i < 3; ++i) {
+    uint32_t r = uniform_int(philox_draw(a.seed, PURPOSE_CHOICE, (uint32_t)a.gen, (uint32_t)p, (uint32_t)i),
+                             (uint32_t)(a.P - 1 - i));
+    // ascending order of the excluded set
+    int srt[4];
+    for (int q = 0; q < nex; ++q) srt[q] = ex[q];
+    for (int q = 1; q < nex; ++q)
+      for (int z = q; z > 0 && srt[z - 1] > srt[z]; --z) {
+        int tmp = srt[z];
+        srt[z] = srt[z - 1];
+        srt[z - 1] = tmp;
+      }
+    for (int q = 0; q < nex; ++q)
+      if ((int)r >= srt[q]) ++r;
+    a.abc[3 * p + i] = (int)r;
+    ex[nex++] = (int)r;
+  }
+  uint32_t d[5];
+  for (int i = 0; i < 5; ++i) d[i] = philox_draw(a.seed, PURPOSE_MAPPARAM, (uint32_t)a.gen, (uint32_t)p, (uint32_t)i);
+  const int span = a.t_max - a.t_min + 1;
+  const int tx = a.t_min + (int)uniform_int(d[0], (uint32_t)span);
+  const int ty = a.t_min + (int)uniform_int(d[1], (uint32_t)span);
+  a.mapprm[5 * p + 0] = tx;
+  a.mapprm[5 * p + 1] = ty;
+  a.mapprm[5 * p + 2] = (int)uniform_int(d[2], (uint32_t)tx);
+  a.mapprm[5 * p + 3] = (int)uniform_int(d[3], (uint32_t)ty);
+  a.mapprm[5 * p + 4] = (int)uniform_int(d[4], (uint32_t)N_ROTATIONS);
+}
+
+// Reshift decision per (child, parent) pair from the per-block argmax records:
+// shift = argmax index, twin iff its peak is strictly higher, phase of C(d).
+__device__ __forceinline__ bool better_rec(const ArgmaxRec& x, const ArgmaxRec& y) {
+  return x.val > y.val || (x.val == y.val && x.idx < y.idx);
+}
+
+__global__ void k_align(AlignArgs a) {
+  const int pair = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pair >= a.npairs) return;
+  ArgmaxRec b[2];
+  for (int tw = 0; tw < 2; ++tw) {
+    const ArgmaxRec* src = a.partial + (size_t)(2 * pair + tw) * a.blocks;
+    ArgmaxRec best = src[0];
+    for (int i = 1; i < a.blocks; ++i)
+      if (better_rec(src[i], best)) best = src[i];
+    b[tw] = best;
+  }
+  const int twin = b[1].val > b[0].val ? 1 : 0;
+  const ArgmaxRec& c = b[twin];
+  AlignRec r;
+  r.dr = c.idx / a.n;
+  r.dc = c.idx % a.n;
+  r.twin = twin;
+  r.pad = 0;
+  const float mag = sqrtf(c.re * c.re + c.im * c.im);
+  if (mag > 0.f) {
+    r.pr = c.re / mag;
+    r.pi = c.im / mag;
+  } else {
+    r.pr = 1.f;
+    r.pi = 0.f;
+  }
+  r.peak1 = b[0].val;
+  r.peak2 = b[1].val;
+  r.second = 0.f;
+  r.pad2 = 0.f;
+  a.align[pair] = r;
+}
+
+// Crossover support logic: S_new = S_a' OR (S_b' AND S_c' AND S_p), where the
+// aligned supports are S(y - d) (or S(d - y) for the twin).
+__global__ void k_support_mix(SupportMixArgs a) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)a.P * a.W) return;
+  const int p = (int)(gid / a.W);
+  const int w = (int)(gid % a.W);
+  const long nn = (long)a.n * a.n;
+  const uint32_t* Sq[3];
+  AlignRec al[3];
+  for (int k = 0; k < 3; ++k) {
+    Sq[k] = a.S + (size_t)a.table[a.abc[3 * p + k]] * a.W;
+    al[k] = a.align[3 * p + k];
+  }
+  const uint32_t* Sp = a.S + (size_t)a.table[p] * a.W;
+  uint32_t bits = 0;
+  for (int b = 0; b < 32; ++b) {
+    const long idx = (long)w * 32 + b;
+    if (idx >= nn) break;
+    const int yr = (int)(idx / a.n), yc = (int)(idx % a.n);
+    bool s[3];
+    for (int k = 0; k < 3; ++k) {
+      int sr, sc;
+      if (al[k].twin) {
+        sr = al[k].dr - yr;
+        sc = al[k].dc - yc;
+      } else {
+        sr = yr - al[k].dr;
+        sc = yc - al[k].dc;
+      }
+      sr = ((sr % a.n) + a.n) % a.n;
+      sc = ((sc % a.n) + a.n) % a.n;
+      s[k] = bit_at(Sq[k], (long)sr * a.n + sc);
+    }
+    const bool sp = bit_at(Sp, idx);
+    if (s[0] || (s[1] && s[2] && sp)) bits |= 1u << b;
+  }
+  a.S[(size_t)a.table[a.P + p] * a.W + w] = bits;
+}
+
+// uint8 supports [member][n*n] <-> bit words [slot][W]
+__global__ void k_pack(PackArgs a) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)a.nm * a.W) return;
+  const int m = (int)(gid / a.W);
+  const int w = (int)(gid % a.W);
+  const long nn = (long)a.n * a.n;
+  const uint8_t* src = a.bytes + (a.broadcast ? 0 : (size_t)m * nn);
+  uint32_t bits = 0;
+  for (int b = 0; b < 32; ++b) {
+    const long idx = (long)w * 32 + b;
+    if (idx < nn && src[idx]) bits |= 1u << b;
+  }
+  a.S[(size_t)a.slots[m] * a.W + w] = bits;
+}
+
+__global__ void k_unpack(PackArgs a) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nn = (long)a.n * a.n;
+  if (gid >= (long)a.nm * nn) return;
+  const int m = (int)(gid / nn);
+  const long idx = gid % nn;
+  const uint32_t* Sm = a.S + (size_t)a.slots[m] * a.W;
+  a.bytes[gid] = bit_at(Sm, idx) ? 1 : 0;
+}
+
+inline unsigned blocks_for(long n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
+
+}  // namespace
+
+hipError_t launch_err_final(const ErrFinalArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_err_final, dim3(blocks_for(a.nm, 64)), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_smooth(const SmoothArgs& rows, const SmoothColArgs& cols, const MemberMaxArgs& mx,
+                         hipStream_t s) {
+  const long total = (long)rows.nm * rows.n * rows.n;
+  hipLaunchKernelGGL(k_smooth_rows, dim3(blocks_for(total, 256)), dim3(256), 0, s, rows);
+  const unsigned bpm = blocks_for((long)rows.n * rows.n, 256);
+  hipLaunchKernelGGL(k_smooth_cols, dim3(bpm, cols.nm), dim3(256), 0, s, cols);
+  hipLaunchKernelGGL(k_member_max, dim3(blocks_for(mx.nm, 64)), dim3(64), 0, s, mx);
+  return hipGetLastError();
+}
+hipError_t launch_threshold(const ThresholdArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_threshold, dim3(blocks_for((long)a.nm * a.W, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_topk(const TopkArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_topk, dim3(a.nm), dim3(TOPK_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_stats(const StatsArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_select(const SelectArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_choice(const ChoiceArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_choice, dim3(blocks_for(a.P, 64)), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_align(const AlignArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_align, dim3(blocks_for(a.npairs, 64)), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_support_mix(const SupportMixArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_support_mix, dim3(blocks_for((long)a.P * a.W, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(blocks_for((long)a.nm * a.W, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_unpack(const PackArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack, dim3(blocks_for((long)a.nm * a.n * a.n, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace spr

@@ -1,0 +1,135 @@
+// Argument blocks and launchers of the size-independent kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace spr {
+
+constexpr int MAX_TAPS = 65;  // Gaussian radius ceil(4 sigma) <= 32
+
+// Device-side scalars of a population: areas from the last STATS.
+struct PopScalars {
+  double alpha[2];   // [0] alpha_best, [1] alpha_eval
+  double alpha_all;
+  int best;
+  int pad;
+};
+
+// Device record of one generation (mirrors spr_gen_stats).
+struct GenStatsDev {
+  int gen, best, alpha_best, alpha_all;
+  double alpha_eval, err_best, err_mean, err_worst;
+  int replaced, pad;
+};
+
+struct ErrFinalArgs {
+  const double* partial;
+  int ntiles;
+  int nm;
+  const int* slots;
+  double den;     // sum of Xi M^2
+  double* E;      // [slot]
+  int* flags;     // bit 0: non-finite fitness
+};
+
+struct SmoothArgs {
+  const int* slots;
+  int nm, n, r;
+  const float2* X;
+  float* out;     // [member][n*n]
+  float w[MAX_TAPS];
+};
+
+struct SmoothColArgs {
+  int nm, n, r;
+  const float* in;
+  float* out;
+  float* block_max;  // [member][blocks per member]
+  float w[MAX_TAPS];
+};
+
+struct MemberMaxArgs {
+  int nm, blocks_per_member;
+  const float* block_max;
+  float* maxv;
+};
+
+struct ThresholdArgs {
+  const int* slots;
+  int nm, n, W;
+  const float* in;
+  const float* maxv;
+  double tau;
+  uint32_t* S;
+};
+
+struct TopkArgs {
+  const int* slots;
+  int nm, n, W;
+  const float* in;
+  const double* alpha_src;  // device scalars or null
+  int alpha_index;
+  double alpha_abs;
+  uint32_t* S;
+};
+
+struct StatsArgs {
+  int P, W, gen, gens;
+  const int* table;
+  const double* E;
+  const uint32_t* S;
+  PopScalars* scal;
+  GenStatsDev* rec;
+};
+
+struct SelectArgs {
+  int P, gen;
+  int* table;
+  const double* E;
+  GenStatsDev* rec;
+};
+
+struct ChoiceArgs {
+  int P, gen, t_min, t_max;
+  uint64_t seed;
+  int* abc;
+  int* mapprm;
+};
+
+struct AlignArgs {
+  int npairs, blocks, n;
+  const ArgmaxRec* partial;
+  AlignRec* align;
+};
+
+struct SupportMixArgs {
+  int P, n, W;
+  const int* table;
+  const int* abc;
+  const AlignRec* align;
+  uint32_t* S;
+};
+
+struct PackArgs {
+  const int* slots;
+  int nm, n, W, broadcast;
+  uint8_t* bytes;
+  uint32_t* S;
+};
+
+hipError_t launch_err_final(const ErrFinalArgs& a, hipStream_t s);
+hipError_t launch_smooth(const SmoothArgs& rows, const SmoothColArgs& cols, const MemberMaxArgs& mx,
+                         hipStream_t s);
+hipError_t launch_threshold(const ThresholdArgs& a, hipStream_t s);
+hipError_t launch_topk(const TopkArgs& a, hipStream_t s);
+hipError_t launch_stats(const StatsArgs& a, hipStream_t s);
+hipError_t launch_select(const SelectArgs& a, hipStream_t s);
+hipError_t launch_choice(const ChoiceArgs& a, hipStream_t s);
+hipError_t launch_align(const AlignArgs& a, hipStream_t s);
+hipError_t launch_support_mix(const SupportMixArgs& a, hipStream_t s);
+hipError_t launch_pack(const PackArgs& a, hipStream_t s);
+hipError_t launch_unpack(const PackArgs& a, hipStream_t s);
+
+}  // namespace spr

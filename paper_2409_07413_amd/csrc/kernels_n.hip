@@ -1,0 +1,503 @@
+// Size-specialised kernels of the projection loop, compiled once per detector
+// size N (macro SPR_N).  Every 2D transform is two passes through HBM:
+//
+//   row pass     one workgroup owns RW whole rows; each row is one Stockham
+//                transform in LDS; the real-space work (support/phase
+//                projection, ER/HIO/RAAR update, shrink-wrap masking) is fused
+//                around the row transforms;
+//   column pass  one workgroup owns a tile of C adjacent columns; the masked
+//                modulus projection (Eq. pm_full) or the fitness residual
+//                (Eq. error_calc) is fused between the forward and inverse
+//                column transforms.
+//
+// The iterate is kept as its row transform T = rowFFT(x): a column pass turns
+// T into rowFFT(P_M x) and the next row pass turns that back into the next
+// iterate's row transform, so each iteration is one read-write sweep per pass.
+#include "common.hpp"
+#include "fft.hpp"
+
+#ifndef SPR_N
+#error "SPR_N must be defined"
+#endif
+
+namespace spr {
+namespace {
+
+constexpr int N = SPR_N;
+using PL = Plan<N>;
+constexpr int E = PL::E;
+constexpr int T = PL::T;
+constexpr int C = PL::C;
+constexpr int RW = PL::RW;
+constexpr size_t NN = (size_t)N * N;
+static_assert(N % C == 0, "column tile must divide N");
+
+// rows per workgroup for kernels whose workgroups must not straddle images
+constexpr int rows_within_image() {
+  int r = RW < N ? RW : N;
+  while (N % r != 0) --r;
+  return r;
+}
+constexpr int RWI = rows_within_image();
+
+__device__ __forceinline__ bool bit_at(const uint32_t* __restrict__ S, int idx) {
+  return (S[idx >> 5] >> (idx & 31)) & 1u;
+}
+
+// Nearest point of {|arg z| <= chi pi} (positivity: Re z >= 0 exactly).
+__device__ __forceinline__ float2 proj_phase(float2 z, const Phase& ph) {
+  if (ph.mode == PHASE_OFF) return z;
+  if (ph.mode == PHASE_POS) return make_float2(fmaxf(z.x, 0.f), z.y);
+  const float aim = fabsf(z.y);
+  if (aim * ph.c <= z.x * ph.s) return z;
+  const float p = fmaxf(z.x * ph.c + aim * ph.s, 0.f);
+  const float sg = z.y < 0.f ? -1.f : 1.f;
+  return make_float2(p * ph.c, sg * p * ph.s);
+}
+
+__device__ __forceinline__ bool inside_phase(float2 z, const Phase& ph) {
+  if (ph.mode == PHASE_OFF) return true;
+  if (ph.mode == PHASE_POS) return z.x >= 0.f;
+  return fabsf(z.y) * ph.c <= z.x * ph.s;
+}
+
+// Masked modulus replacement on one unitary Fourier value (Eq. pm_full):
+// measured pixels get modulus M with the current phase (phase 0 if X = 0).
+__device__ __forceinline__ float2 modulus_replace(float2 X, float stored, float scale) {
+  if (signbit(stored)) return X;
+  const float Mv = stored * scale;
+  const float m2 = X.x * X.x + X.y * X.y;
+  if (m2 > 0.f) return cscale(X, Mv * rsqrtf(m2));
+  return make_float2(Mv, 0.f);
+}
+
+// ---------------------------------------------------------------------------
+// Row ingest: real-space density -> (optional constraint) -> row FFT.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int r = tid / T, t = tid % T;
+  const int grow = blockIdx.x * RW + r;
+  const bool valid = grow < a.nm * N;
+  const int member = valid ? grow / N : 0;
+  const int row = valid ? grow % N : 0;
+  const int slot = a.slots[member];
+  const size_t off = (size_t)slot * NN + (size_t)row * N;
+  const uint32_t* Sm = a.S + (size_t)slot * a.W;
+  float2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int e = t + T * m;
+    float2 z = valid ? a.X[off + e] : make_float2(0.f, 0.f);
+    if (a.mode != INGEST_PLAIN) {
+      const bool s = bit_at(Sm, row * N + e);
+      if (a.mode == INGEST_PC) z = s ? proj_phase(z, a.ph) : make_float2(0.f, 0.f);
+      else z = s ? z : make_float2(0.f, 0.f);
+    }
+    v[m] = z;
+  }
+  fft<N, -1, 1>(v, lds + r * N, t, a.tw);
+  if (valid) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) a.T[off + t + T * m] = v[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column projection: column FFT -> masked P_M -> column IFFT.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int c = tid % C, t = tid / C;
+  const int col = blockIdx.x * C + c;
+  const int slot = a.slots[blockIdx.y];
+  const float2* src = a.T + (size_t)slot * NN;
+  float2* dst = a.Y + (size_t)slot * NN;
+  float2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = src[(size_t)(t + T * m) * N + col];
+  fft<N, -1, C>(v, lds + c, t, a.tw);
+  const float inv = 1.0f / (float)N;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int e = t + T * m;
+    const float2 X = cscale(v[m], inv);  // unitary spectrum
+    v[m] = cscale(modulus_replace(X, a.amp[(size_t)e * N + col], a.amp_scale), inv);
+  }
+  fft<N, +1, C>(v, lds + c, t, a.tw);
+#pragma unroll
+  for (int m = 0; m < E; ++m) dst[(size_t)(t + T * m) * N + col] = v[m];
+}
+
+// ---------------------------------------------------------------------------
+// Row update: row IFFTs -> ER/HIO/RAAR real-space step -> next row FFT (or the
+// final real-space density).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int r = tid / T, t = tid % T;
+  const int grow = blockIdx.x * RW + r;
+  const bool valid = grow < a.nm * N;
+  const int member = valid ? grow / N : 0;
+  const int row = valid ? grow % N : 0;
+  const int slot = a.slots[member];
+  const size_t off = (size_t)slot * NN + (size_t)row * N;
+  const uint32_t* Sm = a.S + (size_t)slot * a.W;
+  float2* l = lds + r * N;
+
+  float2 y[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) y[m] = valid ? a.Y[off + t + T * m] : make_float2(0.f, 0.f);
+  fft<N, +1, 1>(y, l, t, a.tw);  // y = P_M x (real space)
+
+  float2 xn[E];
+  if (a.alg == ALG_ER) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) xn[m] = y[m];
+  } else {
+    float2 x[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) x[m] = valid ? a.T[off + t + T * m] : make_float2(0.f, 0.f);
+    fft<N, +1, 1>(x, l, t, a.tw);
+    const float inv = 1.0f / (float)N;
+    const float beta = a.beta;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const float2 xv = cscale(x[m], inv);
+      const float2 yv = y[m];
+      const bool s = bit_at(Sm, row * N + t + T * m);
+      if (a.alg == ALG_HIO) {
+        const bool feasible = s && inside_phase(yv, a.ph);
+        xn[m] = feasible ? yv : make_float2(xv.x - beta * yv.x, xv.y - beta * yv.y);
+      } else {  // RAAR
+        const float2 z = make_float2(2.f * yv.x - xv.x, 2.f * yv.y - xv.y);
+        const float2 pc = s ? proj_phase(z, a.ph) : make_float2(0.f, 0.f);
+        const float g = 1.f - 2.f * beta;
+        xn[m] = make_float2(beta * pc.x + beta * xv.x + g * yv.x, beta * pc.y + beta * xv.y + g * yv.y);
+      }
+    }
+  }
+
+  if (a.out_mode == OUT_REAL) {
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) a.X[off + t + T * m] = xn[m];
+    }
+    return;
+  }
+  if (a.out_mode == OUT_T_PC) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const bool s = bit_at(Sm, row * N + t + T * m);
+      xn[m] = s ? proj_phase(xn[m], a.ph_next) : make_float2(0.f, 0.f);
+    }
+  }
+  fft<N, -1, 1>(xn, l, t, a.tw);
+  if (valid) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) a.T[off + t + T * m] = xn[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fitness column pass: column FFT of rowFFT(S x), FP64 partial sums of
+// Xi (|X| - M)^2 per tile (Eq. error_calc numerator).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(C* T) void k_col_err(ColErrArgs a) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int c = tid % C, t = tid / C;
+  const int col = blockIdx.x * C + c;
+  const int slot = a.slots[blockIdx.y];
+  const float2* src = a.T + (size_t)slot * NN;
+  float2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = src[(size_t)(t + T * m) * N + col];
+  fft<N, -1, C>(v, lds + c, t, a.tw);
+  const float inv = 1.0f / (float)N;
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int e = t + T * m;
+    const float stored = a.amp[(size_t)e * N + col];
+    if (!signbit(stored)) {
+      const float2 X = cscale(v[m], inv);
+      const double d = (double)sqrtf(X.x * X.x + X.y * X.y) - (double)(stored * a.amp_scale);
+      acc += d * d;
+    }
+  }
+  acc = wave_sum(acc);
+  const int nw = (blockDim.x + 63) / 64;
+  double* wsum = reinterpret_cast<double*>(lds);  // the transform left the tile buffer free
+  if ((tid & 63) == 0) wsum[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += wsum[w];
+    a.partial[(size_t)blockIdx.y * (N / C) + blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Generic row / column transforms (spectra for crossover, the fft2 entry point).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(RW* T) void k_row_fft(RowFftArgs a) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int r = tid / T, t = tid % T;
+  const int grow = blockIdx.x * RW + r;
+  const bool valid = grow < a.nm * N;
+  const int member = valid ? grow / N : 0;
+  const int row = valid ? grow % N : 0;
+  const int si = a.slots_in ? a.slots_in[member] : member;
+  const int so = a.slots_out ? a.slots_out[member] : member;
+  const size_t offi = (size_t)si * NN + (size_t)row * N;
+  const size_t offo = (size_t)so * NN + (size_t)row * N;
+  float2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = valid ? a.in[offi + t + T * m] : make_float2(0.f, 0.f);
+  if (a.dir < 0) fft<N, -1, 1>(v, lds + r * N, t, a.tw);
+  else fft<N, +1, 1>(v, lds + r * N, t, a.tw);
+  if (valid) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) a.out[offo + t + T * m] = cscale(v[m], a.scale);
+  }
+}
+
+__global__ __launch_bounds__(C* T) void k_col_fft(ColFftArgs a) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int c = tid % C, t = tid / C;
+  const int col = blockIdx.x * C + c;
+  const int member = blockIdx.y;
+  const int si = a.slots_in ? a.slots_in[member] : member;
+  const int so = a.slots_out ? a.slots_out[member] : member;
+  const float2* src = a.in + (size_t)si * NN;
+  float2* dst = a.out + (size_t)so * NN;
+  float2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = src[(size_t)(t + T * m) * N + col];
+  if (a.dir < 0) fft<N, -1, C>(v, lds + c, t, a.tw);
+  else fft<N, +1, C>(v, lds + c, t, a.tw);
+#pragma unroll
+  for (int m = 0; m < E; ++m) dst[(size_t)(t + T * m) * N + col] = cscale(v[m], a.scale);
+}
+
+// ---------------------------------------------------------------------------
+// Reshift cross-correlations (Eq. crosscorr): column IFFT of the masked
+// products Xi conj(Xq) Xp (parent as is) and Xi Xq Xp (its twin).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(C* T) void k_col_corr(ColCorrArgs a) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int c = tid % C, t = tid / C;
+  const int col = blockIdx.x * C + c;
+  const int pair = blockIdx.y;
+  const int p = pair / 3;
+  const int q = a.abc[pair];
+  const float2* Xq = a.F + (size_t)q * NN;
+  const float2* Xp = a.F + (size_t)p * NN;
+  float2 v1[E], v2[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const size_t i = (size_t)(t + T * m) * N + col;
+    const float2 xq = Xq[i], xp = Xp[i];
+    const bool known = !signbit(a.amp[i]);
+    v1[m] = known ? cmul(cconj(xq), xp) : make_float2(0.f, 0.f);
+    v2[m] = known ? cmul(xq, xp) : make_float2(0.f, 0.f);
+  }
+  fft<N, +1, C>(v1, lds + c, t, a.tw);
+  fft<N, +1, C>(v2, lds + c, t, a.tw);
+  float2* d1 = a.C + (size_t)(2 * pair) * NN;
+  float2* d2 = d1 + NN;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const size_t i = (size_t)(t + T * m) * N + col;
+    d1[i] = v1[m];
+    d2[i] = v2[m];
+  }
+}
+
+// Row IFFT of the correlation images and per-workgroup argmax of |C|^2
+// (ties to the lowest linear index).
+__device__ __forceinline__ bool better(float v1, int i1, float v2, int i2) {
+  return v1 > v2 || (v1 == v2 && i1 < i2);
+}
+
+__global__ __launch_bounds__(RWI* T) void k_row_argmax(RowArgmaxArgs a) {
+  extern __shared__ float2 lds[];
+  __shared__ ArgmaxRec red[RWI * T];
+  const int tid = threadIdx.x;
+  const int r = tid / T, t = tid % T;
+  const int img = blockIdx.y;
+  const int row = blockIdx.x * RWI + r;
+  const float2* src = a.C + (size_t)img * NN + (size_t)row * N;
+  float2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = src[t + T * m];
+  fft<N, +1, 1>(v, lds + r * N, t, a.tw);
+  ArgmaxRec b;
+  b.val = -1.f;
+  b.idx = 0x7fffffff;
+  b.re = b.im = 0.f;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const float q = v[m].x * v[m].x + v[m].y * v[m].y;
+    const int idx = row * N + t + T * m;
+    if (better(q, idx, b.val, b.idx)) {
+      b.val = q;
+      b.idx = idx;
+      b.re = v[m].x;
+      b.im = v[m].y;
+    }
+  }
+  red[tid] = b;
+  __syncthreads();
+  if (tid == 0) {
+    ArgmaxRec best = red[0];
+    for (int i = 1; i < RWI * T; ++i)
+      if (better(red[i].val, red[i].idx, best.val, best.idx)) best = red[i];
+    a.partial[(size_t)img * (N / RWI) + blockIdx.x] = best;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Crossover mixing in the Fourier domain, fused with the column IFFT:
+// aligned parents X' = e^{i phi} e^{-2 pi i k.d/N} (X or conj X); on the
+// crossover map X_a' + C_w (X_b' - X_c'), elsewhere the child's own parent.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(C* T) void k_col_mix(ColMixArgs a) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int c = tid % C, t = tid / C;
+  const int col = blockIdx.x * C + c;
+  const int p = blockIdx.y;
+  const int* abc = a.abc + 3 * p;
+  const int* mp = a.mapprm + 5 * p;
+  const int tx = mp[0], ty = mp[1], sx = mp[2], sy = mp[3];
+  int ra, rb, rh;
+  rotation(mp[4], ra, rb, rh);
+  const AlignRec al[3] = {a.align[3 * p], a.align[3 * p + 1], a.align[3 * p + 2]};
+  const float2* Fq[3] = {a.F + (size_t)abc[0] * NN, a.F + (size_t)abc[1] * NN,
+                         a.F + (size_t)abc[2] * NN};
+  const float2* Fp = a.F + (size_t)p * NN;
+  const int vv = col < N / 2 ? col : col - N;
+  float2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int e = t + T * m;
+    const size_t i = (size_t)e * N + col;
+    const int u = e < N / 2 ? e : e - N;
+    const int ur = ra * u + rb * vv;
+    const int vr = -rb * u + ra * vv;
+    const int qx = floor_div(ur + rh * sx, rh * tx);
+    const int qy = floor_div(vr + rh * sy, rh * ty);
+    const uint32_t key = ((uint32_t)(qx & 0xFFFF) << 16) | (uint32_t)(qy & 0xFFFF);
+    const U4 o = philox4x32_10(key, (uint32_t)p, (uint32_t)a.gen, PURPOSE_TILE, (uint32_t)a.seed,
+                               (uint32_t)(a.seed >> 32));
+    float2 out;
+    if ((uint64_t)o.v[0] < a.cp_thr) {
+      float2 xs[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        float2 xq = Fq[k][i];
+        if (al[k].twin) xq = cconj(xq);
+        const int ridx = (int)(((long long)e * al[k].dr + (long long)col * al[k].dc) % N);
+        const float2 w = a.tw[ridx];  // exp(-2 pi i ridx / N)
+        xs[k] = cmul(make_float2(al[k].pr, al[k].pi), cmul(w, xq));
+      }
+      out = make_float2(xs[0].x + a.c_w * (xs[1].x - xs[2].x), xs[0].y + a.c_w * (xs[1].y - xs[2].y));
+    } else {
+      out = Fp[i];
+    }
+    v[m] = cscale(out, a.inv_n);
+  }
+  fft<N, +1, C>(v, lds + c, t, a.tw);
+  float2* dst = a.out + (size_t)a.table[a.P + p] * NN;
+#pragma unroll
+  for (int m = 0; m < E; ++m) dst[(size_t)(t + T * m) * N + col] = v[m];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+constexpr size_t kColLds = (size_t)C * N * sizeof(float2);
+constexpr size_t kRowLds = (size_t)RW * N * sizeof(float2);
+constexpr size_t kRowLdsI = (size_t)RWI * N * sizeof(float2);
+
+template <typename K>
+hipError_t set_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+int row_blocks(int nm) { return (nm * N + RW - 1) / RW; }
+
+hipError_t l_row_ingest(const RowIngestArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_ingest, dim3(row_blocks(a.nm)), dim3(RW * T), kRowLds, s, a);
+  return hipGetLastError();
+}
+hipError_t l_col_proj(const ColProjArgs& a, hipStream_t s) {
+  static const hipError_t init = set_lds(k_col_proj, kColLds);
+  if (init != hipSuccess) return init;
+  hipLaunchKernelGGL(k_col_proj, dim3(N / C, a.nm), dim3(C * T), kColLds, s, a);
+  return hipGetLastError();
+}
+hipError_t l_row_update(const RowUpdateArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_update, dim3(row_blocks(a.nm)), dim3(RW * T), kRowLds, s, a);
+  return hipGetLastError();
+}
+hipError_t l_col_err(const ColErrArgs& a, hipStream_t s) {
+  static const hipError_t init = set_lds(k_col_err, kColLds);
+  if (init != hipSuccess) return init;
+  hipLaunchKernelGGL(k_col_err, dim3(N / C, a.nm), dim3(C * T), kColLds, s, a);
+  return hipGetLastError();
+}
+hipError_t l_row_fft(const RowFftArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_fft, dim3(row_blocks(a.nm)), dim3(RW * T), kRowLds, s, a);
+  return hipGetLastError();
+}
+hipError_t l_col_fft(const ColFftArgs& a, hipStream_t s) {
+  static const hipError_t init = set_lds(k_col_fft, kColLds);
+  if (init != hipSuccess) return init;
+  hipLaunchKernelGGL(k_col_fft, dim3(N / C, a.nm), dim3(C * T), kColLds, s, a);
+  return hipGetLastError();
+}
+hipError_t l_col_corr(const ColCorrArgs& a, hipStream_t s) {
+  static const hipError_t init = set_lds(k_col_corr, kColLds);
+  if (init != hipSuccess) return init;
+  hipLaunchKernelGGL(k_col_corr, dim3(N / C, a.npairs), dim3(C * T), kColLds, s, a);
+  return hipGetLastError();
+}
+hipError_t l_row_argmax(const RowArgmaxArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_argmax, dim3(N / RWI, a.nimg), dim3(RWI * T), kRowLdsI, s, a);
+  return hipGetLastError();
+}
+hipError_t l_col_mix(const ColMixArgs& a, hipStream_t s) {
+  static const hipError_t init = set_lds(k_col_mix, kColLds);
+  if (init != hipSuccess) return init;
+  hipLaunchKernelGGL(k_col_mix, dim3(N / C, a.P), dim3(C * T), kColLds, s, a);
+  return hipGetLastError();
+}
+
+const SizeKernels kTable = {N,          E,          T,          C,           RW,         RWI,
+                            kColLds,    kRowLds,    l_row_ingest, l_col_proj, l_row_update,
+                            l_col_err,  l_row_fft,  l_col_fft,  l_col_corr,  l_row_argmax,
+                            l_col_mix};
+
+}  // namespace
+
+#define SPR_CAT2(a, b) a##b
+#define SPR_CAT(a, b) SPR_CAT2(a, b)
+const SizeKernels* SPR_CAT(size_kernels_, SPR_N)() { return &kTable; }
+
+}  // namespace spr

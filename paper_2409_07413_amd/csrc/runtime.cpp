@@ -1,0 +1,1117 @@
+// Host runtime and C ABI (include/spr.h): contexts, shots, populations,
+// schedules and the enqueueing of the hot-path kernels on a HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels_common.hpp"
+#include "spr.h"
+
+namespace spr {
+
+#define SPR_SIZES(X) \
+  X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+#define SPR_DECL(n) const SizeKernels* size_kernels_##n();
+SPR_SIZES(SPR_DECL)
+#undef SPR_DECL
+
+const SizeKernels* size_kernels(int n) {
+  switch (n) {
+#define SPR_CASE(n) \
+  case n:           \
+    return size_kernels_##n();
+    SPR_SIZES(SPR_CASE)
+#undef SPR_CASE
+    default:
+      return nullptr;
+  }
+}
+
+}  // namespace spr
+
+using namespace spr;
+
+struct spr_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::map<int, float2*> tw;
+  std::mutex mu;
+};
+
+struct spr_shot {
+  spr_ctx* ctx = nullptr;
+  int n = 0;
+  const SizeKernels* K = nullptr;
+  float* amp = nullptr;  // FFT order, sign bit = unknown
+  float amp_scale = 1.f;
+  double den = 0.0;      // sum of Xi M^2
+  int live = 0;
+};
+
+struct spr_pop {
+  spr_shot* shot = nullptr;
+  spr_ctx* ctx = nullptr;
+  const SizeKernels* K = nullptr;
+  int n = 0, P = 0, nslots = 0, W = 0;
+  bool memetic = false;
+  uint64_t seed = 0;
+  int gen_offset = 0;
+  float2 *X = nullptr, *T = nullptr, *Y = nullptr;
+  uint32_t* S = nullptr;
+  double* E = nullptr;
+  int* table = nullptr;
+  double* err_partial = nullptr;
+  float* block_max = nullptr;
+  float* maxv = nullptr;
+  int* flags = nullptr;
+  PopScalars* scal = nullptr;
+  GenStatsDev* hist = nullptr;
+  int hist_cap = 4096;
+  float2* F = nullptr;
+  float2* Cc = nullptr;
+  ArgmaxRec* amax = nullptr;
+  AlignRec* align = nullptr;
+  int* abc = nullptr;
+  int* mapprm = nullptr;
+  uint8_t* stage = nullptr;
+  size_t stage_bytes = 0;
+  hipStream_t last = nullptr;
+  // optional per-kernel timing: HIP events recorded around each launch
+  bool timing = false;
+  struct Stamp {
+    int kernel;
+    hipEvent_t start, stop;
+  };
+  std::vector<Stamp> stamps;
+  std::vector<hipEvent_t> event_pool;
+  double kernel_ms[SPR_KERNEL_COUNT] = {};
+  int64_t kernel_launches[SPR_KERNEL_COUNT] = {};
+};
+
+struct spr_sched {
+  std::vector<spr_op> ops;
+};
+
+namespace {
+
+struct Fail {
+  spr_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(spr_status code, const std::string& msg) { throw Fail{code, msg}; }
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) fail(SPR_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T_>
+T_* dalloc(size_t count) {
+  void* p = nullptr;
+  size_t bytes = std::max<size_t>(count * sizeof(T_), 256);
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(SPR_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  return static_cast<T_*>(p);
+}
+
+template <class T_>
+void dfree(T_*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+template <class Fn>
+spr_status guarded(spr_ctx* ctx, Fn&& fn) {
+  try {
+    fn();
+    return SPR_OK;
+  } catch (const Fail& f) {
+    if (ctx) ctx->err = f.msg;
+    return f.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->err = "host allocation failed";
+    return SPR_E_OOM;
+  } catch (...) {
+    if (ctx) ctx->err = "unexpected internal error";
+    return SPR_E_INVALID_ARG;
+  }
+}
+
+void use_device(spr_ctx* ctx) { HIPCHK(hipSetDevice(ctx->device)); }
+
+const float2* twiddles(spr_ctx* ctx, int n) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  auto it = ctx->tw.find(n);
+  if (it != ctx->tw.end()) return it->second;
+  std::vector<float2> h(n);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int e = 0; e < n; ++e) {
+    const double ang = two_pi * (double)e / (double)n;
+    h[e] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+  }
+  float2* d = dalloc<float2>(n);
+  HIPCHK(hipMemcpy(d, h.data(), n * sizeof(float2), hipMemcpyHostToDevice));
+  ctx->tw[n] = d;
+  return d;
+}
+
+Phase phase_of(double chi) {
+  Phase p;
+  p.c = 0.f;
+  p.s = 0.f;
+  if (!(chi > 0.0) || chi >= 1.0) {
+    p.mode = PHASE_OFF;
+  } else if (chi == 0.5) {
+    p.mode = PHASE_POS;
+  } else {
+    p.mode = PHASE_CONE;
+    const double th = chi * 3.14159265358979323846264338327950288;
+    p.c = (float)std::cos(th);
+    p.s = (float)std::sin(th);
+  }
+  return p;
+}
+
+void to_host(std::vector<uint8_t>& dst, const void* src, size_t bytes, bool device) {
+  dst.resize(bytes);
+  if (device) HIPCHK(hipMemcpy(dst.data(), src, bytes, hipMemcpyDeviceToHost));
+  else std::memcpy(dst.data(), src, bytes);
+}
+
+uint8_t* stage(spr_pop* pop, size_t bytes) {
+  if (pop->stage_bytes < bytes) {
+    dfree(pop->stage);
+    pop->stage = dalloc<uint8_t>(bytes);
+    pop->stage_bytes = bytes;
+  }
+  return pop->stage;
+}
+
+struct Scope {
+  const int* slots;
+  int nm;
+};
+
+Scope scope_of(spr_pop* pop, int scope) {
+  switch (scope) {
+    case SPR_SCOPE_ALL:
+      return {pop->table, pop->nslots};
+    case SPR_SCOPE_PARENTS:
+      return {pop->table, pop->P};
+    case SPR_SCOPE_CHILDREN:
+      if (!pop->memetic) fail(SPR_E_INVALID_ARG, "children scope on a population without children");
+      return {pop->table + pop->P, pop->P};
+    default:
+      fail(SPR_E_INVALID_ARG, "unknown scope " + std::to_string(scope));
+  }
+}
+
+void launch_ok(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(SPR_E_HIP, std::string("launch of ") + what + " failed: " + hipGetErrorString(e));
+}
+
+hipEvent_t pooled_event(spr_pop* pop) {
+  if (!pop->event_pool.empty()) {
+    hipEvent_t e = pop->event_pool.back();
+    pop->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
+// Launch through `fn`, bracketing it with events when timing is enabled.
+template <class Fn>
+void timed(spr_pop* pop, int kernel, hipStream_t s, const char* what, Fn&& fn) {
+  if (!pop->timing) {
+    launch_ok(fn(), what);
+    return;
+  }
+  hipEvent_t a = pooled_event(pop), b = pooled_event(pop);
+  HIPCHK(hipEventRecord(a, s));
+  launch_ok(fn(), what);
+  HIPCHK(hipEventRecord(b, s));
+  pop->stamps.push_back({kernel, a, b});
+}
+
+// Fold finished stamps into the per-kernel totals (after a synchronisation).
+void collect_stamps(spr_pop* pop) {
+  for (auto& st : pop->stamps) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, st.start, st.stop));
+    pop->kernel_ms[st.kernel] += ms;
+    pop->kernel_launches[st.kernel] += 1;
+    pop->event_pool.push_back(st.start);
+    pop->event_pool.push_back(st.stop);
+  }
+  pop->stamps.clear();
+}
+
+struct Iter {
+  int alg;
+  float beta;
+  double chi;
+};
+
+// One Sequence: ingest, then per iteration a column pass and a row pass.
+void run_iterations(spr_pop* pop, const std::vector<Iter>& its, int scope, hipStream_t s) {
+  if (its.empty()) return;
+  const SizeKernels* K = pop->K;
+  const float2* tw = twiddles(pop->ctx, pop->n);
+  Scope sc = scope_of(pop, scope);
+  RowIngestArgs ia{sc.slots, sc.nm, pop->X, pop->T, pop->S, pop->W,
+                   its[0].alg == ALG_ER ? INGEST_PC : INGEST_PLAIN, phase_of(its[0].chi), tw};
+  timed(pop, SPR_KERNEL_ROW_INGEST, s, "row_ingest", [&] { return K->row_ingest(ia, s); });
+  for (size_t i = 0; i < its.size(); ++i) {
+    ColProjArgs ca{sc.slots, sc.nm, pop->T, pop->Y, pop->shot->amp, pop->shot->amp_scale, tw};
+    timed(pop, SPR_KERNEL_COL_PROJ, s, "col_proj", [&] { return K->col_proj(ca, s); });
+    const bool last = i + 1 == its.size();
+    RowUpdateArgs ra;
+    ra.slots = sc.slots;
+    ra.nm = sc.nm;
+    ra.Y = pop->Y;
+    ra.T = pop->T;
+    ra.X = pop->X;
+    ra.S = pop->S;
+    ra.W = pop->W;
+    ra.alg = its[i].alg;
+    ra.beta = its[i].beta;
+    ra.ph = phase_of(its[i].chi);
+    ra.out_mode = last ? OUT_REAL : (its[i + 1].alg == ALG_ER ? OUT_T_PC : OUT_T_PLAIN);
+    ra.ph_next = last ? phase_of(1.0) : phase_of(its[i + 1].chi);
+    ra.tw = tw;
+    const int kid = ra.alg == ALG_ER ? SPR_KERNEL_ROW_UPDATE_ER : SPR_KERNEL_ROW_UPDATE_IA;
+    timed(pop, kid, s, "row_update", [&] { return K->row_update(ra, s); });
+  }
+}
+
+void smooth(spr_pop* pop, double sigma, Scope sc, hipStream_t s) {
+  SmoothArgs ra{};
+  SmoothColArgs ca{};
+  int r = 0;
+  std::vector<double> w(1, 1.0);
+  if (sigma > 0) {
+    r = (int)std::ceil(4.0 * sigma);
+    if (r > (MAX_TAPS - 1) / 2) fail(SPR_E_INVALID_ARG, "shrink-wrap sigma above 8 pixels is not supported");
+    w.assign(2 * r + 1, 0.0);
+    double sum = 0.0;
+    for (int k = -r; k <= r; ++k) {
+      w[k + r] = std::exp(-(double)(k * k) / (2.0 * sigma * sigma));
+      sum += w[k + r];
+    }
+    for (auto& v : w) v /= sum;
+  }
+  ra.slots = sc.slots;
+  ra.nm = sc.nm;
+  ra.n = pop->n;
+  ra.r = r;
+  ra.X = pop->X;
+  ra.out = reinterpret_cast<float*>(pop->T);
+  ca.nm = sc.nm;
+  ca.n = pop->n;
+  ca.r = r;
+  ca.in = ra.out;
+  ca.out = reinterpret_cast<float*>(pop->Y);
+  ca.block_max = pop->block_max;
+  for (int k = 0; k <= 2 * r; ++k) ra.w[k] = ca.w[k] = (float)w[k];
+  MemberMaxArgs ma{sc.nm, (int)(((long)pop->n * pop->n + 255) / 256), pop->block_max, pop->maxv};
+  launch_ok(launch_smooth(ra, ca, ma, s), "smooth");
+}
+
+void shrinkwrap(spr_pop* pop, const spr_op& op, hipStream_t s) {
+  Scope sc = scope_of(pop, op.scope);
+  smooth(pop, op.sigma, sc, s);
+  ThresholdArgs ta{sc.slots, sc.nm, pop->n, pop->W, reinterpret_cast<const float*>(pop->Y), pop->maxv,
+                   op.tau, pop->S};
+  launch_ok(launch_threshold(ta, s), "threshold");
+}
+
+void support_area(spr_pop* pop, const spr_op& op, hipStream_t s) {
+  Scope sc = scope_of(pop, op.scope);
+  smooth(pop, op.sigma, sc, s);
+  TopkArgs ta{};
+  ta.slots = sc.slots;
+  ta.nm = sc.nm;
+  ta.n = pop->n;
+  ta.W = pop->W;
+  ta.in = reinterpret_cast<const float*>(pop->Y);
+  if (op.which == SPR_AREA_ABS) {
+    ta.alpha_src = nullptr;
+    ta.alpha_abs = op.alpha;
+  } else if (op.which == SPR_AREA_BEST || op.which == SPR_AREA_EVAL) {
+    ta.alpha_src = pop->scal->alpha;
+    ta.alpha_index = op.which;
+  } else {
+    fail(SPR_E_INVALID_ARG, "unknown support-area source");
+  }
+  ta.S = pop->S;
+  launch_ok(launch_topk(ta, s), "topk");
+}
+
+void get_error(spr_pop* pop, int scope, hipStream_t s) {
+  const SizeKernels* K = pop->K;
+  const float2* tw = twiddles(pop->ctx, pop->n);
+  Scope sc = scope_of(pop, scope);
+  RowIngestArgs ia{sc.slots, sc.nm, pop->X, pop->T, pop->S, pop->W, INGEST_SMASK, phase_of(1.0), tw};
+  launch_ok(K->row_ingest(ia, s), "row_ingest");
+  ColErrArgs ea{sc.slots, sc.nm, pop->T, pop->shot->amp, pop->shot->amp_scale, pop->err_partial, tw};
+  launch_ok(K->col_err(ea, s), "col_err");
+  ErrFinalArgs fa{pop->err_partial, pop->n / K->C, sc.nm, sc.slots, pop->shot->den, pop->E, pop->flags};
+  launch_ok(launch_err_final(fa, s), "err_final");
+}
+
+void need_memetic(spr_pop* pop, const char* what) {
+  if (!pop->memetic) fail(SPR_E_INVALID_ARG, std::string(what) + " needs a population created with SPR_POP_MEMETIC");
+}
+
+void crossover(spr_pop* pop, const spr_op& op, hipStream_t s) {
+  need_memetic(pop, "CROSSOVER");
+  if (pop->P < 4) fail(SPR_E_INVALID_ARG, "crossover needs P >= 4");
+  const SizeKernels* K = pop->K;
+  const int n = pop->n, P = pop->P;
+  const size_t nn = (size_t)n * n;
+  const float2* tw = twiddles(pop->ctx, n);
+  int t_min = op.t_min > 0 ? op.t_min : 4;
+  int t_max = op.t_max > 0 ? op.t_max : std::max(t_min, n / 8);
+  if (t_max < t_min) fail(SPR_E_INVALID_ARG, "crossover t_max < t_min");
+  if (!(op.c_p >= 0.0 && op.c_p <= 1.0)) fail(SPR_E_INVALID_ARG, "crossover probability outside [0, 1]");
+  const int blocks = n / K->RWI;
+  if (!pop->F) {
+    pop->F = dalloc<float2>((size_t)P * nn);
+    pop->Cc = dalloc<float2>((size_t)6 * P * nn);
+    pop->amax = dalloc<ArgmaxRec>((size_t)6 * P * blocks);
+    pop->align = dalloc<AlignRec>((size_t)3 * P);
+    pop->abc = dalloc<int>((size_t)3 * P);
+    pop->mapprm = dalloc<int>((size_t)5 * P);
+  }
+  // parent spectra F[p] (unitary)
+  RowFftArgs r1{pop->table, pop->table, P, pop->X, pop->T, -1, 1.f, tw};
+  launch_ok(K->row_fft(r1, s), "row_fft");
+  ColFftArgs c1{pop->table, nullptr, P, pop->T, pop->F, -1, 1.f / (float)n, tw};
+  launch_ok(K->col_fft(c1, s), "col_fft");
+  ChoiceArgs ch{P, op.gen, t_min, t_max, pop->seed, pop->abc, pop->mapprm};
+  launch_ok(launch_choice(ch, s), "choice");
+  ColCorrArgs cc{3 * P, pop->abc, pop->F, pop->shot->amp, pop->Cc, tw};
+  launch_ok(K->col_corr(cc, s), "col_corr");
+  RowArgmaxArgs am{6 * P, pop->Cc, pop->amax, tw};
+  launch_ok(K->row_argmax(am, s), "row_argmax");
+  AlignArgs al{3 * P, blocks, n, pop->amax, pop->align};
+  launch_ok(launch_align(al, s), "align");
+  double thr = std::floor(op.c_p * 4294967296.0);
+  thr = std::min(std::max(thr, 0.0), 4294967296.0);
+  ColMixArgs mx{P, pop->abc, pop->mapprm, pop->align, pop->F, pop->table, pop->T, (float)op.c_w,
+                pop->seed, op.gen, (uint64_t)thr, 1.f / (float)n, tw};
+  launch_ok(K->col_mix(mx, s), "col_mix");
+  RowFftArgs r2{pop->table + P, pop->table + P, P, pop->T, pop->X, +1, 1.f, tw};
+  launch_ok(K->row_fft(r2, s), "row_fft");
+  SupportMixArgs sm{P, n, pop->W, pop->table, pop->abc, pop->align, pop->S};
+  launch_ok(launch_support_mix(sm, s), "support_mix");
+}
+
+GenStatsDev* record(spr_pop* pop, int gen) {
+  int g = gen - 1;
+  if (g < 0) g = 0;
+  return pop->hist + (g % pop->hist_cap);
+}
+
+void validate_op(const spr_op& o) {
+  switch (o.kind) {
+    case SPR_OP_ER:
+    case SPR_OP_HIO:
+    case SPR_OP_RAAR:
+      if (o.count < 0) fail(SPR_E_INVALID_ARG, "negative iteration count");
+      if (o.kind != SPR_OP_ER && !(o.beta > 0.0 && o.beta <= 1.0)) fail(SPR_E_INVALID_ARG, "beta outside (0, 1]");
+      break;
+    case SPR_OP_SHRINKWRAP:
+      if (!(o.sigma >= 0.0 && o.sigma <= 8.0)) fail(SPR_E_INVALID_ARG, "sigma outside [0, 8]");
+      if (!(o.tau >= 0.0 && o.tau <= 1.0)) fail(SPR_E_INVALID_ARG, "tau outside [0, 1]");
+      break;
+    case SPR_OP_SUPPORT_AREA:
+      if (!(o.sigma >= 0.0 && o.sigma <= 8.0)) fail(SPR_E_INVALID_ARG, "sigma outside [0, 8]");
+      if (o.which < 0 || o.which > 2) fail(SPR_E_INVALID_ARG, "unknown area source");
+      break;
+    case SPR_OP_GET_ERROR:
+      break;
+    case SPR_OP_STATS:
+      if (o.gen < 1 || o.gens < 1) fail(SPR_E_INVALID_ARG, "STATS needs gen >= 1 and gens >= 1");
+      break;
+    case SPR_OP_CROSSOVER:
+      if (o.gen < 1) fail(SPR_E_INVALID_ARG, "CROSSOVER needs gen >= 1");
+      if (!(o.c_w >= 0.0 && o.c_w <= 2.0)) fail(SPR_E_INVALID_ARG, "c_w outside [0, 2]");
+      break;
+    case SPR_OP_SELECT:
+      if (o.gen < 1) fail(SPR_E_INVALID_ARG, "SELECT needs gen >= 1");
+      break;
+    default:
+      fail(SPR_E_INVALID_ARG, "unknown op kind " + std::to_string(o.kind));
+  }
+  if (o.scope < 0 || o.scope > 2) fail(SPR_E_INVALID_ARG, "unknown scope");
+}
+
+void run_schedule(spr_pop* pop, const spr_sched* sch, hipStream_t s) {
+  const auto& ops = sch->ops;
+  for (const auto& o : ops) {
+    if ((o.kind == SPR_OP_CROSSOVER || o.kind == SPR_OP_SELECT || o.kind == SPR_OP_STATS ||
+         o.scope == SPR_SCOPE_CHILDREN) && !pop->memetic)
+      fail(SPR_E_INVALID_ARG, "schedule needs a population created with SPR_POP_MEMETIC");
+    if (o.kind == SPR_OP_CROSSOVER && pop->P < 4) fail(SPR_E_INVALID_ARG, "crossover needs P >= 4");
+  }
+  size_t i = 0;
+  while (i < ops.size()) {
+    const spr_op& o = ops[i];
+    if (o.kind == SPR_OP_ER || o.kind == SPR_OP_HIO || o.kind == SPR_OP_RAAR) {
+      std::vector<Iter> its;
+      const int scope = o.scope;
+      while (i < ops.size() &&
+             (ops[i].kind == SPR_OP_ER || ops[i].kind == SPR_OP_HIO || ops[i].kind == SPR_OP_RAAR) &&
+             ops[i].scope == scope) {
+        const spr_op& q = ops[i];
+        const int alg = q.kind == SPR_OP_ER ? ALG_ER : (q.kind == SPR_OP_HIO ? ALG_HIO : ALG_RAAR);
+        for (int c = 0; c < q.count; ++c) its.push_back({alg, (float)q.beta, q.chi});
+        ++i;
+      }
+      run_iterations(pop, its, scope, s);
+      continue;
+    }
+    switch (o.kind) {
+      case SPR_OP_SHRINKWRAP:
+        shrinkwrap(pop, o, s);
+        break;
+      case SPR_OP_SUPPORT_AREA:
+        support_area(pop, o, s);
+        break;
+      case SPR_OP_GET_ERROR:
+        get_error(pop, o.scope, s);
+        break;
+      case SPR_OP_STATS: {
+        need_memetic(pop, "STATS");
+        StatsArgs sa{pop->P, pop->W, o.gen, o.gens, pop->table, pop->E, pop->S, pop->scal, record(pop, o.gen)};
+        launch_ok(launch_stats(sa, s), "stats");
+        break;
+      }
+      case SPR_OP_CROSSOVER:
+        crossover(pop, o, s);
+        break;
+      case SPR_OP_SELECT: {
+        need_memetic(pop, "SELECT");
+        SelectArgs se{pop->P, o.gen, pop->table, pop->E, record(pop, o.gen)};
+        launch_ok(launch_select(se, s), "select");
+        break;
+      }
+      default:
+        fail(SPR_E_INVALID_ARG, "unknown op kind");
+    }
+    ++i;
+  }
+}
+
+void sched_at(int g, int G, int j, int j_er, int j_end, double sigma, double sigma_end, double tau,
+              double tau_end, int& jg, int& jer, double& sg, double& tg) {
+  const double t = G <= 1 ? 0.0 : (double)(g - 1) / (double)(G - 1);
+  jg = (int)std::floor((double)j + t * (double)(j_end - j) + 0.5);
+  jer = j + j_er - jg;
+  sg = sigma + t * (sigma_end - sigma);
+  tg = tau + t * (tau_end - tau);
+}
+
+spr_op make_op(int kind) {
+  spr_op o;
+  std::memset(&o, 0, sizeof(o));
+  o.kind = kind;
+  o.chi = 0.5;
+  return o;
+}
+
+void push_seq(std::vector<spr_op>& ops, int alg, int jg, int jer, double beta, double chi) {
+  if (jg > 0) {
+    spr_op o = make_op(alg == SPR_ALG_RAAR ? SPR_OP_RAAR : SPR_OP_HIO);
+    o.count = jg;
+    o.beta = beta;
+    o.chi = chi;
+    ops.push_back(o);
+  }
+  if (jer > 0) {
+    spr_op o = make_op(SPR_OP_ER);
+    o.count = jer;
+    o.chi = chi;
+    ops.push_back(o);
+  }
+}
+
+void destroy_pop(spr_pop* p) {
+  for (auto& st : p->stamps) {
+    (void)hipEventDestroy(st.start);
+    (void)hipEventDestroy(st.stop);
+  }
+  p->stamps.clear();
+  for (auto e : p->event_pool) (void)hipEventDestroy(e);
+  p->event_pool.clear();
+  dfree(p->X);
+  dfree(p->T);
+  dfree(p->Y);
+  dfree(p->S);
+  dfree(p->E);
+  dfree(p->table);
+  dfree(p->err_partial);
+  dfree(p->block_max);
+  dfree(p->maxv);
+  dfree(p->flags);
+  dfree(p->scal);
+  dfree(p->hist);
+  dfree(p->F);
+  dfree(p->Cc);
+  dfree(p->amax);
+  dfree(p->align);
+  dfree(p->abc);
+  dfree(p->mapprm);
+  dfree(p->stage);
+}
+
+std::vector<int> host_table(spr_pop* pop) {
+  std::vector<int> t(pop->nslots);
+  HIPCHK(hipMemcpy(t.data(), pop->table, sizeof(int) * pop->nslots, hipMemcpyDeviceToHost));
+  return t;
+}
+
+void sync_pop(spr_pop* pop) {
+  if (pop->last) HIPCHK(hipStreamSynchronize(pop->last));
+  HIPCHK(hipStreamSynchronize(pop->ctx->stream));
+  if (!pop->stamps.empty()) collect_stamps(pop);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int32_t spr_supported_size(int32_t n) { return size_kernels(n) ? 1 : 0; }
+
+spr_status spr_ctx_create(int32_t hip_device, spr_ctx** out) {
+  if (!out) return SPR_E_INVALID_ARG;
+  *out = nullptr;
+  spr_ctx* ctx = new (std::nothrow) spr_ctx();
+  if (!ctx) return SPR_E_OOM;
+  spr_status st = guarded(ctx, [&] {
+    int count = 0;
+    HIPCHK(hipGetDeviceCount(&count));
+    if (hip_device < 0 || hip_device >= count) fail(SPR_E_INVALID_ARG, "no such device");
+    ctx->device = hip_device;
+    use_device(ctx);
+    HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+  });
+  if (st != SPR_OK) {
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return SPR_OK;
+}
+
+void spr_ctx_destroy(spr_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->tw) (void)hipFree(kv.second);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+const char* spr_ctx_last_error(const spr_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+spr_status spr_shot_create(spr_ctx* ctx, int32_t n, const float* amp, const uint8_t* mask, uint32_t flags,
+                           spr_shot** out) {
+  if (!ctx || !out || !amp || !mask) return SPR_E_INVALID_ARG;
+  *out = nullptr;
+  return guarded(ctx, [&] {
+    const SizeKernels* K = size_kernels(n);
+    if (!K) fail(SPR_E_UNSUPPORTED_SIZE, "unsupported detector size " + std::to_string(n));
+    use_device(ctx);
+    const size_t nn = (size_t)n * n;
+    const bool dev = flags & SPR_DEVICE_PTRS;
+    std::vector<uint8_t> ab, mb;
+    to_host(ab, amp, nn * sizeof(float), dev);
+    to_host(mb, mask, nn, dev);
+    const float* a = reinterpret_cast<const float*>(ab.data());
+    std::vector<float> enc(nn);
+    double den = 0.0;
+    const int h = (flags & SPR_LAYOUT_FFT) ? 0 : n / 2;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        // FFT-order index (i, j) reads the centred image at (i + n/2, j + n/2) mod n
+        const size_t src = (size_t)((i + h) % n) * n + (size_t)((j + h) % n);
+        const bool known = mb[src] != 0;
+        const float v = a[src];
+        if (known) {
+          if (!std::isfinite(v) || v < 0.f) fail(SPR_E_NUMERIC, "measured amplitude is negative or not finite");
+          enc[(size_t)i * n + j] = v == 0.f ? 0.f : v;
+          den += (double)v * (double)v;
+        } else {
+          enc[(size_t)i * n + j] = -0.f;
+        }
+      }
+    if (!(den > 0.0)) fail(SPR_E_INVALID_ARG, "sum of measured M^2 must be positive");
+    spr_shot* sh = new spr_shot();
+    sh->ctx = ctx;
+    sh->n = n;
+    sh->K = K;
+    sh->den = den;
+    try {
+      sh->amp = dalloc<float>(nn);
+      HIPCHK(hipMemcpy(sh->amp, enc.data(), nn * sizeof(float), hipMemcpyHostToDevice));
+      (void)twiddles(ctx, n);
+    } catch (...) {
+      dfree(sh->amp);
+      delete sh;
+      throw;
+    }
+    *out = sh;
+  });
+}
+
+spr_status spr_shot_destroy(spr_shot* shot) {
+  if (!shot) return SPR_E_INVALID_ARG;
+  if (shot->live > 0) {
+    shot->ctx->err = "shot still has live populations";
+    return SPR_E_BUSY;
+  }
+  (void)hipSetDevice(shot->ctx->device);
+  dfree(shot->amp);
+  delete shot;
+  return SPR_OK;
+}
+
+spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const uint8_t* supp0,
+                          int32_t supp_per_member, uint32_t flags, uint64_t seed, int32_t gen_offset,
+                          spr_pop** out) {
+  if (!shot || !out || !rho0 || !supp0) return SPR_E_INVALID_ARG;
+  *out = nullptr;
+  spr_ctx* ctx = shot->ctx;
+  return guarded(ctx, [&] {
+    if (P < 1) fail(SPR_E_INVALID_ARG, "P must be >= 1");
+    if (gen_offset < 0) fail(SPR_E_INVALID_ARG, "negative generation offset");
+    use_device(ctx);
+    spr_pop* pop = new spr_pop();
+    pop->shot = shot;
+    pop->ctx = ctx;
+    pop->K = shot->K;
+    pop->n = shot->n;
+    pop->P = P;
+    pop->memetic = (flags & SPR_POP_MEMETIC) != 0;
+    pop->nslots = pop->memetic ? 2 * P : P;
+    const size_t nn = (size_t)pop->n * pop->n;
+    pop->W = (int)((nn + 31) / 32);
+    pop->seed = seed;
+    pop->gen_offset = gen_offset;
+    try {
+      const size_t ns = pop->nslots;
+      pop->X = dalloc<float2>(ns * nn);
+      pop->T = dalloc<float2>(ns * nn);
+      pop->Y = dalloc<float2>(ns * nn);
+      pop->S = dalloc<uint32_t>(ns * pop->W);
+      pop->E = dalloc<double>(ns);
+      pop->table = dalloc<int>(ns);
+      pop->err_partial = dalloc<double>(ns * (pop->n / pop->K->C));
+      pop->block_max = dalloc<float>(ns * ((nn + 255) / 256));
+      pop->maxv = dalloc<float>(ns);
+      pop->flags = dalloc<int>(1);
+      pop->scal = dalloc<PopScalars>(1);
+      pop->hist = dalloc<GenStatsDev>(pop->hist_cap);
+      std::vector<int> tbl(ns);
+      for (size_t i = 0; i < ns; ++i) tbl[i] = (int)i;
+      HIPCHK(hipMemcpy(pop->table, tbl.data(), ns * sizeof(int), hipMemcpyHostToDevice));
+      std::vector<double> e(ns, std::numeric_limits<double>::infinity());
+      HIPCHK(hipMemcpy(pop->E, e.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+      HIPCHK(hipMemset(pop->flags, 0, sizeof(int)));
+      HIPCHK(hipMemset(pop->scal, 0, sizeof(PopScalars)));
+      HIPCHK(hipMemset(pop->hist, 0, sizeof(GenStatsDev) * pop->hist_cap));
+      HIPCHK(hipMemset(pop->S, 0, ns * pop->W * sizeof(uint32_t)));
+      HIPCHK(hipMemset(pop->X, 0, ns * nn * sizeof(float2)));
+      const bool dev = flags & SPR_DEVICE_PTRS;
+      HIPCHK(hipMemcpy(pop->X, rho0, (size_t)P * nn * sizeof(float2),
+                       dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+      const size_t sb = supp_per_member ? (size_t)P * nn : nn;
+      uint8_t* st = stage(pop, sb);
+      HIPCHK(hipMemcpy(st, supp0, sb, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+      PackArgs pa{pop->table, P, pop->n, pop->W, supp_per_member ? 0 : 1, st, pop->S};
+      launch_ok(launch_pack(pa, ctx->stream), "pack");
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    } catch (...) {
+      destroy_pop(pop);
+      delete pop;
+      throw;
+    }
+    shot->live++;
+    *out = pop;
+  });
+}
+
+spr_status spr_pop_destroy(spr_pop* pop) {
+  if (!pop) return SPR_E_INVALID_ARG;
+  (void)hipSetDevice(pop->ctx->device);
+  if (pop->last) (void)hipStreamSynchronize(pop->last);
+  (void)hipStreamSynchronize(pop->ctx->stream);
+  destroy_pop(pop);
+  pop->shot->live--;
+  delete pop;
+  return SPR_OK;
+}
+
+spr_status spr_pop_write(spr_pop* pop, const float* rho, const uint8_t* supp, const double* err,
+                         uint32_t flags) {
+  if (!pop) return SPR_E_INVALID_ARG;
+  spr_ctx* ctx = pop->ctx;
+  return guarded(ctx, [&] {
+    use_device(ctx);
+    sync_pop(pop);
+    const bool kids = flags & SPR_READ_CHILDREN;
+    if (kids) need_memetic(pop, "writing children");
+    const bool dev = flags & SPR_DEVICE_PTRS;
+    const size_t nn = (size_t)pop->n * pop->n;
+    std::vector<int> tbl = host_table(pop);
+    const int base = kids ? pop->P : 0;
+    if (rho) {
+      for (int p = 0; p < pop->P; ++p)
+        HIPCHK(hipMemcpy(pop->X + (size_t)tbl[base + p] * nn, rho + (size_t)p * nn * 2, nn * sizeof(float2),
+                         dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+    }
+    if (supp) {
+      uint8_t* st = stage(pop, (size_t)pop->P * nn);
+      HIPCHK(hipMemcpy(st, supp, (size_t)pop->P * nn, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+      PackArgs pa{pop->table + base, pop->P, pop->n, pop->W, 0, st, pop->S};
+      launch_ok(launch_pack(pa, ctx->stream), "pack");
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    if (err) {
+      std::vector<double> e(pop->nslots), in(pop->P);
+      HIPCHK(hipMemcpy(e.data(), pop->E, sizeof(double) * pop->nslots, hipMemcpyDeviceToHost));
+      if (dev) HIPCHK(hipMemcpy(in.data(), err, sizeof(double) * pop->P, hipMemcpyDeviceToHost));
+      else std::memcpy(in.data(), err, sizeof(double) * pop->P);
+      for (int p = 0; p < pop->P; ++p) e[tbl[base + p]] = in[p];
+      HIPCHK(hipMemcpy(pop->E, e.data(), sizeof(double) * pop->nslots, hipMemcpyHostToDevice));
+    }
+  });
+}
+
+spr_status spr_sched_create(spr_ctx* ctx, const spr_op* ops, int32_t nops, spr_sched** out) {
+  if (!out || (nops > 0 && !ops) || nops < 0) return SPR_E_INVALID_ARG;
+  *out = nullptr;
+  return guarded(ctx, [&] {
+    spr_sched* s = new spr_sched();
+    s->ops.assign(ops, ops + nops);
+    try {
+      for (const auto& o : s->ops) validate_op(o);
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    *out = s;
+  });
+}
+
+spr_status spr_sched_plain(spr_ctx* ctx, const spr_plain_params* prm, spr_sched** out) {
+  if (!prm || !out) return SPR_E_INVALID_ARG;
+  *out = nullptr;
+  return guarded(ctx, [&] {
+    if (prm->G < 1 || prm->j < 0 || prm->j_er < 0 || prm->j_end < 0) fail(SPR_E_INVALID_ARG, "bad plain schedule counts");
+    if (prm->alg != SPR_ALG_HIO && prm->alg != SPR_ALG_RAAR) fail(SPR_E_INVALID_ARG, "alg must be HIO or RAAR");
+    spr_sched* s = new spr_sched();
+    for (int g = 1; g <= prm->G; ++g) {
+      int jg, jer;
+      double sg, tg;
+      sched_at(g, prm->G, prm->j, prm->j_er, prm->j_end, prm->sigma, prm->sigma_end, prm->tau, prm->tau_end,
+               jg, jer, sg, tg);
+      push_seq(s->ops, prm->alg, jg, jer, prm->beta, prm->chi);
+      spr_op sw = make_op(SPR_OP_SHRINKWRAP);
+      sw.sigma = sg;
+      sw.tau = tg;
+      s->ops.push_back(sw);
+    }
+    s->ops.push_back(make_op(SPR_OP_GET_ERROR));
+    try {
+      for (const auto& o : s->ops) validate_op(o);
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    *out = s;
+  });
+}
+
+spr_status spr_sched_mpr(spr_ctx* ctx, const spr_mpr_params* prm, spr_sched** out) {
+  if (!prm || !out) return SPR_E_INVALID_ARG;
+  *out = nullptr;
+  return guarded(ctx, [&] {
+    if (prm->G < 1 || prm->R < 2 || prm->j < 0 || prm->j_er < 0 || prm->j_end < 0 || prm->j_eval < 0)
+      fail(SPR_E_INVALID_ARG, "bad MPR schedule counts");
+    if (prm->alg != SPR_ALG_HIO && prm->alg != SPR_ALG_RAAR) fail(SPR_E_INVALID_ARG, "alg must be HIO or RAAR");
+    const int g0 = prm->gen_first > 0 ? prm->gen_first : 1;
+    const int g1 = prm->gen_count > 0 ? g0 + prm->gen_count - 1 : prm->G;
+    spr_sched* s = new spr_sched();
+    auto& ops = s->ops;
+    if (prm->init_error) {
+      spr_op e = make_op(SPR_OP_GET_ERROR);
+      e.scope = SPR_SCOPE_PARENTS;
+      ops.push_back(e);
+    }
+    for (int g = g0; g <= g1; ++g) {
+      spr_op x = make_op(SPR_OP_CROSSOVER);
+      x.gen = g;
+      x.c_p = prm->c_p;
+      x.c_w = prm->c_w;
+      x.t_min = prm->t_min;
+      x.t_max = prm->t_max;
+      ops.push_back(x);
+      spr_op st = make_op(SPR_OP_STATS);
+      st.gen = g;
+      st.gens = prm->G;
+      ops.push_back(st);
+      int jg, jer;
+      double sg, tg;
+      sched_at(g, prm->G, prm->j, prm->j_er, prm->j_end, prm->sigma, prm->sigma_end, prm->tau, prm->tau_end,
+               jg, jer, sg, tg);
+      spr_op sw = make_op(SPR_OP_SHRINKWRAP);
+      sw.sigma = sg;
+      sw.tau = tg;
+      for (int r = 0; r < prm->R - 2; ++r) {
+        push_seq(ops, prm->alg, jg, jer, prm->beta, prm->chi);
+        ops.push_back(sw);
+      }
+      push_seq(ops, prm->alg, jg, jer, prm->beta, prm->chi);
+      spr_op ab = make_op(SPR_OP_SUPPORT_AREA);
+      ab.sigma = sg;
+      ab.which = SPR_AREA_BEST;
+      ops.push_back(ab);
+      push_seq(ops, prm->alg, jg, jer, prm->beta, prm->chi);
+      spr_op ae = ab;
+      ae.which = SPR_AREA_EVAL;
+      ops.push_back(ae);
+      push_seq(ops, prm->alg, 0, prm->j_eval, prm->beta, prm->chi);
+      ops.push_back(make_op(SPR_OP_GET_ERROR));
+      ops.push_back(sw);
+      spr_op se = make_op(SPR_OP_SELECT);
+      se.gen = g;
+      ops.push_back(se);
+    }
+    for (auto& o : ops)
+      if (o.kind == SPR_OP_ER || o.kind == SPR_OP_HIO || o.kind == SPR_OP_RAAR) o.chi = prm->chi;
+    try {
+      for (const auto& o : ops) validate_op(o);
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    *out = s;
+  });
+}
+
+spr_status spr_sched_destroy(spr_sched* sched) {
+  if (!sched) return SPR_E_INVALID_ARG;
+  delete sched;
+  return SPR_OK;
+}
+
+spr_status spr_sched_ops(const spr_sched* sched, spr_op* ops, int32_t max_ops, int32_t* n_ops) {
+  if (!sched || !n_ops) return SPR_E_INVALID_ARG;
+  *n_ops = (int32_t)sched->ops.size();
+  if (ops) {
+    const int32_t k = std::min<int32_t>(max_ops, *n_ops);
+    for (int32_t i = 0; i < k; ++i) ops[i] = sched->ops[i];
+  }
+  return SPR_OK;
+}
+
+spr_status spr_run(spr_pop* pop, const spr_sched* sched, void* hip_stream) {
+  if (!pop || !sched) return SPR_E_INVALID_ARG;
+  spr_ctx* ctx = pop->ctx;
+  return guarded(ctx, [&] {
+    use_device(ctx);
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    if (pop->last && pop->last != s) {
+      // order after work previously enqueued on another stream
+      hipEvent_t ev;
+      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(ev, pop->last));
+      HIPCHK(hipStreamWaitEvent(s, ev, 0));
+      HIPCHK(hipEventDestroy(ev));
+    }
+    pop->last = s;
+    run_schedule(pop, sched, s);
+  });
+}
+
+spr_status spr_sync(spr_pop* pop) {
+  if (!pop) return SPR_E_INVALID_ARG;
+  spr_ctx* ctx = pop->ctx;
+  return guarded(ctx, [&] {
+    use_device(ctx);
+    sync_pop(pop);
+    int f = 0;
+    HIPCHK(hipMemcpy(&f, pop->flags, sizeof(int), hipMemcpyDeviceToHost));
+    if (f & 1) fail(SPR_E_NUMERIC, "a fitness value is not finite");
+  });
+}
+
+spr_status spr_read(spr_pop* pop, float* rho, uint8_t* supp, double* err, uint32_t flags) {
+  if (!pop) return SPR_E_INVALID_ARG;
+  spr_ctx* ctx = pop->ctx;
+  return guarded(ctx, [&] {
+    use_device(ctx);
+    sync_pop(pop);
+    const bool kids = flags & SPR_READ_CHILDREN;
+    if (kids) need_memetic(pop, "reading children");
+    const bool dev = flags & SPR_DEVICE_PTRS;
+    const size_t nn = (size_t)pop->n * pop->n;
+    std::vector<int> tbl = host_table(pop);
+    const int base = kids ? pop->P : 0;
+    if (rho) {
+      for (int p = 0; p < pop->P; ++p)
+        HIPCHK(hipMemcpy(rho + (size_t)p * nn * 2, pop->X + (size_t)tbl[base + p] * nn, nn * sizeof(float2),
+                         dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    }
+    if (supp) {
+      uint8_t* st = stage(pop, (size_t)pop->P * nn);
+      PackArgs pa{pop->table + base, pop->P, pop->n, pop->W, 0, st, pop->S};
+      launch_ok(launch_unpack(pa, ctx->stream), "unpack");
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      HIPCHK(hipMemcpy(supp, st, (size_t)pop->P * nn, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    }
+    if (err) {
+      std::vector<double> e(pop->nslots), o(pop->P);
+      HIPCHK(hipMemcpy(e.data(), pop->E, sizeof(double) * pop->nslots, hipMemcpyDeviceToHost));
+      for (int p = 0; p < pop->P; ++p) o[p] = e[tbl[base + p]];
+      if (dev) HIPCHK(hipMemcpy(err, o.data(), sizeof(double) * pop->P, hipMemcpyHostToDevice));
+      else std::memcpy(err, o.data(), sizeof(double) * pop->P);
+    }
+  });
+}
+
+spr_status spr_read_stats(spr_pop* pop, spr_gen_stats* out, int32_t max_n, int32_t* n_out) {
+  if (!pop || !n_out || (max_n > 0 && !out)) return SPR_E_INVALID_ARG;
+  spr_ctx* ctx = pop->ctx;
+  return guarded(ctx, [&] {
+    use_device(ctx);
+    sync_pop(pop);
+    std::vector<GenStatsDev> h(pop->hist_cap);
+    HIPCHK(hipMemcpy(h.data(), pop->hist, sizeof(GenStatsDev) * pop->hist_cap, hipMemcpyDeviceToHost));
+    std::vector<GenStatsDev> used;
+    for (auto& r : h)
+      if (r.gen > 0) used.push_back(r);
+    std::sort(used.begin(), used.end(), [](const GenStatsDev& a, const GenStatsDev& b) { return a.gen < b.gen; });
+    int32_t k = 0;
+    for (auto& r : used) {
+      if (k >= max_n) break;
+      spr_gen_stats o;
+      o.gen = r.gen;
+      o.best = r.best;
+      o.alpha_best = r.alpha_best;
+      o.alpha_all = r.alpha_all;
+      o.alpha_eval = r.alpha_eval;
+      o.err_best = r.err_best;
+      o.err_mean = r.err_mean;
+      o.err_worst = r.err_worst;
+      o.replaced = r.replaced;
+      o.pad = 0;
+      out[k++] = o;
+    }
+    *n_out = k;
+  });
+}
+
+spr_status spr_read_xover(spr_pop* pop, spr_xover_info* out, int32_t max_n) {
+  if (!pop || !out) return SPR_E_INVALID_ARG;
+  spr_ctx* ctx = pop->ctx;
+  return guarded(ctx, [&] {
+    use_device(ctx);
+    if (!pop->abc) fail(SPR_E_INVALID_ARG, "no crossover has run on this population");
+    sync_pop(pop);
+    const int P = pop->P;
+    std::vector<int> abc(3 * P), mp(5 * P);
+    std::vector<AlignRec> al(3 * P);
+    HIPCHK(hipMemcpy(abc.data(), pop->abc, sizeof(int) * 3 * P, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(mp.data(), pop->mapprm, sizeof(int) * 5 * P, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(al.data(), pop->align, sizeof(AlignRec) * 3 * P, hipMemcpyDeviceToHost));
+    for (int p = 0; p < std::min(P, max_n); ++p) {
+      spr_xover_info& o = out[p];
+      o.a = abc[3 * p];
+      o.b = abc[3 * p + 1];
+      o.c = abc[3 * p + 2];
+      o.tx = mp[5 * p];
+      o.ty = mp[5 * p + 1];
+      o.sx = mp[5 * p + 2];
+      o.sy = mp[5 * p + 3];
+      o.rot = mp[5 * p + 4];
+      for (int k = 0; k < 3; ++k) {
+        const AlignRec& r = al[3 * p + k];
+        o.dr[k] = r.dr;
+        o.dc[k] = r.dc;
+        o.twin[k] = r.twin;
+        o.phase[k][0] = r.pr;
+        o.phase[k][1] = r.pi;
+        o.peak[k][0] = r.peak1;
+        o.peak[k][1] = r.peak2;
+      }
+    }
+  });
+}
+
+spr_status spr_timing_enable(spr_pop* pop, int32_t enable) {
+  if (!pop) return SPR_E_INVALID_ARG;
+  return guarded(pop->ctx, [&] {
+    use_device(pop->ctx);
+    sync_pop(pop);
+    pop->timing = enable != 0;
+    for (int k = 0; k < SPR_KERNEL_COUNT; ++k) {
+      pop->kernel_ms[k] = 0.0;
+      pop->kernel_launches[k] = 0;
+    }
+  });
+}
+
+spr_status spr_timing_read(spr_pop* pop, int32_t kernel, int64_t* launches, double* total_ms) {
+  if (!pop || !launches || !total_ms || kernel < 0 || kernel >= SPR_KERNEL_COUNT) return SPR_E_INVALID_ARG;
+  return guarded(pop->ctx, [&] {
+    use_device(pop->ctx);
+    sync_pop(pop);
+    *launches = pop->kernel_launches[kernel];
+    *total_ms = pop->kernel_ms[kernel];
+  });
+}
+
+spr_status spr_fft2(spr_ctx* ctx, int32_t n, int32_t batch, const float* in, float* out, int32_t inverse,
+                    void* hip_stream) {
+  if (!ctx || !in || !out || batch < 0) return SPR_E_INVALID_ARG;
+  return guarded(ctx, [&] {
+    const SizeKernels* K = size_kernels(n);
+    if (!K) fail(SPR_E_UNSUPPORTED_SIZE, "unsupported size " + std::to_string(n));
+    if (batch == 0) return;
+    use_device(ctx);
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    const float2* tw = twiddles(ctx, n);
+    const int dir = inverse ? +1 : -1;
+    RowFftArgs r{nullptr, nullptr, batch, reinterpret_cast<const float2*>(in), reinterpret_cast<float2*>(out),
+                 dir, 1.f, tw};
+    launch_ok(K->row_fft(r, s), "row_fft");
+    ColFftArgs c{nullptr, nullptr, batch, reinterpret_cast<float2*>(out), reinterpret_cast<float2*>(out), dir,
+                 1.f / (float)n, tw};
+    launch_ok(K->col_fft(c, s), "col_fft");
+  });
+}
+
+}  // extern "C"

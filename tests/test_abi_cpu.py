@@ -1,0 +1,144 @@
+"""C-ABI checks that need no GPU: symbols, supported sizes, the host-side
+schedule compiler (checked against the oracle's schedule) and validation."""
+
+import os
+import re
+
+import pytest
+
+from oracle import mpr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spr.h")
+
+
+def _lib():
+    from paper_2409_07413_amd import binding
+    return binding, binding.load()
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(spr_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    binding, lib = _lib()
+    names = header_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(binding.EXPORTS)
+
+
+def test_supported_sizes():
+    _, lib = _lib()
+    for n in (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024):
+        assert lib.spr_supported_size(n) == 1
+    for n in (0, 7, 10, 20, 100, 1000, 1536, 2048, -8):
+        assert lib.spr_supported_size(n) == 0
+
+
+PLAIN = dict(alg=1, G=10, j=16, j_er=4, j_end=0, beta=0.9, chi=0.5, sigma=2.0, sigma_end=1.0,
+             tau=0.1, tau_end=0.1)
+
+
+def test_plain_schedule_matches_oracle_schedule():
+    binding, _ = _lib()
+    ops = binding.sched_plain(**PLAIN).ops()
+    exp = []
+    for g in range(1, 11):
+        jg, jer, sg, tg = mpr.schedule_at(g, 10, 16, 4, 0, 2.0, 1.0, 0.1, 0.1)
+        if jg:
+            exp.append((binding.OP_HIO, jg))
+        if jer:
+            exp.append((binding.OP_ER, jer))
+        exp.append((binding.OP_SHRINKWRAP, sg, tg))
+    exp.append((binding.OP_GET_ERROR,))
+    got = []
+    for o in ops:
+        if o.kind in (binding.OP_HIO, binding.OP_ER):
+            got.append((o.kind, o.count))
+            assert o.chi == 0.5
+        elif o.kind == binding.OP_SHRINKWRAP:
+            got.append((o.kind, o.sigma, o.tau))
+        else:
+            got.append((o.kind,))
+    assert got == exp
+
+
+MPR = dict(alg=2, G=20, R=3, j=16, j_er=4, j_end=0, j_eval=40, t_min=4, t_max=64, gen_first=1,
+           gen_count=0, init_error=1, beta=0.9, chi=0.5, sigma=2.0, sigma_end=0.5, tau=0.1,
+           tau_end=0.1 * 2 / 3, c_p=0.6, c_w=0.4)
+
+
+def test_mpr_schedule_structure_and_iteration_count():
+    binding, _ = _lib()
+    ops = binding.sched_mpr(**MPR).ops()
+    assert ops[0].kind == binding.OP_GET_ERROR and ops[0].scope == binding.SCOPE_PARENTS
+    gens = [o for o in ops if o.kind == binding.OP_CROSSOVER]
+    assert [o.gen for o in gens] == list(range(1, 21))
+    # per generation: R (j + j_ER) + j_eval = 100 iterations on every member
+    per_gen = {}
+    g = 0
+    for o in ops:
+        if o.kind == binding.OP_CROSSOVER:
+            g = o.gen
+        if o.kind in (binding.OP_ER, binding.OP_RAAR):
+            per_gen[g] = per_gen.get(g, 0) + o.count
+            assert o.scope == binding.SCOPE_ALL
+    assert all(v == 100 for v in per_gen.values()) and len(per_gen) == 20
+    # order inside a generation follows Alg. mpr / Alg. improve
+    seq = []
+    for o in ops[1:]:
+        if o.kind == binding.OP_CROSSOVER and o.gen == 2:
+            break
+        seq.append(o.kind)
+    K = binding
+    assert seq == [K.OP_CROSSOVER, K.OP_STATS, K.OP_RAAR, K.OP_ER, K.OP_SHRINKWRAP, K.OP_RAAR, K.OP_ER,
+                   K.OP_SUPPORT_AREA, K.OP_RAAR, K.OP_ER, K.OP_SUPPORT_AREA, K.OP_ER, K.OP_GET_ERROR,
+                   K.OP_SHRINKWRAP, K.OP_SELECT]
+    areas = [o.which for o in ops if o.kind == binding.OP_SUPPORT_AREA][:2]
+    assert areas == [binding.AREA_BEST, binding.AREA_EVAL]
+    # linear schedules agree with the oracle at every generation
+    g = 0
+    for o in ops:
+        if o.kind == binding.OP_CROSSOVER:
+            g = o.gen
+            jg, jer, sg, tg = mpr.schedule_at(g, 20, 16, 4, 0, 2.0, 0.5, 0.1, 0.1 * 2 / 3)
+        if o.kind == binding.OP_RAAR:
+            assert o.count == jg and abs(o.beta - 0.9) < 1e-15
+        if o.kind == binding.OP_SHRINKWRAP:
+            assert o.sigma == sg and o.tau == tg
+    stats = [o for o in ops if o.kind == binding.OP_STATS]
+    assert all(o.gens == 20 for o in stats)
+
+
+def test_mpr_schedule_resume_window():
+    binding, _ = _lib()
+    ops = binding.sched_mpr(**dict(MPR, gen_first=7, gen_count=3, init_error=0)).ops()
+    assert [o.gen for o in ops if o.kind == binding.OP_CROSSOVER] == [7, 8, 9]
+    assert ops[0].kind == binding.OP_CROSSOVER
+
+
+@pytest.mark.parametrize("bad", [dict(G=0), dict(R=1), dict(alg=3), dict(j=-1)])
+def test_mpr_schedule_validation(bad):
+    binding, _ = _lib()
+    with pytest.raises(binding.SprError) as e:
+        binding.sched_mpr(**dict(MPR, **bad))
+    assert e.value.code == -1
+
+
+def test_op_validation():
+    binding, _ = _lib()
+    for o in (binding.op(binding.OP_HIO, count=3, beta=1.5),
+              binding.op(binding.OP_SHRINKWRAP, sigma=9.0, tau=0.1),
+              binding.op(binding.OP_SHRINKWRAP, sigma=1.0, tau=2.0),
+              binding.op(binding.OP_STATS, gen=0, gens=10),
+              binding.op(99),
+              binding.op(binding.OP_ER, count=1, scope=5)):
+        with pytest.raises(binding.SprError):
+            binding.sched_ops([o])
+    s = binding.sched_ops([binding.op(binding.OP_ER, count=2), binding.op(binding.OP_GET_ERROR)])
+    assert [o.kind for o in s.ops()] == [binding.OP_ER, binding.OP_GET_ERROR]
