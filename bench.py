@@ -123,7 +123,9 @@ def main():
     total = args.warmup + args.steps
     G = max(G_SCHEDULE, total)
     scheds = [B.sched_mpr(ctx, **mpr_params(g, G, g == 1)) for g in range(1, total + 1)]
-    stream = torch.cuda.current_stream()
+    # a dedicated stream (default priority): its handle is non-null, so the
+    # library's kernels and the timing events below share it
+    stream = torch.cuda.Stream()
 
     for i in range(args.warmup):
         pop.run(scheds[i], stream)

@@ -117,9 +117,19 @@ def _proto(lib):
 
 
 def load():
-    """Load libspr.so (raises if it has not been built)."""
+    """Load libspr.so (raises if it has not been built).
+
+    A process must hold one HIP runtime.  PyTorch ships its own libamdhip64
+    with the same soname as the system one; importing torch first makes
+    libspr.so bind to that copy, so torch streams and device pointers are valid
+    in the library.  Without torch the system runtime is used.
+    """
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401  (loads the process-wide HIP runtime first)
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
                                "(run python -m paper_2409_07413_amd.build)")
@@ -225,14 +235,25 @@ class Context:
         return sched_mpr(self, **kw)
 
     def fft2(self, x_in, x_out, inverse=False, stream=None):
-        """Unitary 2D DFT of a batch of N x N complex64 device tensors."""
+        """Unitary 2D DFT of a batch of N x N complex64 device tensors.
+
+        With stream=None the call is ordered with torch's work by device-wide
+        synchronisation before and after (torch's default stream has the null
+        handle, which the library reads as its own context stream).
+        """
         n = x_in.shape[-1]
         batch = x_in.numel() // (n * n)
         pi, di = _ptr(x_in)
         po, do = _ptr(x_out)
         if not (di and do):
             raise ValueError("fft2 takes device tensors")
-        self._check(self.lib.spr_fft2(self.h, n, batch, pi, po, 1 if inverse else 0, _stream_ptr(stream)))
+        sp = _stream_ptr(stream)
+        if not sp:
+            import torch
+            torch.cuda.synchronize()
+        self._check(self.lib.spr_fft2(self.h, n, batch, pi, po, 1 if inverse else 0, sp))
+        if not sp:
+            torch.cuda.synchronize()
 
 
 class Shot:

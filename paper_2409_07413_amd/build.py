@@ -22,6 +22,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # code object v5 loads under every ROCm 7.x runtime, including the one PyTorch ships
+    "-mcode-object-version=5",
     # keep the compiler from emitting packed-FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", CSRC, "-I", os.path.join(ROOT, "include"),

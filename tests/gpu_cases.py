@@ -46,3 +46,40 @@ class Case:
         sh = self.shot(ctx)
         pop = sh.population(self.rho32, self.supp8, memetic=memetic, seed=seed)
         return sh, pop
+
+
+def perturbed(x, rng, eps=1e-7):
+    """x plus complex Gaussian noise of size eps * max|x| (FP32 rounding scale)."""
+    return x + eps * np.abs(x).max() * (rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape))
+
+
+def self_sensitivity(fn, x, seed=0, eps=1e-7):
+    """Relative change of the FP64 oracle map fn under an FP32-rounding-size
+    perturbation of its input: how far any FP32 evaluation can legitimately be
+    from the FP64 trajectory."""
+    rng = np.random.default_rng(seed)
+    return rel(fn(perturbed(x, rng, eps)), fn(x))
+
+
+class NearSolutionCase(Case):
+    """Noiseless clustered-sphere pattern, support from the smoothed object and
+    a start 5% away from the true density: the regime in which the projection
+    iterations are well conditioned."""
+
+    def __init__(self, n, P, seed=1):
+        kw = dict(count=12, radius=(0.012 * n, 0.047 * n), spread=0.06 * n, extent=0.3 * n)
+        sh = synth.shot(n, "spheres", seed, 1e8, beamstop=max(2, n // 21), gap=4, noiseless=True, **kw)
+        self.n, self.P = n, P
+        self.amp32 = sh["amp"].astype(np.float32)
+        self.mask8 = sh["mask"].astype(np.uint8)
+        self.M = mpr.to_fft_order(self.amp32.astype(np.float64))
+        self.known = mpr.to_fft_order(sh["mask"])
+        xt = sh["obj"] * sh["scale"]
+        self.obj = xt
+        S = mpr.smooth(xt, 2.0) > 0.01 * xt.max()
+        rng = np.random.default_rng(seed + 1)
+        xs = [xt + 0.05 * xt.max() * rng.standard_normal(xt.shape) * S for _ in range(P)]
+        self.rho32 = np.stack(xs).astype(np.complex64)
+        self.rho = self.rho32.astype(np.complex128)
+        self.S = np.stack([S] * P)
+        self.supp8 = self.S.astype(np.uint8)
