@@ -19,6 +19,11 @@ LIB = os.path.join(HERE, "libspr.so")
 SIZES = (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024)
 ARCH = os.environ.get("SPR_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# extra compile definitions and an alternative output path (tuning builds)
+EXTRA = os.environ.get("SPR_EXTRA_FLAGS", "").split()
+if os.environ.get("SPR_LIB_OUT"):
+    LIB = os.environ["SPR_LIB_OUT"]
+    OBJ = LIB + ".objs"
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -42,7 +47,7 @@ def _jobs():
 
 def _compile(job):
     src, obj, extra = job
-    cmd = [HIPCC] + FLAGS + extra + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA + extra + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

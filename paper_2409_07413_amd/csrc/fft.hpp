@@ -65,7 +65,7 @@ SPR_DEFINE_PLAN(128, 8, 16, 2, 8, 8)
 SPR_DEFINE_PLAN(192, 24, 16, 3, 8, 8)
 SPR_DEFINE_PLAN(256, 8, 16, 4, 8, 8)
 SPR_DEFINE_PLAN(384, 24, 16, 3, 2, 8, 8)
-SPR_DEFINE_PLAN(512, 8, 16, 8, 8, 8)
+SPR_DEFINE_PLAN(512, 8, 8, 8, 8, 8)
 SPR_DEFINE_PLAN(768, 24, 8, 3, 4, 8, 8)
 SPR_DEFINE_PLAN(1024, 16, 8, 16, 8, 8)
 
@@ -167,13 +167,112 @@ template <int DIR> __device__ __forceinline__ float2 twiddle(const float2* __res
   return DIR < 0 ? w : cconj(w);
 }
 
-// Barrier among the threads that share the exchange buffer.
-__device__ __forceinline__ void lds_sync() { __syncthreads(); }
+#ifndef SPR_TW_MODE
+#define SPR_TW_MODE 1
+#endif
 
-// One Stockham pass (and, recursively, the following ones).
-template <int N, int DIR, int PASS, int NS, int ES>
+// Twiddles w[r] = exp(DIR 2 pi i r b / N), r = 1..R-1.  Mode 1 loads the
+// power-of-two multiples (b, 2b, 4b, 8b) and forms the others as products of
+// two or three table values (a few ulp), cutting the table loads from R-1 to
+// log2 R for the power-of-two radices.
+template <int R, int DIR>
+__device__ __forceinline__ void twiddles_for(const float2* __restrict__ tw, int b, float2* w) {
+  if constexpr (SPR_TW_MODE == 0 || R <= 3) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) w[r] = twiddle<DIR>(tw, r * b);
+  } else {
+    w[1] = twiddle<DIR>(tw, b);
+    w[2] = twiddle<DIR>(tw, 2 * b);
+    w[3] = cmul(w[1], w[2]);
+    if constexpr (R >= 8) {
+      w[4] = twiddle<DIR>(tw, 4 * b);
+      w[5] = cmul(w[1], w[4]);
+      w[6] = cmul(w[2], w[4]);
+      w[7] = cmul(w[3], w[4]);
+    }
+    if constexpr (R >= 16) {
+      w[8] = twiddle<DIR>(tw, 8 * b);
+#pragma unroll
+      for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
+    }
+  }
+}
+
+// LDS addressing of one transform: element position `pos` lives at
+// (pos + pos / PAD) * ES (PAD = 0: no padding).  WAVE = true when every
+// transform sharing the buffer is held by a single wavefront, so exchanges
+// need only wavefront-scope ordering, not a workgroup barrier.
+template <int ES_, int PAD_, bool WAVE_> struct Lds {
+  static constexpr int ES = ES_;
+  static constexpr int PAD = PAD_;
+  static constexpr bool WAVE = WAVE_;
+  __device__ static __forceinline__ int at(int pos) { return (PAD ? pos + pos / PAD : pos) * ES; }
+  __host__ __device__ static constexpr int span(int n) { return PAD ? n + n / PAD : n; }
+};
+
+template <bool WAVE> __device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    // LDS operations of one wavefront complete in order; the fences keep the
+    // compiler from moving LDS accesses across the exchange point
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Per-thread twiddle set: the twiddles of every pass after the first, for the
+// butterflies of thread t, in the forward direction.  A kernel that runs
+// several transforms (inverse ones use the conjugates) loads them once.
+template <int N, int PASS> __host__ __device__ constexpr int tw_offset() {
+  using P = Plan<N>;
+  int off = 0;
+  for (int p = 1; p < PASS && p < P::passes(); ++p) off += (P::E / P::radix(p)) * (P::radix(p) - 1);
+  return off;
+}
+template <int N> __host__ __device__ constexpr int tw_count() { return tw_offset<N, 64>(); }
+// keep the set in registers only when it is small
+#ifndef SPR_TWSET
+#define SPR_TWSET 1
+#endif
+template <int N> constexpr bool tw_in_regs() {
+  return SPR_TWSET && tw_count<N>() > 0 && tw_count<N>() <= 16;
+}
+
+template <int N> struct TwSet {
+  float2 w[tw_count<N>() > 0 ? tw_count<N>() : 1];
+};
+
+template <int N, int PASS, int NS>
+__device__ __forceinline__ void fill_tw(TwSet<N>& s, int t, const float2* __restrict__ tw) {
+  using P = Plan<N>;
+  if constexpr (PASS < P::passes()) {
+    constexpr int R = P::radix(PASS), NB = P::E / R, T = P::T;
+    if constexpr (PASS > 0) {
+      constexpr int step = N / (NS * R);
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        float2 w[R];
+        twiddles_for<R, -1>(tw, ((t + k * T) % NS) * step, w);
+#pragma unroll
+        for (int r = 1; r < R; ++r) s.w[tw_offset<N, PASS>() + k * (R - 1) + r - 1] = w[r];
+      }
+    }
+    fill_tw<N, PASS + 1, NS * R>(s, t, tw);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void load_twiddle_set(TwSet<N>& s, int t, const float2* __restrict__ tw) {
+  if constexpr (tw_in_regs<N>()) fill_tw<N, 0, 1>(s, t, tw);
+}
+
+// One Stockham pass (and, recursively, the following ones).  With a twiddle
+// set (PRE) the pass takes its twiddles from registers.
+template <int N, int DIR, int PASS, int NS, class L, bool PRE = false>
 __device__ __forceinline__ void fft_passes(float2 (&v)[Plan<N>::E], float2* lds, int t,
-                                           const float2* __restrict__ tw) {
+                                           const float2* __restrict__ tw, const TwSet<N>* ws = nullptr) {
   using P = Plan<N>;
   if constexpr (PASS < P::passes()) {
     constexpr int R = P::radix(PASS);
@@ -188,10 +287,19 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[Plan<N>::E], float2* lds,
 #pragma unroll
       for (int r = 0; r < R; ++r) a[r] = v[k + r * NB];
       if constexpr (NS > 1) {
-        const int jm = j % NS;
-        constexpr int step = N / (NS * R);
+        if constexpr (PRE) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) a[r] = cmul(a[r], twiddle<DIR>(tw, jm * r * step));
+          for (int r = 1; r < R; ++r) {
+            const float2 w = ws->w[tw_offset<N, PASS>() + k * (R - 1) + r - 1];
+            a[r] = cmul(a[r], DIR < 0 ? w : cconj(w));
+          }
+        } else {
+          constexpr int step = N / (NS * R);
+          float2 w[R];
+          twiddles_for<R, DIR>(tw, (j % NS) * step, w);
+#pragma unroll
+          for (int r = 1; r < R; ++r) a[r] = cmul(a[r], w[r]);
+        }
       }
       butterfly<R, DIR>(a);
       if constexpr (LAST) {
@@ -200,25 +308,34 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[Plan<N>::E], float2* lds,
       } else {
         const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[(base + r * NS) * ES] = a[r];
+        for (int r = 0; r < R; ++r) lds[L::at(base + r * NS)] = a[r];
       }
     }
     if constexpr (!LAST) {
-      lds_sync();
+      lds_sync<L::WAVE>();
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = lds[(t + T * m) * ES];
-      lds_sync();
-      fft_passes<N, DIR, PASS + 1, NS * R, ES>(v, lds, t, tw);
+      for (int m = 0; m < E; ++m) v[m] = lds[L::at(t + T * m)];
+      lds_sync<L::WAVE>();
+      fft_passes<N, DIR, PASS + 1, NS * R, L, PRE>(v, lds, t, tw, ws);
     }
   }
 }
 
 // Transform the E register elements of thread t (positions t + T*m).
-// Every thread of the workgroup must call this (it contains barriers).
-template <int N, int DIR, int ES>
+// Every thread sharing the buffer must call this (it contains barriers).
+template <int N, int DIR, class L>
 __device__ __forceinline__ void fft(float2 (&v)[Plan<N>::E], float2* lds, int t,
                                     const float2* __restrict__ tw) {
-  fft_passes<N, DIR, 0, 1, ES>(v, lds, t, tw);
+  fft_passes<N, DIR, 0, 1, L>(v, lds, t, tw);
+}
+
+// Same, with the thread's twiddle set from load_twiddle_set (used when the set
+// fits in registers, otherwise twiddles are formed per pass).
+template <int N, int DIR, class L>
+__device__ __forceinline__ void fft(float2 (&v)[Plan<N>::E], float2* lds, int t,
+                                    const float2* __restrict__ tw, const TwSet<N>& ws) {
+  if constexpr (tw_in_regs<N>()) fft_passes<N, DIR, 0, 1, L, true>(v, lds, t, tw, &ws);
+  else fft_passes<N, DIR, 0, 1, L>(v, lds, t, tw);
 }
 
 }  // namespace spr

@@ -27,9 +27,26 @@ constexpr int N = SPR_N;
 using PL = Plan<N>;
 constexpr int E = PL::E;
 constexpr int T = PL::T;
+#if defined(SPR_COLS)
+constexpr int C = (N % SPR_COLS == 0) ? SPR_COLS : PL::C;
+#else
 constexpr int C = PL::C;
+#endif
 constexpr int RW = PL::RW;
 constexpr size_t NN = (size_t)N * N;
+
+#ifndef SPR_ROW_PAD
+#define SPR_ROW_PAD 8
+#endif
+#ifndef SPR_ROW_WAVE
+#define SPR_ROW_WAVE 1
+#endif
+// Row transforms: one row per T lanes (T divides 64, so a row never spans two
+// wavefronts); the column tile interleaves C transforms across the workgroup.
+static_assert(64 % T == 0, "row transforms must not straddle wavefronts");
+using RowL = Lds<1, SPR_ROW_PAD, SPR_ROW_WAVE != 0>;
+using ColL = Lds<C, 0, false>;
+constexpr int NR = RowL::span(N);  // LDS elements per row
 static_assert(N % C == 0, "column tile must divide N");
 
 // rows per workgroup for kernels whose workgroups must not straddle images
@@ -59,6 +76,25 @@ __device__ __forceinline__ bool inside_phase(float2 z, const Phase& ph) {
   if (ph.mode == PHASE_OFF) return true;
   if (ph.mode == PHASE_POS) return z.x >= 0.f;
   return fabsf(z.y) * ph.c <= z.x * ph.s;
+}
+
+// Column-tile placement.  Workgroups go to the 8 XCDs round-robin by linear
+// id, and each XCD has its own L2.  A tile of C columns reads 8C bytes of every
+// 128-byte line, so G = 128 / 8C neighbouring tiles share lines; they are given
+// to workgroups lin, lin+8, ..., which run back to back on one XCD, so each
+// line is fetched from HBM once.  Grid: (N/C tiles, images).
+struct TileId {
+  int tile, img;
+};
+__device__ __forceinline__ TileId col_tile_id() {
+  constexpr int ntiles = N / C;
+  constexpr int G = (8 * C >= 128) ? 1 : 128 / (8 * C);
+  const int total = ntiles * (int)gridDim.y;
+  if (G == 1 || ntiles % G != 0 || total % (8 * G) != 0) return {(int)blockIdx.x, (int)blockIdx.y};
+  const int lin = blockIdx.x + blockIdx.y * ntiles;
+  const int x = lin & 7, h = (lin >> 3) % G, q = lin / (8 * G);
+  const int ltile = (8 * q + x) * G + h;
+  return {ltile % ntiles, ltile / ntiles};
 }
 
 // Masked modulus replacement on one unitary Fourier value (Eq. pm_full):
@@ -97,7 +133,7 @@ __global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
     }
     v[m] = z;
   }
-  fft<N, -1, 1>(v, lds + r * N, t, a.tw);
+  fft<N, -1, RowL>(v, lds + r * NR, t, a.tw);
   if (valid) {
 #pragma unroll
     for (int m = 0; m < E; ++m) a.T[off + t + T * m] = v[m];
@@ -111,22 +147,27 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const int c = tid % C, t = tid / C;
-  const int col = blockIdx.x * C + c;
-  const int slot = a.slots[blockIdx.y];
+  const TileId id = col_tile_id();
+  const int col = id.tile * C + c;
+  const int slot = a.slots[id.img];
   const float2* src = a.T + (size_t)slot * NN;
   float2* dst = a.Y + (size_t)slot * NN;
   float2 v[E];
+  float mv[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = src[(size_t)(t + T * m) * N + col];
-  fft<N, -1, C>(v, lds + c, t, a.tw);
+#pragma unroll
+  for (int m = 0; m < E; ++m) mv[m] = a.amp[(size_t)(t + T * m) * N + col];
+  TwSet<N> ws;
+  load_twiddle_set<N>(ws, t, a.tw);
+  fft<N, -1, ColL>(v, lds + c, t, a.tw, ws);
   const float inv = 1.0f / (float)N;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    const int e = t + T * m;
     const float2 X = cscale(v[m], inv);  // unitary spectrum
-    v[m] = cscale(modulus_replace(X, a.amp[(size_t)e * N + col], a.amp_scale), inv);
+    v[m] = cscale(modulus_replace(X, mv[m], a.amp_scale), inv);
   }
-  fft<N, +1, C>(v, lds + c, t, a.tw);
+  fft<N, +1, ColL>(v, lds + c, t, a.tw, ws);
 #pragma unroll
   for (int m = 0; m < E; ++m) dst[(size_t)(t + T * m) * N + col] = v[m];
 }
@@ -146,22 +187,26 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   const int slot = a.slots[member];
   const size_t off = (size_t)slot * NN + (size_t)row * N;
   const uint32_t* Sm = a.S + (size_t)slot * a.W;
-  float2* l = lds + r * N;
+  float2* l = lds + r * NR;
 
-  float2 y[E];
+  const bool ia = a.alg != ALG_ER;
+  float2 y[E], x[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) y[m] = valid ? a.Y[off + t + T * m] : make_float2(0.f, 0.f);
-  fft<N, +1, 1>(y, l, t, a.tw);  // y = P_M x (real space)
+  if (ia) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) x[m] = valid ? a.T[off + t + T * m] : make_float2(0.f, 0.f);
+  }
+  TwSet<N> ws;
+  load_twiddle_set<N>(ws, t, a.tw);
+  fft<N, +1, RowL>(y, l, t, a.tw, ws);  // y = P_M x (real space)
 
   float2 xn[E];
-  if (a.alg == ALG_ER) {
+  if (!ia) {
 #pragma unroll
     for (int m = 0; m < E; ++m) xn[m] = y[m];
   } else {
-    float2 x[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) x[m] = valid ? a.T[off + t + T * m] : make_float2(0.f, 0.f);
-    fft<N, +1, 1>(x, l, t, a.tw);
+    fft<N, +1, RowL>(x, l, t, a.tw, ws);
     const float inv = 1.0f / (float)N;
     const float beta = a.beta;
 #pragma unroll
@@ -195,7 +240,7 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
       xn[m] = s ? proj_phase(xn[m], a.ph_next) : make_float2(0.f, 0.f);
     }
   }
-  fft<N, -1, 1>(xn, l, t, a.tw);
+  fft<N, -1, RowL>(xn, l, t, a.tw, ws);
   if (valid) {
 #pragma unroll
     for (int m = 0; m < E; ++m) a.T[off + t + T * m] = xn[m];
@@ -216,19 +261,22 @@ __global__ __launch_bounds__(C* T) void k_col_err(ColErrArgs a) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const int c = tid % C, t = tid / C;
-  const int col = blockIdx.x * C + c;
-  const int slot = a.slots[blockIdx.y];
+  const TileId id = col_tile_id();
+  const int col = id.tile * C + c;
+  const int slot = a.slots[id.img];
   const float2* src = a.T + (size_t)slot * NN;
   float2 v[E];
+  float mv[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = src[(size_t)(t + T * m) * N + col];
-  fft<N, -1, C>(v, lds + c, t, a.tw);
+#pragma unroll
+  for (int m = 0; m < E; ++m) mv[m] = a.amp[(size_t)(t + T * m) * N + col];
+  fft<N, -1, ColL>(v, lds + c, t, a.tw);
   const float inv = 1.0f / (float)N;
   double acc = 0.0;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    const int e = t + T * m;
-    const float stored = a.amp[(size_t)e * N + col];
+    const float stored = mv[m];
     if (!signbit(stored)) {
       const float2 X = cscale(v[m], inv);
       const double d = (double)sqrtf(X.x * X.x + X.y * X.y) - (double)(stored * a.amp_scale);
@@ -243,7 +291,7 @@ __global__ __launch_bounds__(C* T) void k_col_err(ColErrArgs a) {
   if (tid == 0) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += wsum[w];
-    a.partial[(size_t)blockIdx.y * (N / C) + blockIdx.x] = s;
+    a.partial[(size_t)id.img * (N / C) + id.tile] = s;
   }
 }
 
@@ -265,8 +313,8 @@ __global__ __launch_bounds__(RW* T) void k_row_fft(RowFftArgs a) {
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = valid ? a.in[offi + t + T * m] : make_float2(0.f, 0.f);
-  if (a.dir < 0) fft<N, -1, 1>(v, lds + r * N, t, a.tw);
-  else fft<N, +1, 1>(v, lds + r * N, t, a.tw);
+  if (a.dir < 0) fft<N, -1, RowL>(v, lds + r * NR, t, a.tw);
+  else fft<N, +1, RowL>(v, lds + r * NR, t, a.tw);
   if (valid) {
 #pragma unroll
     for (int m = 0; m < E; ++m) a.out[offo + t + T * m] = cscale(v[m], a.scale);
@@ -277,8 +325,9 @@ __global__ __launch_bounds__(C* T) void k_col_fft(ColFftArgs a) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const int c = tid % C, t = tid / C;
-  const int col = blockIdx.x * C + c;
-  const int member = blockIdx.y;
+  const TileId id = col_tile_id();
+  const int col = id.tile * C + c;
+  const int member = id.img;
   const int si = a.slots_in ? a.slots_in[member] : member;
   const int so = a.slots_out ? a.slots_out[member] : member;
   const float2* src = a.in + (size_t)si * NN;
@@ -286,8 +335,8 @@ __global__ __launch_bounds__(C* T) void k_col_fft(ColFftArgs a) {
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = src[(size_t)(t + T * m) * N + col];
-  if (a.dir < 0) fft<N, -1, C>(v, lds + c, t, a.tw);
-  else fft<N, +1, C>(v, lds + c, t, a.tw);
+  if (a.dir < 0) fft<N, -1, ColL>(v, lds + c, t, a.tw);
+  else fft<N, +1, ColL>(v, lds + c, t, a.tw);
 #pragma unroll
   for (int m = 0; m < E; ++m) dst[(size_t)(t + T * m) * N + col] = cscale(v[m], a.scale);
 }
@@ -300,8 +349,9 @@ __global__ __launch_bounds__(C* T) void k_col_corr(ColCorrArgs a) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const int c = tid % C, t = tid / C;
-  const int col = blockIdx.x * C + c;
-  const int pair = blockIdx.y;
+  const TileId id = col_tile_id();
+  const int col = id.tile * C + c;
+  const int pair = id.img;
   const int p = pair / 3;
   const int q = a.abc[pair];
   const float2* Xq = a.F + (size_t)q * NN;
@@ -315,8 +365,10 @@ __global__ __launch_bounds__(C* T) void k_col_corr(ColCorrArgs a) {
     v1[m] = known ? cmul(cconj(xq), xp) : make_float2(0.f, 0.f);
     v2[m] = known ? cmul(xq, xp) : make_float2(0.f, 0.f);
   }
-  fft<N, +1, C>(v1, lds + c, t, a.tw);
-  fft<N, +1, C>(v2, lds + c, t, a.tw);
+  TwSet<N> ws;
+  load_twiddle_set<N>(ws, t, a.tw);
+  fft<N, +1, ColL>(v1, lds + c, t, a.tw, ws);
+  fft<N, +1, ColL>(v2, lds + c, t, a.tw, ws);
   float2* d1 = a.C + (size_t)(2 * pair) * NN;
   float2* d2 = d1 + NN;
 #pragma unroll
@@ -344,7 +396,7 @@ __global__ __launch_bounds__(RWI* T) void k_row_argmax(RowArgmaxArgs a) {
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = src[t + T * m];
-  fft<N, +1, 1>(v, lds + r * N, t, a.tw);
+  fft<N, +1, RowL>(v, lds + r * NR, t, a.tw);
   ArgmaxRec b;
   b.val = -1.f;
   b.idx = 0x7fffffff;
@@ -379,8 +431,9 @@ __global__ __launch_bounds__(C* T) void k_col_mix(ColMixArgs a) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const int c = tid % C, t = tid / C;
-  const int col = blockIdx.x * C + c;
-  const int p = blockIdx.y;
+  const TileId id = col_tile_id();
+  const int col = id.tile * C + c;
+  const int p = id.img;
   const int* abc = a.abc + 3 * p;
   const int* mp = a.mapprm + 5 * p;
   const int tx = mp[0], ty = mp[1], sx = mp[2], sy = mp[3];
@@ -421,7 +474,7 @@ __global__ __launch_bounds__(C* T) void k_col_mix(ColMixArgs a) {
     }
     v[m] = cscale(out, a.inv_n);
   }
-  fft<N, +1, C>(v, lds + c, t, a.tw);
+  fft<N, +1, ColL>(v, lds + c, t, a.tw);
   float2* dst = a.out + (size_t)a.table[a.P + p] * NN;
 #pragma unroll
   for (int m = 0; m < E; ++m) dst[(size_t)(t + T * m) * N + col] = v[m];
@@ -431,8 +484,8 @@ __global__ __launch_bounds__(C* T) void k_col_mix(ColMixArgs a) {
 // Launchers.
 // ---------------------------------------------------------------------------
 constexpr size_t kColLds = (size_t)C * N * sizeof(float2);
-constexpr size_t kRowLds = (size_t)RW * N * sizeof(float2);
-constexpr size_t kRowLdsI = (size_t)RWI * N * sizeof(float2);
+constexpr size_t kRowLds = (size_t)RW * NR * sizeof(float2);
+constexpr size_t kRowLdsI = (size_t)RWI * NR * sizeof(float2);
 
 template <typename K>
 hipError_t set_lds(K kernel, size_t bytes) {
