@@ -72,92 +72,123 @@ __global__ void k_err_final(ErrFinalArgs a) {
 // ---------------------------------------------------------------------------
 // Shrink-wrap: |x| smoothed by a circular separable Gaussian (rows, columns).
 // ---------------------------------------------------------------------------
-__global__ void k_smooth_rows(SmoothArgs a) {
-  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long nn = (long)a.n * a.n;
-  if (gid >= (long)a.nm * nn) return;
-  const int m = (int)(gid / nn);
-  const long p = gid % nn;
-  const int i = (int)(p / a.n), j = (int)(p % a.n);
-  const float2* xr = a.X + (size_t)a.slots[m] * nn + (size_t)i * a.n;
-  float acc = 0.f;
-  for (int k = -a.r; k <= a.r; ++k) {
-    int jj = j + k;
-    jj = jj < 0 ? jj + a.n : (jj >= a.n ? jj - a.n : jj);
-    const float2 z = xr[jj];
-    acc += a.w[k + a.r] * sqrtf(z.x * z.x + z.y * z.y);
+constexpr int SMOOTH_THREADS = 256;
+constexpr int COLS_PER_TILE = 64;
+constexpr int ROWS_PER_TILE = 64;
+
+// One workgroup per row: |x| with its periodic halo in LDS, then the taps.
+__global__ __launch_bounds__(SMOOTH_THREADS) void k_smooth_rows(SmoothArgs a) {
+  __shared__ float ext[1024 + MAX_TAPS];
+  const int n = a.n, r = a.r;
+  const int i = blockIdx.x, m = blockIdx.y;
+  const float2* xr = a.X + (size_t)a.slots[m] * n * n + (size_t)i * n;
+  for (int q = threadIdx.x; q < n + 2 * r; q += blockDim.x) {
+    int j = (q - r) % n;
+    j = j < 0 ? j + n : j;
+    const float2 z = xr[j];
+    ext[q] = sqrtf(z.x * z.x + z.y * z.y);
   }
-  a.out[gid] = acc;
+  __syncthreads();
+  float* out = a.out + (size_t)m * n * n + (size_t)i * n;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    float acc = 0.f;
+    for (int k = 0; k <= 2 * r; ++k) acc += a.w[k] * ext[j + k];
+    out[j] = acc;
+  }
 }
 
-__global__ void k_smooth_cols(SmoothColArgs a) {
-  __shared__ float sh[16];
-  const long nn = (long)a.n * a.n;
-  const int m = blockIdx.y;
-  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  float v = 0.f;
-  if (p < nn) {
-    const int i = (int)(p / a.n), j = (int)(p % a.n);
-    const float* src = a.in + (size_t)m * nn;
-    float acc = 0.f;
-    for (int k = -a.r; k <= a.r; ++k) {
-      int ii = i + k;
-      ii = ii < 0 ? ii + a.n : (ii >= a.n ? ii - a.n : ii);
-      acc += a.w[k + a.r] * src[(size_t)ii * a.n + j];
+// Column smoothing on a tile of 64 columns x 64 rows staged (with its periodic
+// halo rows) in LDS; also the tile maximum.
+__global__ __launch_bounds__(SMOOTH_THREADS) void k_smooth_cols(SmoothColArgs a) {
+  __shared__ float tile[(ROWS_PER_TILE + MAX_TAPS) * COLS_PER_TILE];
+  __shared__ float wmax[SMOOTH_THREADS / 64];
+  const int n = a.n, r = a.r;
+  const int cw = n < COLS_PER_TILE ? n : COLS_PER_TILE;
+  const int rh = n < ROWS_PER_TILE ? n : ROWS_PER_TILE;
+  const int c0 = blockIdx.x * cw, i0 = blockIdx.y * rh, m = blockIdx.z;
+  const float* src = a.in + (size_t)m * n * n;
+  const int rows_ext = rh + 2 * r;
+  for (int q = threadIdx.x; q < rows_ext * COLS_PER_TILE; q += blockDim.x) {
+    const int rr = q / COLS_PER_TILE, cc = q % COLS_PER_TILE;
+    if (cc < cw && c0 + cc < n) {
+      int ii = (i0 + rr - r) % n;
+      ii = ii < 0 ? ii + n : ii;
+      tile[q] = src[(size_t)ii * n + c0 + cc];
     }
-    a.out[(size_t)m * nn + p] = acc;
-    v = acc;
   }
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float mx = 0.f;
+  float* out = a.out + (size_t)m * n * n;
+  for (int q = threadIdx.x; q < rh * COLS_PER_TILE; q += blockDim.x) {
+    const int rr = q / COLS_PER_TILE, cc = q % COLS_PER_TILE;
+    if (cc < cw && c0 + cc < n && i0 + rr < n) {
+      float acc = 0.f;
+      for (int k = 0; k <= 2 * r; ++k) acc += a.w[k] * tile[(rr + k) * COLS_PER_TILE + cc];
+      out[(size_t)(i0 + rr) * n + c0 + cc] = acc;
+      mx = fmaxf(mx, acc);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
   __syncthreads();
   if (threadIdx.x == 0) {
-    float mx = sh[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mx = fmaxf(mx, sh[w]);
-    a.block_max[(size_t)m * gridDim.x + blockIdx.x] = mx;
+    float v = wmax[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmaxf(v, wmax[w]);
+    a.block_max[(size_t)m * (gridDim.x * gridDim.y) + blockIdx.y * gridDim.x + blockIdx.x] = v;
   }
 }
 
-__global__ void k_member_max(MemberMaxArgs a) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= a.nm) return;
+__global__ __launch_bounds__(256) void k_member_max(MemberMaxArgs a) {
+  __shared__ float wmax[4];
+  const int m = blockIdx.x;
   float mx = 0.f;
-  for (int i = 0; i < a.blocks_per_member; ++i) mx = fmaxf(mx, a.block_max[(size_t)m * a.blocks_per_member + i]);
-  a.maxv[m] = mx;
+  for (int i = threadIdx.x; i < a.blocks_per_member; i += blockDim.x)
+    mx = fmaxf(mx, a.block_max[(size_t)m * a.blocks_per_member + i]);
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float v = wmax[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmaxf(v, wmax[w]);
+    a.maxv[m] = v;
+  }
 }
 
 // S' = {a_sigma > tau * max a_sigma}, compared in double; unchanged if max = 0.
-__global__ void k_threshold(ThresholdArgs a) {
-  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (long)a.nm * a.W) return;
-  const int m = (int)(gid / a.W);
-  const int w = (int)(gid % a.W);
-  const float mx = a.maxv[m];
-  if (!(mx > 0.f)) return;
-  const double thr = a.tau * (double)mx;
+// One thread per pixel; a wavefront covers 64 consecutive pixels = 2 words.
+__global__ __launch_bounds__(256) void k_threshold(ThresholdArgs a) {
   const long nn = (long)a.n * a.n;
-  const float* src = a.in + (size_t)m * nn;
-  uint32_t bits = 0;
-  for (int b = 0; b < 32; ++b) {
-    const long idx = (long)w * 32 + b;
-    if (idx < nn && (double)src[idx] > thr) bits |= 1u << b;
-  }
-  a.S[(size_t)a.slots[m] * a.W + w] = bits;
+  const int m = blockIdx.y;
+  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const float mx = a.maxv[m];
+  if (!(mx > 0.f)) return;  // uniform over the workgroup
+  const double thr = a.tau * (double)mx;
+  const bool bit = p < nn && (double)a.in[(size_t)m * nn + p] > thr;
+  const unsigned long long b = __ballot(bit);
+  const int lane = threadIdx.x & 63;
+  const long w0 = (p - lane) >> 5;  // first word of this wavefront
+  uint32_t* Sm = a.S + (size_t)a.slots[m] * a.W;
+  if (lane == 0 && w0 < a.W) Sm[w0] = (uint32_t)b;
+  if (lane == 1 && w0 + 1 < a.W) Sm[w0 + 1] = (uint32_t)(b >> 32);
 }
 
 // ---------------------------------------------------------------------------
 // UpdateSupportSize: exact top-k of the smoothed modulus, ties to the lower
 // linear index.  One workgroup per member: MSB-first radix select on the
-// float bit patterns (order-preserving for values >= 0), then an index-ordered
-// pass that takes the remaining ties first-come.
+// float bit patterns (order-preserving for values >= 0) with per-wavefront
+// histograms, then an index-ordered pass that takes the remaining ties in
+// index order (wavefront ballots and a workgroup prefix count).
 // ---------------------------------------------------------------------------
 constexpr int TOPK_THREADS = 1024;
+constexpr int TOPK_WAVES = TOPK_THREADS / 64;
 
 __global__ __launch_bounds__(TOPK_THREADS) void k_topk(TopkArgs a) {
-  __shared__ uint32_t hist[256];
+  __shared__ uint32_t hist[TOPK_WAVES][256];
+  __shared__ uint32_t tot[256];
   __shared__ uint32_t sh_prefix, sh_rem;
-  __shared__ int scan_sh[TOPK_THREADS / 64];
+  __shared__ int wcount[TOPK_WAVES];
   const int m = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long nn = (long)a.n * a.n;
   const uint32_t* keys = reinterpret_cast<const uint32_t*>(a.in + (size_t)m * nn);
   uint32_t* Sm = a.S + (size_t)a.slots[m] * a.W;
@@ -170,22 +201,28 @@ __global__ __launch_bounds__(TOPK_THREADS) void k_topk(TopkArgs a) {
   uint32_t prefix = 0, pmask = 0, rem = k;
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 24 - 8 * pass;
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+    for (int i = threadIdx.x; i < TOPK_WAVES * 256; i += blockDim.x) (&hist[0][0])[i] = 0;
     __syncthreads();
     for (long i = threadIdx.x; i < nn; i += blockDim.x) {
       const uint32_t key = keys[i];
-      if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+      if ((key & pmask) == prefix) atomicAdd(&hist[wv][(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 256; b += blockDim.x) {
+      uint32_t sum = 0;
+      for (int w = 0; w < TOPK_WAVES; ++w) sum += hist[w][b];
+      tot[b] = sum;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       uint32_t cum = 0;
       int digit = 0;
       for (int b = 255; b >= 0; --b) {
-        if (cum + hist[b] >= rem) {
+        if (cum + tot[b] >= rem) {
           digit = b;
           break;
         }
-        cum += hist[b];
+        cum += tot[b];
       }
       sh_prefix = prefix | ((uint32_t)digit << shift);
       sh_rem = rem - cum;
@@ -194,37 +231,32 @@ __global__ __launch_bounds__(TOPK_THREADS) void k_topk(TopkArgs a) {
     prefix = sh_prefix;
     rem = sh_rem;
     pmask |= 255u << shift;
-    __syncthreads();
   }
-  // prefix = k-th largest key; rem = how many keys equal to it are taken
-  int taken_before = 0;
-  for (int wb = 0; wb < a.W; wb += blockDim.x) {
-    const int w = wb + threadIdx.x;
-    int ties = 0;
-    if (w < a.W) {
-      for (int b = 0; b < 32; ++b) {
-        const long idx = (long)w * 32 + b;
-        if (idx < nn && keys[idx] == prefix) ++ties;
-      }
+  // prefix = k-th largest key; rem = number of keys equal to it to take
+  const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  uint32_t taken = 0;  // ties taken before the current chunk (uniform)
+  for (long base = 0; base < nn; base += blockDim.x) {
+    const long p = base + threadIdx.x;
+    const uint32_t key = p < nn ? keys[p] : 0u;
+    const bool gt = p < nn && key > prefix;
+    const bool eq = p < nn && key == prefix;
+    const unsigned long long eqb = __ballot(eq);
+    if (lane == 0) wcount[wv] = __popcll(eqb);
+    __syncthreads();
+    uint32_t before = taken;
+    uint32_t chunk = 0;
+    for (int w = 0; w < TOPK_WAVES; ++w) {
+      if (w < wv) before += wcount[w];
+      chunk += wcount[w];
     }
-    int total;
-    const int before = block_exclusive_scan(ties, scan_sh, &total);
-    if (w < a.W) {
-      uint32_t bits = 0;
-      int rank = taken_before + before;
-      for (int b = 0; b < 32; ++b) {
-        const long idx = (long)w * 32 + b;
-        if (idx >= nn) break;
-        const uint32_t key = keys[idx];
-        if (key > prefix) bits |= 1u << b;
-        else if (key == prefix) {
-          if ((uint32_t)rank < rem) bits |= 1u << b;
-          ++rank;
-        }
-      }
-      Sm[w] = bits;
-    }
-    taken_before += total;
+    before += __popcll(eqb & lt_mask);
+    const bool bit = gt || (eq && before < rem);
+    const unsigned long long bb = __ballot(bit);
+    const long w0 = (p - lane) >> 5;
+    if (lane == 0 && w0 < a.W) Sm[w0] = (uint32_t)bb;
+    if (lane == 1 && w0 + 1 < a.W) Sm[w0 + 1] = (uint32_t)(bb >> 32);
+    taken += chunk;
+    __syncthreads();
   }
 }
 
@@ -452,17 +484,26 @@ hipError_t launch_err_final(const ErrFinalArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_err_final, dim3(blocks_for(a.nm, 64)), dim3(64), 0, s, a);
   return hipGetLastError();
 }
+int smooth_blocks_per_member(int n) {
+  const int cw = n < COLS_PER_TILE ? n : COLS_PER_TILE;
+  const int rh = n < ROWS_PER_TILE ? n : ROWS_PER_TILE;
+  return ((n + cw - 1) / cw) * ((n + rh - 1) / rh);
+}
+
 hipError_t launch_smooth(const SmoothArgs& rows, const SmoothColArgs& cols, const MemberMaxArgs& mx,
                          hipStream_t s) {
-  const long total = (long)rows.nm * rows.n * rows.n;
-  hipLaunchKernelGGL(k_smooth_rows, dim3(blocks_for(total, 256)), dim3(256), 0, s, rows);
-  const unsigned bpm = blocks_for((long)rows.n * rows.n, 256);
-  hipLaunchKernelGGL(k_smooth_cols, dim3(bpm, cols.nm), dim3(256), 0, s, cols);
-  hipLaunchKernelGGL(k_member_max, dim3(blocks_for(mx.nm, 64)), dim3(64), 0, s, mx);
+  const int n = rows.n;
+  if (n > 1024 || rows.r > (MAX_TAPS - 1) / 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_smooth_rows, dim3(n, rows.nm), dim3(SMOOTH_THREADS), 0, s, rows);
+  const int cw = n < COLS_PER_TILE ? n : COLS_PER_TILE;
+  const int rh = n < ROWS_PER_TILE ? n : ROWS_PER_TILE;
+  hipLaunchKernelGGL(k_smooth_cols, dim3((n + cw - 1) / cw, (n + rh - 1) / rh, cols.nm), dim3(SMOOTH_THREADS), 0,
+                     s, cols);
+  hipLaunchKernelGGL(k_member_max, dim3(mx.nm), dim3(256), 0, s, mx);
   return hipGetLastError();
 }
 hipError_t launch_threshold(const ThresholdArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_threshold, dim3(blocks_for((long)a.nm * a.W, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_threshold, dim3(blocks_for((long)a.n * a.n, 256), a.nm), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_topk(const TopkArgs& a, hipStream_t s) {

@@ -119,6 +119,9 @@ struct PackArgs {
   uint32_t* S;
 };
 
+// Blocks per member of the column smoothing pass (size of the block-max array).
+int smooth_blocks_per_member(int n);
+
 hipError_t launch_err_final(const ErrFinalArgs& a, hipStream_t s);
 hipError_t launch_smooth(const SmoothArgs& rows, const SmoothColArgs& cols, const MemberMaxArgs& mx,
                          hipStream_t s);

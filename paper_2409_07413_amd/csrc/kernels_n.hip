@@ -412,13 +412,39 @@ __global__ __launch_bounds__(RWI* T) void k_row_argmax(RowArgmaxArgs a) {
       b.im = v[m].y;
     }
   }
-  red[tid] = b;
-  __syncthreads();
-  if (tid == 0) {
-    ArgmaxRec best = red[0];
-    for (int i = 1; i < RWI * T; ++i)
-      if (better(red[i].val, red[i].idx, best.val, best.idx)) best = red[i];
-    a.partial[(size_t)img * (N / RWI) + blockIdx.x] = best;
+  constexpr int NT = RWI * T;
+  if constexpr (NT % 64 == 0) {
+    // wavefront butterfly reduction, then one record per wavefront
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const float ov = __shfl_xor(b.val, o, 64);
+      const int oi = __shfl_xor(b.idx, o, 64);
+      const float ore = __shfl_xor(b.re, o, 64);
+      const float oim = __shfl_xor(b.im, o, 64);
+      if (better(ov, oi, b.val, b.idx)) {
+        b.val = ov;
+        b.idx = oi;
+        b.re = ore;
+        b.im = oim;
+      }
+    }
+    if ((tid & 63) == 0) red[tid >> 6] = b;
+    __syncthreads();
+    if (tid == 0) {
+      ArgmaxRec best = red[0];
+      for (int i = 1; i < NT / 64; ++i)
+        if (better(red[i].val, red[i].idx, best.val, best.idx)) best = red[i];
+      a.partial[(size_t)img * (N / RWI) + blockIdx.x] = best;
+    }
+  } else {
+    red[tid] = b;
+    __syncthreads();
+    if (tid == 0) {
+      ArgmaxRec best = red[0];
+      for (int i = 1; i < NT; ++i)
+        if (better(red[i].val, red[i].idx, best.val, best.idx)) best = red[i];
+      a.partial[(size_t)img * (N / RWI) + blockIdx.x] = best;
+    }
   }
 }
 

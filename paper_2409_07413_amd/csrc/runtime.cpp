@@ -329,7 +329,7 @@ void smooth(spr_pop* pop, double sigma, Scope sc, hipStream_t s) {
   ca.out = reinterpret_cast<float*>(pop->Y);
   ca.block_max = pop->block_max;
   for (int k = 0; k <= 2 * r; ++k) ra.w[k] = ca.w[k] = (float)w[k];
-  MemberMaxArgs ma{sc.nm, (int)(((long)pop->n * pop->n + 255) / 256), pop->block_max, pop->maxv};
+  MemberMaxArgs ma{sc.nm, smooth_blocks_per_member(pop->n), pop->block_max, pop->maxv};
   launch_ok(launch_smooth(ra, ca, ma, s), "smooth");
 }
 
@@ -728,7 +728,7 @@ spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const ui
       pop->E = dalloc<double>(ns);
       pop->table = dalloc<int>(ns);
       pop->err_partial = dalloc<double>(ns * (pop->n / pop->K->C));
-      pop->block_max = dalloc<float>(ns * ((nn + 255) / 256));
+      pop->block_max = dalloc<float>(ns * smooth_blocks_per_member(pop->n));
       pop->maxv = dalloc<float>(ns);
       pop->flags = dalloc<int>(1);
       pop->scal = dalloc<PopScalars>(1);
