@@ -74,6 +74,11 @@ void spr_ctx_destroy(spr_ctx* ctx);
 const char* spr_ctx_last_error(const spr_ctx* ctx);
 /* 1 if N is a supported detector size, else 0. */
 int32_t spr_supported_size(int32_t n);
+/* Iteration runs (consecutive ER/HIO/RAAR ops) proceed in chunks of members    */
+/* whose two N x N complex work buffers fit in `bytes` (default 256 MiB, the     */
+/* memory-side cache of one MI355X); members are independent inside a run, so   */
+/* results do not depend on it.  0 = one chunk.                                  */
+spr_status spr_ctx_set_cache_budget(spr_ctx* ctx, uint64_t bytes);
 
 /* ------------------------------------------------------------------------- */
 /* Shot: the measured modulus M = sqrt(I) and mask Xi (1 = measured) of one    */
@@ -225,17 +230,18 @@ typedef struct spr_xover_info {
 spr_status spr_read_xover(spr_pop* pop, spr_xover_info* out, int32_t max_n);
 
 /* ------------------------------------------------------------------------- */
-/* Kernel timing: when enabled, HIP events are recorded on the launch stream   */
-/* around every launch of the iteration kernels; spr_timing_read returns the   */
-/* number of launches and their summed event time since enabling (it waits    */
-/* for the population's work).  Enabling resets the totals.                    */
+/* Kernel timing: HIP events are recorded on the launch stream around every   */
+/* launch of the kernels selected by `mask` (bit k = SPR_KERNEL_k; 0 = off);   */
+/* spr_timing_read returns the number of launches and their summed event time */
+/* since the last spr_timing_enable (it waits for the population's work).      */
 /* ------------------------------------------------------------------------- */
 #define SPR_KERNEL_ROW_INGEST 0    /* real-space density -> row FFT (sequence start) */
 #define SPR_KERNEL_COL_PROJ 1      /* column FFT, masked modulus projection, column IFFT */
 #define SPR_KERNEL_ROW_UPDATE_ER 2 /* row IFFT, ER step, row FFT */
 #define SPR_KERNEL_ROW_UPDATE_IA 3 /* row IFFTs, HIO/RAAR step, row FFT */
 #define SPR_KERNEL_COUNT 4
-spr_status spr_timing_enable(spr_pop* pop, int32_t enable);
+#define SPR_TIMING_ALL 0xF
+spr_status spr_timing_enable(spr_pop* pop, int32_t mask);
 spr_status spr_timing_read(spr_pop* pop, int32_t kernel, int64_t* launches, double* total_ms);
 
 /* Unitary 2D DFT of `batch` N x N complex images (device pointers, in != out */

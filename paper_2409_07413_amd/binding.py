@@ -75,7 +75,7 @@ EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_suppo
            "spr_shot_create", "spr_shot_destroy", "spr_pop_create", "spr_pop_destroy", "spr_pop_write",
            "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
            "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
-           "spr_timing_enable", "spr_timing_read"]
+           "spr_timing_enable", "spr_timing_read", "spr_ctx_set_cache_budget"]
 
 KERNEL_ROW_INGEST, KERNEL_COL_PROJ, KERNEL_ROW_UPDATE_ER, KERNEL_ROW_UPDATE_IA = range(4)
 KERNEL_NAMES = {0: "k_row_ingest", 1: "k_col_proj", 2: "k_row_update(ER)", 3: "k_row_update(HIO/RAAR)"}
@@ -109,6 +109,7 @@ def _proto(lib):
         "spr_fft2": (i32, [vp, i32, i32, vp, vp, i32, vp]),
         "spr_timing_enable": (i32, [vp, i32]),
         "spr_timing_read": (i32, [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+        "spr_ctx_set_cache_budget": (i32, [vp, C.c_uint64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -217,6 +218,10 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_cache_budget(self, nbytes):
+        """Member-chunk budget of iteration runs in bytes (0 = no chunks)."""
+        self._check(self.lib.spr_ctx_set_cache_budget(self.h, int(nbytes)))
 
     def supported(self, n):
         return bool(self.lib.spr_supported_size(int(n)))
@@ -380,8 +385,12 @@ class Population:
         self.ctx._check(self.ctx.lib.spr_read_stats(self.h, arr, max_n, C.byref(n)))
         return [arr[i] for i in range(n.value)]
 
-    def timing(self, enable=True):
-        self.ctx._check(self.ctx.lib.spr_timing_enable(self.h, 1 if enable else 0))
+    def timing(self, enable=True, kernels=None):
+        """Enable per-launch event timing for the given kernel ids (default all)."""
+        mask = 0
+        if enable:
+            mask = 0xF if kernels is None else sum(1 << k for k in kernels)
+        self.ctx._check(self.ctx.lib.spr_timing_enable(self.h, mask))
 
     def timing_read(self, kernel):
         """(launches, total event milliseconds) of one kernel since timing was enabled."""

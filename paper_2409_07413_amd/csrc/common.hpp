@@ -26,11 +26,14 @@ struct Phase {
   float c, s;  // cos(chi pi), sin(chi pi) for PHASE_CONE
 };
 
+// Densities and supports are addressed by storage slot (slots[m]); the work
+// buffers T and Y by the member's position m in the launch, so a launch over
+// any subset of members works in one compact region.
 struct RowIngestArgs {
   const int* slots;      // launch member -> storage slot
   int nm;                // members
   const float2* X;       // real-space density [slot][N*N]
-  float2* T;             // out: row-FFT of the ingested density
+  float2* T;             // out: row-FFT of the ingested density [member][N*N]
   const uint32_t* S;     // support bits [slot][W]
   int W;
   int mode;              // IngestMode
@@ -39,10 +42,9 @@ struct RowIngestArgs {
 };
 
 struct ColProjArgs {
-  const int* slots;
   int nm;
-  const float2* T;       // row-FFT'd iterate
-  float2* Y;             // out: column-IFFT of the projected spectrum
+  const float2* T;       // row-FFT'd iterate [member][N*N]
+  float2* Y;             // out: column-IFFT of the projected spectrum [member][N*N]
   const float* amp;      // measured modulus, FFT order, sign bit set = unknown
   float amp_scale;       // multiplies the stored modulus
   const float2* tw;
@@ -65,9 +67,8 @@ struct RowUpdateArgs {
 };
 
 struct ColErrArgs {
-  const int* slots;
   int nm;
-  const float2* T;       // row-FFT of S*x
+  const float2* T;       // row-FFT of S*x [member][N*N]
   const float* amp;
   float amp_scale;
   double* partial;       // out: [member][N/C] partial sums of Xi (|X| - M)^2

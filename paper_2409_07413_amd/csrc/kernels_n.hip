@@ -119,7 +119,8 @@ __global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
   const int member = valid ? grow / N : 0;
   const int row = valid ? grow % N : 0;
   const int slot = a.slots[member];
-  const size_t off = (size_t)slot * NN + (size_t)row * N;
+  const size_t off = (size_t)slot * NN + (size_t)row * N;     // density: by storage slot
+  const size_t toff = (size_t)member * NN + (size_t)row * N;  // work buffer: by launch position
   const uint32_t* Sm = a.S + (size_t)slot * a.W;
   float2 v[E];
 #pragma unroll
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
   fft<N, -1, RowL>(v, lds + r * NR, t, a.tw);
   if (valid) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) a.T[off + t + T * m] = v[m];
+    for (int m = 0; m < E; ++m) a.T[toff + t + T * m] = v[m];
   }
 }
 
@@ -149,9 +150,8 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
   const int c = tid % C, t = tid / C;
   const TileId id = col_tile_id();
   const int col = id.tile * C + c;
-  const int slot = a.slots[id.img];
-  const float2* src = a.T + (size_t)slot * NN;
-  float2* dst = a.Y + (size_t)slot * NN;
+  const float2* src = a.T + (size_t)id.img * NN;
+  float2* dst = a.Y + (size_t)id.img * NN;
   float2 v[E];
   float mv[E];
 #pragma unroll
@@ -185,17 +185,18 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   const int member = valid ? grow / N : 0;
   const int row = valid ? grow % N : 0;
   const int slot = a.slots[member];
-  const size_t off = (size_t)slot * NN + (size_t)row * N;
+  const size_t off = (size_t)slot * NN + (size_t)row * N;     // density: by storage slot
+  const size_t toff = (size_t)member * NN + (size_t)row * N;  // work buffers: by launch position
   const uint32_t* Sm = a.S + (size_t)slot * a.W;
   float2* l = lds + r * NR;
 
   const bool ia = a.alg != ALG_ER;
   float2 y[E], x[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) y[m] = valid ? a.Y[off + t + T * m] : make_float2(0.f, 0.f);
+  for (int m = 0; m < E; ++m) y[m] = valid ? a.Y[toff + t + T * m] : make_float2(0.f, 0.f);
   if (ia) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) x[m] = valid ? a.T[off + t + T * m] : make_float2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) x[m] = valid ? a.T[toff + t + T * m] : make_float2(0.f, 0.f);
   }
   TwSet<N> ws;
   load_twiddle_set<N>(ws, t, a.tw);
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   fft<N, -1, RowL>(xn, l, t, a.tw, ws);
   if (valid) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) a.T[off + t + T * m] = xn[m];
+    for (int m = 0; m < E; ++m) a.T[toff + t + T * m] = xn[m];
   }
 }
 
@@ -263,8 +264,7 @@ __global__ __launch_bounds__(C* T) void k_col_err(ColErrArgs a) {
   const int c = tid % C, t = tid / C;
   const TileId id = col_tile_id();
   const int col = id.tile * C + c;
-  const int slot = a.slots[id.img];
-  const float2* src = a.T + (size_t)slot * NN;
+  const float2* src = a.T + (size_t)id.img * NN;
   float2 v[E];
   float mv[E];
 #pragma unroll

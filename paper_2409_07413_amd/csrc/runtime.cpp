@@ -43,6 +43,9 @@ using namespace spr;
 struct spr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  // iteration runs are split into member chunks whose two work buffers fit in
+  // this many bytes (0: no split), so that they stay in the memory-side cache
+  size_t cache_budget = (size_t)256 << 20;
   std::string err;
   std::map<int, float2*> tw;
   std::mutex mu;
@@ -87,7 +90,7 @@ struct spr_pop {
   size_t stage_bytes = 0;
   hipStream_t last = nullptr;
   // optional per-kernel timing: HIP events recorded around each launch
-  bool timing = false;
+  uint32_t timing = 0;  // bit k: time kernel k
   struct Stamp {
     int kernel;
     hipEvent_t start, stop;
@@ -238,7 +241,7 @@ hipEvent_t pooled_event(spr_pop* pop) {
 // Launch through `fn`, bracketing it with events when timing is enabled.
 template <class Fn>
 void timed(spr_pop* pop, int kernel, hipStream_t s, const char* what, Fn&& fn) {
-  if (!pop->timing) {
+  if (!(pop->timing & (1u << kernel))) {
     launch_ok(fn(), what);
     return;
   }
@@ -268,22 +271,21 @@ struct Iter {
   double chi;
 };
 
-// One Sequence: ingest, then per iteration a column pass and a row pass.
-void run_iterations(spr_pop* pop, const std::vector<Iter>& its, int scope, hipStream_t s) {
-  if (its.empty()) return;
+// One Sequence over members slots[0..nm): ingest, then per iteration a column
+// pass and a row pass.
+void run_iterations_on(spr_pop* pop, const std::vector<Iter>& its, const int* slots, int nm, hipStream_t s) {
   const SizeKernels* K = pop->K;
   const float2* tw = twiddles(pop->ctx, pop->n);
-  Scope sc = scope_of(pop, scope);
-  RowIngestArgs ia{sc.slots, sc.nm, pop->X, pop->T, pop->S, pop->W,
+  RowIngestArgs ia{slots, nm, pop->X, pop->T, pop->S, pop->W,
                    its[0].alg == ALG_ER ? INGEST_PC : INGEST_PLAIN, phase_of(its[0].chi), tw};
   timed(pop, SPR_KERNEL_ROW_INGEST, s, "row_ingest", [&] { return K->row_ingest(ia, s); });
   for (size_t i = 0; i < its.size(); ++i) {
-    ColProjArgs ca{sc.slots, sc.nm, pop->T, pop->Y, pop->shot->amp, pop->shot->amp_scale, tw};
+    ColProjArgs ca{nm, pop->T, pop->Y, pop->shot->amp, pop->shot->amp_scale, tw};
     timed(pop, SPR_KERNEL_COL_PROJ, s, "col_proj", [&] { return K->col_proj(ca, s); });
     const bool last = i + 1 == its.size();
     RowUpdateArgs ra;
-    ra.slots = sc.slots;
-    ra.nm = sc.nm;
+    ra.slots = slots;
+    ra.nm = nm;
     ra.Y = pop->Y;
     ra.T = pop->T;
     ra.X = pop->X;
@@ -298,6 +300,19 @@ void run_iterations(spr_pop* pop, const std::vector<Iter>& its, int scope, hipSt
     const int kid = ra.alg == ALG_ER ? SPR_KERNEL_ROW_UPDATE_ER : SPR_KERNEL_ROW_UPDATE_IA;
     timed(pop, kid, s, "row_update", [&] { return K->row_update(ra, s); });
   }
+}
+
+// Members are independent inside a Sequence, so the run may proceed chunk by
+// chunk; with a cache budget the chunk's buffers stay cache-resident across
+// its iterations.
+void run_iterations(spr_pop* pop, const std::vector<Iter>& its, int scope, hipStream_t s) {
+  if (its.empty()) return;
+  Scope sc = scope_of(pop, scope);
+  int chunk = sc.nm;
+  const size_t per_member = 2 * (size_t)pop->n * pop->n * sizeof(float2);
+  if (pop->ctx->cache_budget > 0) chunk = (int)std::max<size_t>(1, pop->ctx->cache_budget / per_member);
+  for (int c0 = 0; c0 < sc.nm; c0 += chunk)
+    run_iterations_on(pop, its, sc.slots + c0, std::min(chunk, sc.nm - c0), s);
 }
 
 void smooth(spr_pop* pop, double sigma, Scope sc, hipStream_t s) {
@@ -369,7 +384,7 @@ void get_error(spr_pop* pop, int scope, hipStream_t s) {
   Scope sc = scope_of(pop, scope);
   RowIngestArgs ia{sc.slots, sc.nm, pop->X, pop->T, pop->S, pop->W, INGEST_SMASK, phase_of(1.0), tw};
   launch_ok(K->row_ingest(ia, s), "row_ingest");
-  ColErrArgs ea{sc.slots, sc.nm, pop->T, pop->shot->amp, pop->shot->amp_scale, pop->err_partial, tw};
+  ColErrArgs ea{sc.nm, pop->T, pop->shot->amp, pop->shot->amp_scale, pop->err_partial, tw};
   launch_ok(K->col_err(ea, s), "col_err");
   ErrFinalArgs fa{pop->err_partial, pop->n / K->C, sc.nm, sc.slots, pop->shot->den, pop->E, pop->flags};
   launch_ok(launch_err_final(fa, s), "err_final");
@@ -1076,12 +1091,18 @@ spr_status spr_timing_enable(spr_pop* pop, int32_t enable) {
   return guarded(pop->ctx, [&] {
     use_device(pop->ctx);
     sync_pop(pop);
-    pop->timing = enable != 0;
+    pop->timing = (uint32_t)enable & ((1u << SPR_KERNEL_COUNT) - 1);
     for (int k = 0; k < SPR_KERNEL_COUNT; ++k) {
       pop->kernel_ms[k] = 0.0;
       pop->kernel_launches[k] = 0;
     }
   });
+}
+
+spr_status spr_ctx_set_cache_budget(spr_ctx* ctx, uint64_t bytes) {
+  if (!ctx) return SPR_E_INVALID_ARG;
+  ctx->cache_budget = (size_t)bytes;
+  return SPR_OK;
 }
 
 spr_status spr_timing_read(spr_pop* pop, int32_t kernel, int64_t* launches, double* total_ms) {
