@@ -123,13 +123,41 @@ def _oracle_member(a):
     return 0
 
 
+def copy_calibration():
+    """A plain copy kernel of known size: 256 MiB read + 256 MiB written per
+    launch (torch copy_, a hipMemcpy device-to-device kernel).  Its FETCH_SIZE /
+    WRITE_SIZE readings calibrate the HBM counters; its bandwidth is the
+    practical ceiling of a read+write sweep."""
+    import torch
+    n = 256 * (1 << 20) // 8
+    a = torch.randn(n, dtype=torch.complex64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 20
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "avg_ms": ms,
+                      "GBps_read_plus_write": 2 * n * 8 / (ms * 1e-3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="time a plain device copy of 256 MiB (reference for HBM counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus above 1 is not "
                                    "supported (the population loop shards by member, see the design notes)"}))

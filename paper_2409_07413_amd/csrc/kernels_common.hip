@@ -180,32 +180,72 @@ __global__ __launch_bounds__(256) void k_threshold(ThresholdArgs a) {
 // index order (wavefront ballots and a workgroup prefix count).
 // ---------------------------------------------------------------------------
 constexpr int TOPK_THREADS = 1024;
+
+// Add one count per lane to hist[bin] (bin < 0: none).  The smoothed modulus
+// is concentrated in a few bins (most pixels are near zero), so lanes with the
+// same bin are first combined with ballots (a few rounds, one atomic per
+// group); the rest add individually.
+__device__ __forceinline__ void wave_histogram_add(uint32_t* hist, int bin, int lane) {
+  bool pending = bin >= 0;
+#pragma unroll
+  for (int round = 0; round < 4; ++round) {
+    const unsigned long long pend = __ballot(pending);
+    if (pend == 0ull) return;
+    const int leader = __ffsll((long long)pend) - 1;
+    const int lb = __shfl(bin, leader, 64);
+    const unsigned long long same = __ballot(pending && bin == lb);
+    if (lane == leader) atomicAdd(&hist[lb], (uint32_t)__popcll(same));
+    if (bin == lb) pending = false;
+  }
+  if (pending) atomicAdd(&hist[bin], 1u);
+}
 constexpr int TOPK_WAVES = TOPK_THREADS / 64;
+
+constexpr int TOPK_PER_THREAD = 8;  // contiguous keys per thread (N^2 is a multiple of 16)
+
+__device__ __forceinline__ void load8(const uint32_t* __restrict__ keys, long i, long nn, uint32_t (&k)[8]) {
+  if (i + 8 <= nn) {
+    const uint4 a = *reinterpret_cast<const uint4*>(keys + i);
+    const uint4 b = *reinterpret_cast<const uint4*>(keys + i + 4);
+    k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
+    k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) k[j] = i + j < nn ? keys[i + j] : 0u;
+  }
+}
 
 __global__ __launch_bounds__(TOPK_THREADS) void k_topk(TopkArgs a) {
   __shared__ uint32_t hist[TOPK_WAVES][256];
   __shared__ uint32_t tot[256];
   __shared__ uint32_t sh_prefix, sh_rem;
-  __shared__ int wcount[TOPK_WAVES];
+  __shared__ int scan_sh[TOPK_WAVES];
   const int m = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long nn = (long)a.n * a.n;
   const uint32_t* keys = reinterpret_cast<const uint32_t*>(a.in + (size_t)m * nn);
-  uint32_t* Sm = a.S + (size_t)a.slots[m] * a.W;
+  uint8_t* Sb = reinterpret_cast<uint8_t*>(a.S + (size_t)a.slots[m] * a.W);
   const double alpha = a.alpha_src ? a.alpha_src[a.alpha_index] : a.alpha_abs;
   double kd = floor(alpha + 0.5);
   if (!(kd >= 1.0)) kd = 1.0;
   if (kd > (double)nn) kd = (double)nn;
   const uint32_t k = (uint32_t)kd;
+  constexpr long CHUNK = (long)TOPK_THREADS * TOPK_PER_THREAD;
 
   uint32_t prefix = 0, pmask = 0, rem = k;
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 24 - 8 * pass;
     for (int i = threadIdx.x; i < TOPK_WAVES * 256; i += blockDim.x) (&hist[0][0])[i] = 0;
     __syncthreads();
-    for (long i = threadIdx.x; i < nn; i += blockDim.x) {
-      const uint32_t key = keys[i];
-      if ((key & pmask) == prefix) atomicAdd(&hist[wv][(key >> shift) & 255u], 1u);
+    for (long base = 0; base < nn; base += CHUNK) {
+      const long i = base + (long)threadIdx.x * TOPK_PER_THREAD;
+      uint32_t kk[8];
+      load8(keys, i, nn, kk);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int bin = (i + j < nn && (kk[j] & pmask) == prefix) ? (int)((kk[j] >> shift) & 255u) : -1;
+        wave_histogram_add(hist[wv], bin, lane);
+      }
     }
     __syncthreads();
     for (int b = threadIdx.x; b < 256; b += blockDim.x) {
@@ -232,31 +272,33 @@ __global__ __launch_bounds__(TOPK_THREADS) void k_topk(TopkArgs a) {
     rem = sh_rem;
     pmask |= 255u << shift;
   }
-  // prefix = k-th largest key; rem = number of keys equal to it to take
-  const unsigned long long lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  uint32_t taken = 0;  // ties taken before the current chunk (uniform)
-  for (long base = 0; base < nn; base += blockDim.x) {
-    const long p = base + threadIdx.x;
-    const uint32_t key = p < nn ? keys[p] : 0u;
-    const bool gt = p < nn && key > prefix;
-    const bool eq = p < nn && key == prefix;
-    const unsigned long long eqb = __ballot(eq);
-    if (lane == 0) wcount[wv] = __popcll(eqb);
-    __syncthreads();
-    uint32_t before = taken;
-    uint32_t chunk = 0;
-    for (int w = 0; w < TOPK_WAVES; ++w) {
-      if (w < wv) before += wcount[w];
-      chunk += wcount[w];
+  // prefix = k-th largest key; rem = number of keys equal to it to take, in
+  // index order.  Thread t owns pixels base + 8t .. base + 8t + 7, i.e. one
+  // byte of the support words.
+  uint32_t taken = 0;
+  for (long base = 0; base < nn; base += CHUNK) {
+    const long i = base + (long)threadIdx.x * TOPK_PER_THREAD;
+    uint32_t kk[8];
+    load8(keys, i, nn, kk);
+    int ties = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ties += (i + j < nn && kk[j] == prefix) ? 1 : 0;
+    int total;
+    const int before = block_exclusive_scan(ties, scan_sh, &total);
+    uint32_t rank = taken + (uint32_t)before;
+    uint32_t byte = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (i + j >= nn) continue;
+      if (kk[j] > prefix) {
+        byte |= 1u << j;
+      } else if (kk[j] == prefix) {
+        if (rank < rem) byte |= 1u << j;
+        ++rank;
+      }
     }
-    before += __popcll(eqb & lt_mask);
-    const bool bit = gt || (eq && before < rem);
-    const unsigned long long bb = __ballot(bit);
-    const long w0 = (p - lane) >> 5;
-    if (lane == 0 && w0 < a.W) Sm[w0] = (uint32_t)bb;
-    if (lane == 1 && w0 + 1 < a.W) Sm[w0 + 1] = (uint32_t)(bb >> 32);
-    taken += chunk;
-    __syncthreads();
+    if (i < nn) Sb[i >> 3] = (uint8_t)byte;
+    taken += (uint32_t)total;
   }
 }
 
