@@ -194,6 +194,15 @@ spr_status spr_sched_ops(const spr_sched* sched, spr_op* ops, int32_t max_ops, i
 /* ------------------------------------------------------------------------- */
 /* Enqueue the schedule on `hip_stream` (a hipStream_t; NULL = context stream). */
 spr_status spr_run(spr_pop* pop, const spr_sched* sched, void* hip_stream);
+/* Batched uneven shots: run scheds[i] on pops[i] for i < n.  Populations of one */
+/* detector size advance together, each operation being one launch over all    */
+/* their members (each reaching its own shot's modulus); sizes run one after    */
+/* another on the stream.  Within a size the schedules must be equal and use    */
+/* only ER/HIO/RAAR, SHRINKWRAP, SUPPORT_AREA with SPR_AREA_ABS and GET_ERROR on  */
+/* scope ALL; otherwise SPR_E_INVALID_ARG.  Results equal running each          */
+/* population alone.  Each population must appear once.                         */
+spr_status spr_run_batch(spr_ctx* ctx, spr_pop* const* pops, const spr_sched* const* scheds, int32_t n,
+                         void* hip_stream);
 /* Wait for the population's work; SPR_E_NUMERIC if a fitness value was NaN/Inf. */
 spr_status spr_sync(spr_pop* pop);
 

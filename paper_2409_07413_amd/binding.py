@@ -75,7 +75,7 @@ EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_suppo
            "spr_shot_create", "spr_shot_destroy", "spr_pop_create", "spr_pop_destroy", "spr_pop_write",
            "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
            "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
-           "spr_timing_enable", "spr_timing_read", "spr_ctx_set_cache_budget"]
+           "spr_timing_enable", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch"]
 
 KERNEL_ROW_INGEST, KERNEL_COL_PROJ, KERNEL_ROW_UPDATE_ER, KERNEL_ROW_UPDATE_IA = range(4)
 KERNEL_NAMES = {0: "k_row_ingest", 1: "k_col_proj", 2: "k_row_update(ER)", 3: "k_row_update(HIO/RAAR)"}
@@ -110,6 +110,7 @@ def _proto(lib):
         "spr_timing_enable": (i32, [vp, i32]),
         "spr_timing_read": (i32, [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
         "spr_ctx_set_cache_budget": (i32, [vp, C.c_uint64]),
+        "spr_run_batch": (i32, [vp, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -222,6 +223,13 @@ class Context:
     def set_cache_budget(self, nbytes):
         """Member-chunk budget of iteration runs in bytes (0 = no chunks)."""
         self._check(self.lib.spr_ctx_set_cache_budget(self.h, int(nbytes)))
+
+    def run_batch(self, pops, scheds, stream=None):
+        """Run scheds[i] on pops[i]; same-size populations share every launch."""
+        n = len(pops)
+        ph = (C.c_void_p * n)(*[p.h.value if isinstance(p.h, C.c_void_p) else p.h for p in pops])
+        sh = (C.c_void_p * n)(*[s.h.value if isinstance(s.h, C.c_void_p) else s.h for s in scheds])
+        self._check(self.lib.spr_run_batch(self.h, ph, sh, n, _stream_ptr(stream)))
 
     def supported(self, n):
         return bool(self.lib.spr_supported_size(int(n)))

@@ -26,15 +26,37 @@ struct Phase {
   float c, s;  // cos(chi pi), sin(chi pi) for PHASE_CONE
 };
 
+// Storage of one reconstruction, reached through slots[m] -> desc[slot]: its
+// density and support words, the measured modulus of its shot and where its
+// fitness goes.  A launch may mix members of several shots of one size.
+struct SlotDesc {
+  float2* X;             // real-space density, N*N complex
+  uint32_t* S;           // support bits, W words
+  const float* amp;      // measured modulus of its shot, FFT order, sign bit set = unknown
+  double* E;             // fitness slot
+  double den;            // sum of Xi M^2 of its shot
+  int* flags;            // status word of its population (bit 0: non-finite fitness)
+  float amp_scale;
+  int pad;
+};
+
+// Per-member iteration parameters (members at different schedule positions).
+struct IterParam {
+  int alg;
+  float beta;
+  Phase ph;
+  int out_mode;
+  Phase ph_next;
+};
+
 // Densities and supports are addressed by storage slot (slots[m]); the work
 // buffers T and Y by the member's position m in the launch, so a launch over
 // any subset of members works in one compact region.
 struct RowIngestArgs {
   const int* slots;      // launch member -> storage slot
   int nm;                // members
-  const float2* X;       // real-space density [slot][N*N]
+  const SlotDesc* desc;  // per slot
   float2* T;             // out: row-FFT of the ingested density [member][N*N]
-  const uint32_t* S;     // support bits [slot][W]
   int W;
   int mode;              // IngestMode
   Phase ph;
@@ -42,22 +64,22 @@ struct RowIngestArgs {
 };
 
 struct ColProjArgs {
+  const int* slots;
   int nm;
+  const SlotDesc* desc;  // measured modulus of each member's shot
   const float2* T;       // row-FFT'd iterate [member][N*N]
   float2* Y;             // out: column-IFFT of the projected spectrum [member][N*N]
-  const float* amp;      // measured modulus, FFT order, sign bit set = unknown
-  float amp_scale;       // multiplies the stored modulus
   const float2* tw;
 };
 
 struct RowUpdateArgs {
   const int* slots;
   int nm;
+  const SlotDesc* desc;
   const float2* Y;       // rowFFT(P_M x) from the column pass
   float2* T;             // in: rowFFT(x) (HIO/RAAR); out: next iterate's row FFT
-  float2* X;             // out (OUT_REAL): real-space density
-  const uint32_t* S;
   int W;
+  const IterParam* ip;   // per-member parameters, or null: the uniform ones below
   int alg;               // Alg
   float beta;
   Phase ph;              // constraint of this step
@@ -67,10 +89,10 @@ struct RowUpdateArgs {
 };
 
 struct ColErrArgs {
+  const int* slots;
   int nm;
+  const SlotDesc* desc;
   const float2* T;       // row-FFT of S*x [member][N*N]
-  const float* amp;
-  float amp_scale;
   double* partial;       // out: [member][N/C] partial sums of Xi (|X| - M)^2
   const float2* tw;
 };

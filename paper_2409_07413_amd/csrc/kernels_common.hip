@@ -64,9 +64,10 @@ __global__ void k_err_final(ErrFinalArgs a) {
   if (m >= a.nm) return;
   double s = 0.0;
   for (int i = 0; i < a.ntiles; ++i) s += a.partial[(size_t)m * a.ntiles + i];
-  const double e = sqrt(s / a.den);
-  a.E[a.slots[m]] = e;
-  if (!isfinite(e)) atomicOr(a.flags, 1);
+  const SlotDesc& d = a.desc[a.slots[m]];
+  const double e = sqrt(s / d.den);
+  *d.E = e;
+  if (!isfinite(e)) atomicOr(d.flags, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(SMOOTH_THREADS) void k_smooth_rows(SmoothArgs a) {
   __shared__ float ext[1024 + MAX_TAPS];
   const int n = a.n, r = a.r;
   const int i = blockIdx.x, m = blockIdx.y;
-  const float2* xr = a.X + (size_t)a.slots[m] * n * n + (size_t)i * n;
+  const float2* xr = a.desc[a.slots[m]].X + (size_t)i * n;
   for (int q = threadIdx.x; q < n + 2 * r; q += blockDim.x) {
     int j = (q - r) % n;
     j = j < 0 ? j + n : j;
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(256) void k_threshold(ThresholdArgs a) {
   const unsigned long long b = __ballot(bit);
   const int lane = threadIdx.x & 63;
   const long w0 = (p - lane) >> 5;  // first word of this wavefront
-  uint32_t* Sm = a.S + (size_t)a.slots[m] * a.W;
+  uint32_t* Sm = a.desc[a.slots[m]].S;
   if (lane == 0 && w0 < a.W) Sm[w0] = (uint32_t)b;
   if (lane == 1 && w0 + 1 < a.W) Sm[w0 + 1] = (uint32_t)(b >> 32);
 }
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(TOPK_THREADS) void k_topk(TopkArgs a) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long nn = (long)a.n * a.n;
   const uint32_t* keys = reinterpret_cast<const uint32_t*>(a.in + (size_t)m * nn);
-  uint8_t* Sb = reinterpret_cast<uint8_t*>(a.S + (size_t)a.slots[m] * a.W);
+  uint8_t* Sb = reinterpret_cast<uint8_t*>(a.desc[a.slots[m]].S);
   const double alpha = a.alpha_src ? a.alpha_src[a.alpha_index] : a.alpha_abs;
   double kd = floor(alpha + 0.5);
   if (!(kd >= 1.0)) kd = 1.0;

@@ -29,15 +29,13 @@ struct ErrFinalArgs {
   int ntiles;
   int nm;
   const int* slots;
-  double den;     // sum of Xi M^2
-  double* E;      // [slot]
-  int* flags;     // bit 0: non-finite fitness
+  const SlotDesc* desc;  // fitness slot, sum of Xi M^2 and status word per member
 };
 
 struct SmoothArgs {
   const int* slots;
   int nm, n, r;
-  const float2* X;
+  const SlotDesc* desc;
   float* out;     // [member][n*n]
   float w[MAX_TAPS];
 };
@@ -62,7 +60,7 @@ struct ThresholdArgs {
   const float* in;
   const float* maxv;
   double tau;
-  uint32_t* S;
+  const SlotDesc* desc;
 };
 
 struct TopkArgs {
@@ -72,7 +70,7 @@ struct TopkArgs {
   const double* alpha_src;  // device scalars or null
   int alpha_index;
   double alpha_abs;
-  uint32_t* S;
+  const SlotDesc* desc;
 };
 
 struct StatsArgs {

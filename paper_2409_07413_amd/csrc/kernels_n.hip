@@ -118,15 +118,15 @@ __global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
   const bool valid = grow < a.nm * N;
   const int member = valid ? grow / N : 0;
   const int row = valid ? grow % N : 0;
-  const int slot = a.slots[member];
-  const size_t off = (size_t)slot * NN + (size_t)row * N;     // density: by storage slot
+  const SlotDesc d = a.desc[a.slots[member]];
+  const size_t off = (size_t)row * N;                         // within the member's density
   const size_t toff = (size_t)member * NN + (size_t)row * N;  // work buffer: by launch position
-  const uint32_t* Sm = a.S + (size_t)slot * a.W;
+  const uint32_t* Sm = d.S;
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int e = t + T * m;
-    float2 z = valid ? a.X[off + e] : make_float2(0.f, 0.f);
+    float2 z = valid ? d.X[off + e] : make_float2(0.f, 0.f);
     if (a.mode != INGEST_PLAIN) {
       const bool s = bit_at(Sm, row * N + e);
       if (a.mode == INGEST_PC) z = s ? proj_phase(z, a.ph) : make_float2(0.f, 0.f);
@@ -152,12 +152,15 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
   const int col = id.tile * C + c;
   const float2* src = a.T + (size_t)id.img * NN;
   float2* dst = a.Y + (size_t)id.img * NN;
+  const SlotDesc& d = a.desc[a.slots[id.img]];
+  const float* amp = d.amp;
+  const float amp_scale = d.amp_scale;
   float2 v[E];
   float mv[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = src[(size_t)(t + T * m) * N + col];
 #pragma unroll
-  for (int m = 0; m < E; ++m) mv[m] = a.amp[(size_t)(t + T * m) * N + col];
+  for (int m = 0; m < E; ++m) mv[m] = amp[(size_t)(t + T * m) * N + col];
   TwSet<N> ws;
   load_twiddle_set<N>(ws, t, a.tw);
   fft<N, -1, ColL>(v, lds + c, t, a.tw, ws);
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const float2 X = cscale(v[m], inv);  // unitary spectrum
-    v[m] = cscale(modulus_replace(X, mv[m], a.amp_scale), inv);
+    v[m] = cscale(modulus_replace(X, mv[m], amp_scale), inv);
   }
   fft<N, +1, ColL>(v, lds + c, t, a.tw, ws);
 #pragma unroll
@@ -184,13 +187,27 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   const bool valid = grow < a.nm * N;
   const int member = valid ? grow / N : 0;
   const int row = valid ? grow % N : 0;
-  const int slot = a.slots[member];
-  const size_t off = (size_t)slot * NN + (size_t)row * N;     // density: by storage slot
+  const SlotDesc d = a.desc[a.slots[member]];
+  const size_t off = (size_t)row * N;                         // within the member's density
   const size_t toff = (size_t)member * NN + (size_t)row * N;  // work buffers: by launch position
-  const uint32_t* Sm = a.S + (size_t)slot * a.W;
+  const uint32_t* Sm = d.S;
   float2* l = lds + r * NR;
+  int alg = a.alg, out_mode = a.out_mode;
+  float beta = a.beta;
+  Phase ph = a.ph, ph_next = a.ph_next;
+  if (a.ip) {
+    // per-member parameters (rows of one member share them; a wavefront may
+    // hold rows of several members when N is small, which is safe because the
+    // row transforms only synchronise within their own wavefront)
+    const IterParam q = a.ip[member];
+    alg = q.alg;
+    out_mode = q.out_mode;
+    beta = q.beta;
+    ph = q.ph;
+    ph_next = q.ph_next;
+  }
 
-  const bool ia = a.alg != ALG_ER;
+  const bool ia = alg != ALG_ER;
   float2 y[E], x[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) y[m] = valid ? a.Y[toff + t + T * m] : make_float2(0.f, 0.f);
@@ -209,36 +226,35 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   } else {
     fft<N, +1, RowL>(x, l, t, a.tw, ws);
     const float inv = 1.0f / (float)N;
-    const float beta = a.beta;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const float2 xv = cscale(x[m], inv);
       const float2 yv = y[m];
       const bool s = bit_at(Sm, row * N + t + T * m);
-      if (a.alg == ALG_HIO) {
-        const bool feasible = s && inside_phase(yv, a.ph);
+      if (alg == ALG_HIO) {
+        const bool feasible = s && inside_phase(yv, ph);
         xn[m] = feasible ? yv : make_float2(xv.x - beta * yv.x, xv.y - beta * yv.y);
       } else {  // RAAR
         const float2 z = make_float2(2.f * yv.x - xv.x, 2.f * yv.y - xv.y);
-        const float2 pc = s ? proj_phase(z, a.ph) : make_float2(0.f, 0.f);
+        const float2 pc = s ? proj_phase(z, ph) : make_float2(0.f, 0.f);
         const float g = 1.f - 2.f * beta;
         xn[m] = make_float2(beta * pc.x + beta * xv.x + g * yv.x, beta * pc.y + beta * xv.y + g * yv.y);
       }
     }
   }
 
-  if (a.out_mode == OUT_REAL) {
+  if (out_mode == OUT_REAL) {
     if (valid) {
 #pragma unroll
-      for (int m = 0; m < E; ++m) a.X[off + t + T * m] = xn[m];
+      for (int m = 0; m < E; ++m) d.X[off + t + T * m] = xn[m];
     }
     return;
   }
-  if (a.out_mode == OUT_T_PC) {
+  if (out_mode == OUT_T_PC) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const bool s = bit_at(Sm, row * N + t + T * m);
-      xn[m] = s ? proj_phase(xn[m], a.ph_next) : make_float2(0.f, 0.f);
+      xn[m] = s ? proj_phase(xn[m], ph_next) : make_float2(0.f, 0.f);
     }
   }
   fft<N, -1, RowL>(xn, l, t, a.tw, ws);
@@ -265,12 +281,13 @@ __global__ __launch_bounds__(C* T) void k_col_err(ColErrArgs a) {
   const TileId id = col_tile_id();
   const int col = id.tile * C + c;
   const float2* src = a.T + (size_t)id.img * NN;
+  const SlotDesc& d = a.desc[a.slots[id.img]];
   float2 v[E];
   float mv[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = src[(size_t)(t + T * m) * N + col];
 #pragma unroll
-  for (int m = 0; m < E; ++m) mv[m] = a.amp[(size_t)(t + T * m) * N + col];
+  for (int m = 0; m < E; ++m) mv[m] = d.amp[(size_t)(t + T * m) * N + col];
   fft<N, -1, ColL>(v, lds + c, t, a.tw);
   const float inv = 1.0f / (float)N;
   double acc = 0.0;
@@ -279,8 +296,8 @@ __global__ __launch_bounds__(C* T) void k_col_err(ColErrArgs a) {
     const float stored = mv[m];
     if (!signbit(stored)) {
       const float2 X = cscale(v[m], inv);
-      const double d = (double)sqrtf(X.x * X.x + X.y * X.y) - (double)(stored * a.amp_scale);
-      acc += d * d;
+      const double df = (double)sqrtf(X.x * X.x + X.y * X.y) - (double)(stored * d.amp_scale);
+      acc += df * df;
     }
   }
   acc = wave_sum(acc);

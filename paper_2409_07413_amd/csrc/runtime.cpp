@@ -40,6 +40,19 @@ const SizeKernels* size_kernels(int n) {
 
 using namespace spr;
 
+// Work buffers of batched launches, per detector size, grown on demand.
+struct Workspace {
+  size_t members = 0;
+  float2* T = nullptr;
+  float2* Y = nullptr;
+  double* err_partial = nullptr;
+  float* block_max = nullptr;
+  float* maxv = nullptr;
+  SlotDesc* desc = nullptr;
+  int* slots = nullptr;
+  hipStream_t last = nullptr;  // stream of the last batch that used these buffers
+};
+
 struct spr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -48,6 +61,7 @@ struct spr_ctx {
   size_t cache_budget = (size_t)256 << 20;
   std::string err;
   std::map<int, float2*> tw;
+  std::map<int, Workspace> ws;
   std::mutex mu;
 };
 
@@ -73,6 +87,7 @@ struct spr_pop {
   uint32_t* S = nullptr;
   double* E = nullptr;
   int* table = nullptr;
+  SlotDesc* desc = nullptr;  // per storage slot
   double* err_partial = nullptr;
   float* block_max = nullptr;
   float* maxv = nullptr;
@@ -271,26 +286,79 @@ struct Iter {
   double chi;
 };
 
+// A launch group: members of one size reached through slot descriptors, and
+// the work buffers they use.  A population's scope and a batch of shots both
+// run through groups.
+struct Group {
+  spr_ctx* ctx = nullptr;
+  const SizeKernels* K = nullptr;
+  int n = 0, W = 0;
+  const int* slots = nullptr;
+  int nm = 0;
+  const SlotDesc* desc = nullptr;
+  float2* T = nullptr;           // work buffers: >= chunk members (>= nm for smoothing/fitness)
+  float2* Y = nullptr;
+  double* err_partial = nullptr; // >= nm * n / C
+  float* block_max = nullptr;    // >= nm * smoothing blocks per member
+  float* maxv = nullptr;         // >= nm
+  int* flags = nullptr;
+  spr_pop* timing = nullptr;     // where launch timings are kept (may be null)
+  int chunk = 0;                 // members per iteration launch
+};
+
+int chunk_for(spr_ctx* ctx, int n, int nm) {
+  if (ctx->cache_budget == 0) return nm;
+  const size_t per_member = 2 * (size_t)n * n * sizeof(float2);
+  return (int)std::min<size_t>((size_t)nm, std::max<size_t>(1, ctx->cache_budget / per_member));
+}
+
+Group pop_group(spr_pop* pop, int scope) {
+  Scope sc = scope_of(pop, scope);
+  Group g;
+  g.ctx = pop->ctx;
+  g.K = pop->K;
+  g.n = pop->n;
+  g.W = pop->W;
+  g.slots = sc.slots;
+  g.nm = sc.nm;
+  g.desc = pop->desc;
+  g.T = pop->T;
+  g.Y = pop->Y;
+  g.err_partial = pop->err_partial;
+  g.block_max = pop->block_max;
+  g.maxv = pop->maxv;
+  g.flags = pop->flags;
+  g.timing = pop;
+  g.chunk = chunk_for(pop->ctx, pop->n, sc.nm);
+  return g;
+}
+
+template <class Fn>
+void launch_timed(spr_pop* tp, int kernel, hipStream_t s, const char* what, Fn&& fn) {
+  if (tp) timed(tp, kernel, s, what, fn);
+  else launch_ok(fn(), what);
+}
+
 // One Sequence over members slots[0..nm): ingest, then per iteration a column
 // pass and a row pass.
-void run_iterations_on(spr_pop* pop, const std::vector<Iter>& its, const int* slots, int nm, hipStream_t s) {
-  const SizeKernels* K = pop->K;
-  const float2* tw = twiddles(pop->ctx, pop->n);
-  RowIngestArgs ia{slots, nm, pop->X, pop->T, pop->S, pop->W,
+void run_iterations_on(const Group& g, const std::vector<Iter>& its, const int* slots, int nm, hipStream_t s) {
+  const SizeKernels* K = g.K;
+  const float2* tw = twiddles(g.ctx, g.n);
+  RowIngestArgs ia{slots, nm, g.desc, g.T, g.W,
                    its[0].alg == ALG_ER ? INGEST_PC : INGEST_PLAIN, phase_of(its[0].chi), tw};
-  timed(pop, SPR_KERNEL_ROW_INGEST, s, "row_ingest", [&] { return K->row_ingest(ia, s); });
+  launch_timed(g.timing, SPR_KERNEL_ROW_INGEST, s, "row_ingest", [&] { return K->row_ingest(ia, s); });
   for (size_t i = 0; i < its.size(); ++i) {
-    ColProjArgs ca{nm, pop->T, pop->Y, pop->shot->amp, pop->shot->amp_scale, tw};
-    timed(pop, SPR_KERNEL_COL_PROJ, s, "col_proj", [&] { return K->col_proj(ca, s); });
+    ColProjArgs ca{slots, nm, g.desc, g.T, g.Y, tw};
+    launch_timed(g.timing, SPR_KERNEL_COL_PROJ, s, "col_proj", [&] { return K->col_proj(ca, s); });
     const bool last = i + 1 == its.size();
     RowUpdateArgs ra;
     ra.slots = slots;
     ra.nm = nm;
-    ra.Y = pop->Y;
-    ra.T = pop->T;
-    ra.X = pop->X;
-    ra.S = pop->S;
-    ra.W = pop->W;
+    ra.desc = g.desc;
+    ra.Y = g.Y;
+    ra.T = g.T;
+    ra.W = g.W;
+    ra.ip = nullptr;
     ra.alg = its[i].alg;
     ra.beta = its[i].beta;
     ra.ph = phase_of(its[i].chi);
@@ -298,24 +366,20 @@ void run_iterations_on(spr_pop* pop, const std::vector<Iter>& its, const int* sl
     ra.ph_next = last ? phase_of(1.0) : phase_of(its[i + 1].chi);
     ra.tw = tw;
     const int kid = ra.alg == ALG_ER ? SPR_KERNEL_ROW_UPDATE_ER : SPR_KERNEL_ROW_UPDATE_IA;
-    timed(pop, kid, s, "row_update", [&] { return K->row_update(ra, s); });
+    launch_timed(g.timing, kid, s, "row_update", [&] { return K->row_update(ra, s); });
   }
 }
 
 // Members are independent inside a Sequence, so the run may proceed chunk by
 // chunk; with a cache budget the chunk's buffers stay cache-resident across
 // its iterations.
-void run_iterations(spr_pop* pop, const std::vector<Iter>& its, int scope, hipStream_t s) {
-  if (its.empty()) return;
-  Scope sc = scope_of(pop, scope);
-  int chunk = sc.nm;
-  const size_t per_member = 2 * (size_t)pop->n * pop->n * sizeof(float2);
-  if (pop->ctx->cache_budget > 0) chunk = (int)std::max<size_t>(1, pop->ctx->cache_budget / per_member);
-  for (int c0 = 0; c0 < sc.nm; c0 += chunk)
-    run_iterations_on(pop, its, sc.slots + c0, std::min(chunk, sc.nm - c0), s);
+void run_iterations(const Group& g, const std::vector<Iter>& its, hipStream_t s) {
+  if (its.empty() || g.nm == 0) return;
+  const int chunk = g.chunk > 0 ? g.chunk : g.nm;
+  for (int c0 = 0; c0 < g.nm; c0 += chunk) run_iterations_on(g, its, g.slots + c0, std::min(chunk, g.nm - c0), s);
 }
 
-void smooth(spr_pop* pop, double sigma, Scope sc, hipStream_t s) {
+void smooth(const Group& g, double sigma, hipStream_t s) {
   SmoothArgs ra{};
   SmoothColArgs ca{};
   int r = 0;
@@ -331,63 +395,72 @@ void smooth(spr_pop* pop, double sigma, Scope sc, hipStream_t s) {
     }
     for (auto& v : w) v /= sum;
   }
-  ra.slots = sc.slots;
-  ra.nm = sc.nm;
-  ra.n = pop->n;
+  ra.slots = g.slots;
+  ra.nm = g.nm;
+  ra.n = g.n;
   ra.r = r;
-  ra.X = pop->X;
-  ra.out = reinterpret_cast<float*>(pop->T);
-  ca.nm = sc.nm;
-  ca.n = pop->n;
+  ra.desc = g.desc;
+  ra.out = reinterpret_cast<float*>(g.T);
+  ca.nm = g.nm;
+  ca.n = g.n;
   ca.r = r;
   ca.in = ra.out;
-  ca.out = reinterpret_cast<float*>(pop->Y);
-  ca.block_max = pop->block_max;
+  ca.out = reinterpret_cast<float*>(g.Y);
+  ca.block_max = g.block_max;
   for (int k = 0; k <= 2 * r; ++k) ra.w[k] = ca.w[k] = (float)w[k];
-  MemberMaxArgs ma{sc.nm, smooth_blocks_per_member(pop->n), pop->block_max, pop->maxv};
+  MemberMaxArgs ma{g.nm, smooth_blocks_per_member(g.n), g.block_max, g.maxv};
   launch_ok(launch_smooth(ra, ca, ma, s), "smooth");
 }
 
-void shrinkwrap(spr_pop* pop, const spr_op& op, hipStream_t s) {
-  Scope sc = scope_of(pop, op.scope);
-  smooth(pop, op.sigma, sc, s);
-  ThresholdArgs ta{sc.slots, sc.nm, pop->n, pop->W, reinterpret_cast<const float*>(pop->Y), pop->maxv,
-                   op.tau, pop->S};
+void shrinkwrap(const Group& g, double sigma, double tau, hipStream_t s) {
+  if (g.nm == 0) return;
+  smooth(g, sigma, s);
+  ThresholdArgs ta{g.slots, g.nm, g.n, g.W, reinterpret_cast<const float*>(g.Y), g.maxv, tau, g.desc};
   launch_ok(launch_threshold(ta, s), "threshold");
 }
 
-void support_area(spr_pop* pop, const spr_op& op, hipStream_t s) {
-  Scope sc = scope_of(pop, op.scope);
-  smooth(pop, op.sigma, sc, s);
+void support_area(const Group& g, double sigma, const double* alpha_src, int alpha_index, double alpha_abs,
+                  hipStream_t s) {
+  if (g.nm == 0) return;
+  smooth(g, sigma, s);
   TopkArgs ta{};
-  ta.slots = sc.slots;
-  ta.nm = sc.nm;
-  ta.n = pop->n;
-  ta.W = pop->W;
-  ta.in = reinterpret_cast<const float*>(pop->Y);
-  if (op.which == SPR_AREA_ABS) {
-    ta.alpha_src = nullptr;
-    ta.alpha_abs = op.alpha;
-  } else if (op.which == SPR_AREA_BEST || op.which == SPR_AREA_EVAL) {
-    ta.alpha_src = pop->scal->alpha;
-    ta.alpha_index = op.which;
-  } else {
-    fail(SPR_E_INVALID_ARG, "unknown support-area source");
-  }
-  ta.S = pop->S;
+  ta.slots = g.slots;
+  ta.nm = g.nm;
+  ta.n = g.n;
+  ta.W = g.W;
+  ta.in = reinterpret_cast<const float*>(g.Y);
+  ta.alpha_src = alpha_src;
+  ta.alpha_index = alpha_index;
+  ta.alpha_abs = alpha_abs;
+  ta.desc = g.desc;
   launch_ok(launch_topk(ta, s), "topk");
 }
 
-void get_error(spr_pop* pop, int scope, hipStream_t s) {
-  const SizeKernels* K = pop->K;
-  const float2* tw = twiddles(pop->ctx, pop->n);
-  Scope sc = scope_of(pop, scope);
-  RowIngestArgs ia{sc.slots, sc.nm, pop->X, pop->T, pop->S, pop->W, INGEST_SMASK, phase_of(1.0), tw};
+void get_error(const Group& g, hipStream_t s) {
+  if (g.nm == 0) return;
+  const SizeKernels* K = g.K;
+  const float2* tw = twiddles(g.ctx, g.n);
+  RowIngestArgs ia{g.slots, g.nm, g.desc, g.T, g.W, INGEST_SMASK, phase_of(1.0), tw};
   launch_ok(K->row_ingest(ia, s), "row_ingest");
-  ColErrArgs ea{sc.nm, pop->T, pop->shot->amp, pop->shot->amp_scale, pop->err_partial, tw};
+  ColErrArgs ea{g.slots, g.nm, g.desc, g.T, g.err_partial, tw};
   launch_ok(K->col_err(ea, s), "col_err");
-  ErrFinalArgs fa{pop->err_partial, pop->n / K->C, sc.nm, sc.slots, pop->shot->den, pop->E, pop->flags};
+  ErrFinalArgs fa{g.err_partial, g.n / K->C, g.nm, g.slots, g.desc};
   launch_ok(launch_err_final(fa, s), "err_final");
+}
+
+const double* alpha_source(spr_pop* pop, const spr_op& op, int& index, double& abs_alpha) {
+  index = 0;
+  abs_alpha = 0.0;
+  if (op.which == SPR_AREA_ABS) {
+    abs_alpha = op.alpha;
+    return nullptr;
+  }
+  if (op.which == SPR_AREA_BEST || op.which == SPR_AREA_EVAL) {
+    if (!pop) fail(SPR_E_INVALID_ARG, "areas from generation statistics need a population");
+    index = op.which;
+    return pop->scal->alpha;
+  }
+  fail(SPR_E_INVALID_ARG, "unknown support-area source");
 }
 
 void need_memetic(spr_pop* pop, const char* what) {
@@ -500,18 +573,22 @@ void run_schedule(spr_pop* pop, const spr_sched* sch, hipStream_t s) {
         for (int c = 0; c < q.count; ++c) its.push_back({alg, (float)q.beta, q.chi});
         ++i;
       }
-      run_iterations(pop, its, scope, s);
+      run_iterations(pop_group(pop, scope), its, s);
       continue;
     }
     switch (o.kind) {
       case SPR_OP_SHRINKWRAP:
-        shrinkwrap(pop, o, s);
+        shrinkwrap(pop_group(pop, o.scope), o.sigma, o.tau, s);
         break;
-      case SPR_OP_SUPPORT_AREA:
-        support_area(pop, o, s);
+      case SPR_OP_SUPPORT_AREA: {
+        int idx;
+        double ab;
+        const double* src = alpha_source(pop, o, idx, ab);
+        support_area(pop_group(pop, o.scope), o.sigma, src, idx, ab, s);
         break;
+      }
       case SPR_OP_GET_ERROR:
-        get_error(pop, o.scope, s);
+        get_error(pop_group(pop, o.scope), s);
         break;
       case SPR_OP_STATS: {
         need_memetic(pop, "STATS");
@@ -582,6 +659,7 @@ void destroy_pop(spr_pop* p) {
   dfree(p->S);
   dfree(p->E);
   dfree(p->table);
+  dfree(p->desc);
   dfree(p->err_partial);
   dfree(p->block_max);
   dfree(p->maxv);
@@ -607,6 +685,69 @@ void sync_pop(spr_pop* pop) {
   if (pop->last) HIPCHK(hipStreamSynchronize(pop->last));
   HIPCHK(hipStreamSynchronize(pop->ctx->stream));
   if (!pop->stamps.empty()) collect_stamps(pop);
+}
+
+Workspace& workspace(spr_ctx* ctx, int n, size_t members, const SizeKernels* K) {
+  Workspace& w = ctx->ws[n];
+  if (w.members >= members) return w;
+  HIPCHK(hipDeviceSynchronize());  // the old buffers may still be in use
+  for (void* q : {(void*)w.T, (void*)w.Y, (void*)w.err_partial, (void*)w.block_max, (void*)w.maxv,
+                  (void*)w.desc, (void*)w.slots})
+    if (q) (void)hipFree(q);
+  w = Workspace();
+  const size_t nn = (size_t)n * n;
+  w.T = dalloc<float2>(members * nn);
+  w.Y = dalloc<float2>(members * nn);
+  w.err_partial = dalloc<double>(members * (n / K->C));
+  w.block_max = dalloc<float>(members * smooth_blocks_per_member(n));
+  w.maxv = dalloc<float>(members);
+  w.desc = dalloc<SlotDesc>(members);
+  w.slots = dalloc<int>(members);
+  w.members = members;
+  return w;
+}
+
+bool same_op(const spr_op& a, const spr_op& b) {
+  return a.kind == b.kind && a.count == b.count && a.scope == b.scope && a.which == b.which && a.gen == b.gen &&
+         a.gens == b.gens && a.t_min == b.t_min && a.t_max == b.t_max && a.beta == b.beta && a.chi == b.chi &&
+         a.sigma == b.sigma && a.tau == b.tau && a.alpha == b.alpha && a.c_p == b.c_p && a.c_w == b.c_w;
+}
+
+// Populations of one size advancing through one schedule together: every
+// operation is a single launch over all their members.
+void run_group_schedule(const Group& g, const spr_sched* sch, hipStream_t s) {
+  const auto& ops = sch->ops;
+  size_t i = 0;
+  while (i < ops.size()) {
+    const spr_op& o = ops[i];
+    if (o.kind == SPR_OP_ER || o.kind == SPR_OP_HIO || o.kind == SPR_OP_RAAR) {
+      std::vector<Iter> its;
+      while (i < ops.size() &&
+             (ops[i].kind == SPR_OP_ER || ops[i].kind == SPR_OP_HIO || ops[i].kind == SPR_OP_RAAR)) {
+        const spr_op& q = ops[i];
+        const int alg = q.kind == SPR_OP_ER ? ALG_ER : (q.kind == SPR_OP_HIO ? ALG_HIO : ALG_RAAR);
+        for (int c = 0; c < q.count; ++c) its.push_back({alg, (float)q.beta, q.chi});
+        ++i;
+      }
+      run_iterations(g, its, s);
+      continue;
+    }
+    switch (o.kind) {
+      case SPR_OP_SHRINKWRAP:
+        shrinkwrap(g, o.sigma, o.tau, s);
+        break;
+      case SPR_OP_SUPPORT_AREA:
+        if (o.which != SPR_AREA_ABS) fail(SPR_E_INVALID_ARG, "batched runs take absolute support areas only");
+        support_area(g, o.sigma, nullptr, 0, o.alpha, s);
+        break;
+      case SPR_OP_GET_ERROR:
+        get_error(g, s);
+        break;
+      default:
+        fail(SPR_E_INVALID_ARG, "batched runs take ER/HIO/RAAR, SHRINKWRAP, SUPPORT_AREA and GET_ERROR only");
+    }
+    ++i;
+  }
 }
 
 }  // namespace
@@ -644,6 +785,12 @@ void spr_ctx_destroy(spr_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->tw) (void)hipFree(kv.second);
+  for (auto& kv : ctx->ws) {
+    Workspace& w = kv.second;
+    for (void* q : {(void*)w.T, (void*)w.Y, (void*)w.err_partial, (void*)w.block_max, (void*)w.maxv,
+                    (void*)w.desc, (void*)w.slots})
+      if (q) (void)hipFree(q);
+  }
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -751,6 +898,19 @@ spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const ui
       std::vector<int> tbl(ns);
       for (size_t i = 0; i < ns; ++i) tbl[i] = (int)i;
       HIPCHK(hipMemcpy(pop->table, tbl.data(), ns * sizeof(int), hipMemcpyHostToDevice));
+      pop->desc = dalloc<SlotDesc>(ns);
+      std::vector<SlotDesc> dh(ns);
+      for (size_t i = 0; i < ns; ++i) {
+        dh[i].X = pop->X + i * nn;
+        dh[i].S = pop->S + i * pop->W;
+        dh[i].amp = shot->amp;
+        dh[i].E = pop->E + i;
+        dh[i].den = shot->den;
+        dh[i].flags = pop->flags;
+        dh[i].amp_scale = shot->amp_scale;
+        dh[i].pad = 0;
+      }
+      HIPCHK(hipMemcpy(pop->desc, dh.data(), ns * sizeof(SlotDesc), hipMemcpyHostToDevice));
       std::vector<double> e(ns, std::numeric_limits<double>::infinity());
       HIPCHK(hipMemcpy(pop->E, e.data(), ns * sizeof(double), hipMemcpyHostToDevice));
       HIPCHK(hipMemset(pop->flags, 0, sizeof(int)));
@@ -968,6 +1128,81 @@ spr_status spr_run(spr_pop* pop, const spr_sched* sched, void* hip_stream) {
     }
     pop->last = s;
     run_schedule(pop, sched, s);
+  });
+}
+
+spr_status spr_run_batch(spr_ctx* ctx, spr_pop* const* pops, const spr_sched* const* scheds, int32_t n,
+                         void* hip_stream) {
+  if (!ctx || (n > 0 && (!pops || !scheds)) || n < 0) return SPR_E_INVALID_ARG;
+  return guarded(ctx, [&] {
+    use_device(ctx);
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    std::map<int, std::vector<int>> by_size;
+    for (int i = 0; i < n; ++i) {
+      if (!pops[i] || !scheds[i]) fail(SPR_E_INVALID_ARG, "null population or schedule");
+      if (pops[i]->ctx != ctx) fail(SPR_E_INVALID_ARG, "population of another context");
+      for (int j = 0; j < i; ++j)
+        if (pops[j] == pops[i]) fail(SPR_E_INVALID_ARG, "population listed twice");
+      for (const auto& o : scheds[i]->ops)
+        if (o.scope != SPR_SCOPE_ALL) fail(SPR_E_INVALID_ARG, "batched runs act on every member (scope ALL)");
+      by_size[pops[i]->n].push_back(i);
+    }
+    for (auto& kv : by_size) {
+      const std::vector<int>& idx = kv.second;
+      const spr_sched* sch = scheds[idx[0]];
+      for (int i : idx) {
+        const auto& a = scheds[i]->ops;
+        if (a.size() != sch->ops.size()) fail(SPR_E_INVALID_ARG, "schedules of one size must be equal");
+        for (size_t k = 0; k < a.size(); ++k)
+          if (!same_op(a[k], sch->ops[k])) fail(SPR_E_INVALID_ARG, "schedules of one size must be equal");
+      }
+      // order after each population's earlier work, then gather its slots
+      size_t total = 0;
+      for (int i : idx) {
+        spr_pop* pop = pops[i];
+        if (pop->last && pop->last != s) {
+          hipEvent_t ev;
+          HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+          HIPCHK(hipEventRecord(ev, pop->last));
+          HIPCHK(hipStreamWaitEvent(s, ev, 0));
+          HIPCHK(hipEventDestroy(ev));
+        }
+        total += pop->nslots;
+      }
+      const SizeKernels* K = pops[idx[0]]->K;
+      Workspace& w = workspace(ctx, kv.first, total, K);
+      if (w.last && w.last != s) HIPCHK(hipStreamSynchronize(w.last));
+      w.last = s;
+      std::vector<int> slots;
+      size_t off = 0;
+      for (int i : idx) {
+        spr_pop* pop = pops[i];
+        HIPCHK(hipMemcpyAsync(w.desc + off, pop->desc, sizeof(SlotDesc) * pop->nslots, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(pop->last ? pop->last : s));
+        std::vector<int> t = host_table(pop);
+        for (int v : t) slots.push_back((int)off + v);
+        off += pop->nslots;
+      }
+      HIPCHK(hipMemcpyAsync(w.slots, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));  // the host slot list goes out of scope
+      Group g;
+      g.ctx = ctx;
+      g.K = K;
+      g.n = kv.first;
+      g.W = pops[idx[0]]->W;
+      g.slots = w.slots;
+      g.nm = (int)total;
+      g.desc = w.desc;
+      g.T = w.T;
+      g.Y = w.Y;
+      g.err_partial = w.err_partial;
+      g.block_max = w.block_max;
+      g.maxv = w.maxv;
+      g.timing = nullptr;
+      g.chunk = chunk_for(ctx, kv.first, (int)total);
+      run_group_schedule(g, sch, s);
+      for (int i : idx) pops[i]->last = s;
+    }
   });
 }
 
