@@ -69,6 +69,8 @@ typedef struct spr_sched spr_sched;
 /* Context: one per device; owns a stream and the per-size twiddle tables.   */
 /* ------------------------------------------------------------------------- */
 spr_status spr_ctx_create(int32_t hip_device, spr_ctx** out);
+/* Destroys the populations and shots still alive on the context, then the     */
+/* context.  Calls on destroyed handles return SPR_E_INVALID_ARG.              */
 void spr_ctx_destroy(spr_ctx* ctx);
 /* Message of the last failed call on this context ("" if none). Owned by ctx. */
 const char* spr_ctx_last_error(const spr_ctx* ctx);

@@ -5,8 +5,10 @@ arrays are torch tensors on the context's device (passed by data pointer with
 SPR_DEVICE_PTRS).  Loading fails loudly when the library has not been built.
 """
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -199,18 +201,43 @@ def _stream_ptr(stream):
     return getattr(stream, "cuda_stream", stream)
 
 
+_live_contexts = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Release every library handle before the interpreter tears down, so no
+    finaliser calls into the HIP runtime during the final collection."""
+    for ctx in list(_live_contexts):
+        try:
+            ctx.close()
+        except Exception:
+            pass
+
+
 class Context:
     def __init__(self, device=0):
         self.lib = load()
+        self._pops = weakref.WeakSet()
+        self._shots = weakref.WeakSet()
         h = C.c_void_p()
         self._check(self.lib.spr_ctx_create(int(device), C.byref(h)), ctx=None)
         self.h = h
+        _live_contexts.add(self)
 
     def _check(self, st, ctx="self"):
         check(st, self.h if ctx == "self" else ctx)
 
     def close(self):
+        """Destroy the context, closing its populations and shots first."""
         if getattr(self, "h", None):
+            for p in list(getattr(self, "_pops", ())):
+                p.close()
+            for sh in list(getattr(self, "_shots", ())):
+                try:
+                    sh.close()
+                except SprError:
+                    pass
             self.lib.spr_ctx_destroy(self.h)
             self.h = None
 
@@ -282,6 +309,7 @@ class Shot:
         ctx._check(ctx.lib.spr_shot_create(ctx.h, self.n, pa, pm, flags, C.byref(h)))
         self.h = h
         self._keep = (amp, mask)
+        ctx._shots.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -341,6 +369,7 @@ class Population:
                                                     int(seed) & 0xFFFFFFFFFFFFFFFF, int(gen_offset),
                                                     C.byref(h)))
         self.h = h
+        self.ctx._pops.add(self)
 
     def close(self):
         if getattr(self, "h", None):

@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,8 @@ struct spr_ctx {
   std::string err;
   std::map<int, float2*> tw;
   std::map<int, Workspace> ws;
+  std::set<spr_shot*> shots;  // live shots and populations created on this context
+  std::set<spr_pop*> pops;
   std::mutex mu;
 };
 
@@ -104,6 +107,7 @@ struct spr_pop {
   uint8_t* stage = nullptr;
   size_t stage_bytes = 0;
   hipStream_t last = nullptr;
+  hipEvent_t done = nullptr;  // recorded after the population's latest enqueued work
   // optional per-kernel timing: HIP events recorded around each launch
   uint32_t timing = 0;  // bit k: time kernel k
   struct Stamp {
@@ -119,6 +123,27 @@ struct spr_pop {
 struct spr_sched {
   std::vector<spr_op> ops;
 };
+
+namespace {
+// Live handles of the process.  Destroy calls on unknown (already destroyed)
+// handles are rejected instead of touching freed memory, and a context being
+// destroyed first destroys the populations and shots still created on it.
+std::mutex g_live_mu;
+std::set<const void*> g_live;
+
+void live_add(const void* h) {
+  std::lock_guard<std::mutex> g(g_live_mu);
+  g_live.insert(h);
+}
+bool live_remove(const void* h) {
+  std::lock_guard<std::mutex> g(g_live_mu);
+  return g_live.erase(h) > 0;
+}
+bool live_has(const void* h) {
+  std::lock_guard<std::mutex> g(g_live_mu);
+  return g_live.count(h) > 0;
+}
+}  // namespace
 
 namespace {
 
@@ -653,6 +678,8 @@ void destroy_pop(spr_pop* p) {
   p->stamps.clear();
   for (auto e : p->event_pool) (void)hipEventDestroy(e);
   p->event_pool.clear();
+  if (p->done) (void)hipEventDestroy(p->done);
+  p->done = nullptr;
   dfree(p->X);
   dfree(p->T);
   dfree(p->Y);
@@ -682,7 +709,7 @@ std::vector<int> host_table(spr_pop* pop) {
 }
 
 void sync_pop(spr_pop* pop) {
-  if (pop->last) HIPCHK(hipStreamSynchronize(pop->last));
+  if (pop->done) HIPCHK(hipEventSynchronize(pop->done));
   HIPCHK(hipStreamSynchronize(pop->ctx->stream));
   if (!pop->stamps.empty()) collect_stamps(pop);
 }
@@ -776,12 +803,21 @@ spr_status spr_ctx_create(int32_t hip_device, spr_ctx** out) {
     delete ctx;
     return st;
   }
+  live_add(ctx);
   *out = ctx;
   return SPR_OK;
 }
 
 void spr_ctx_destroy(spr_ctx* ctx) {
-  if (!ctx) return;
+  if (!ctx || !live_has(ctx)) return;
+  // populations first, then shots, still alive on this context
+  std::vector<spr_pop*> pops;
+  std::vector<spr_shot*> shots;
+  for (spr_pop* p : ctx->pops) pops.push_back(p);
+  for (spr_shot* sh : ctx->shots) shots.push_back(sh);
+  for (spr_pop* p : pops) spr_pop_destroy(p);
+  for (spr_shot* sh : shots) spr_shot_destroy(sh);
+  live_remove(ctx);
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->tw) (void)hipFree(kv.second);
@@ -800,6 +836,7 @@ const char* spr_ctx_last_error(const spr_ctx* ctx) { return ctx ? ctx->err.c_str
 spr_status spr_shot_create(spr_ctx* ctx, int32_t n, const float* amp, const uint8_t* mask, uint32_t flags,
                            spr_shot** out) {
   if (!ctx || !out || !amp || !mask) return SPR_E_INVALID_ARG;
+  if (!live_has(ctx)) return SPR_E_INVALID_ARG;
   *out = nullptr;
   return guarded(ctx, [&] {
     const SizeKernels* K = size_kernels(n);
@@ -843,16 +880,20 @@ spr_status spr_shot_create(spr_ctx* ctx, int32_t n, const float* amp, const uint
       delete sh;
       throw;
     }
+    live_add(sh);
+    ctx->shots.insert(sh);
     *out = sh;
   });
 }
 
 spr_status spr_shot_destroy(spr_shot* shot) {
-  if (!shot) return SPR_E_INVALID_ARG;
+  if (!shot || !live_has(shot)) return SPR_E_INVALID_ARG;
   if (shot->live > 0) {
     shot->ctx->err = "shot still has live populations";
     return SPR_E_BUSY;
   }
+  live_remove(shot);
+  shot->ctx->shots.erase(shot);
   (void)hipSetDevice(shot->ctx->device);
   dfree(shot->amp);
   delete shot;
@@ -863,6 +904,7 @@ spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const ui
                           int32_t supp_per_member, uint32_t flags, uint64_t seed, int32_t gen_offset,
                           spr_pop** out) {
   if (!shot || !out || !rho0 || !supp0) return SPR_E_INVALID_ARG;
+  if (!live_has(shot)) return SPR_E_INVALID_ARG;
   *out = nullptr;
   spr_ctx* ctx = shot->ctx;
   return guarded(ctx, [&] {
@@ -932,15 +974,19 @@ spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const ui
       delete pop;
       throw;
     }
+    HIPCHK(hipEventCreateWithFlags(&pop->done, hipEventDisableTiming));
     shot->live++;
+    live_add(pop);
+    ctx->pops.insert(pop);
     *out = pop;
   });
 }
 
 spr_status spr_pop_destroy(spr_pop* pop) {
-  if (!pop) return SPR_E_INVALID_ARG;
+  if (!pop || !live_remove(pop)) return SPR_E_INVALID_ARG;
+  pop->ctx->pops.erase(pop);
   (void)hipSetDevice(pop->ctx->device);
-  if (pop->last) (void)hipStreamSynchronize(pop->last);
+  if (pop->done) (void)hipEventSynchronize(pop->done);
   (void)hipStreamSynchronize(pop->ctx->stream);
   destroy_pop(pop);
   pop->shot->live--;
@@ -951,6 +997,7 @@ spr_status spr_pop_destroy(spr_pop* pop) {
 spr_status spr_pop_write(spr_pop* pop, const float* rho, const uint8_t* supp, const double* err,
                          uint32_t flags) {
   if (!pop) return SPR_E_INVALID_ARG;
+  if (!live_has(pop)) return SPR_E_INVALID_ARG;
   spr_ctx* ctx = pop->ctx;
   return guarded(ctx, [&] {
     use_device(ctx);
@@ -1114,20 +1161,21 @@ spr_status spr_sched_ops(const spr_sched* sched, spr_op* ops, int32_t max_ops, i
 
 spr_status spr_run(spr_pop* pop, const spr_sched* sched, void* hip_stream) {
   if (!pop || !sched) return SPR_E_INVALID_ARG;
+  if (!live_has(pop)) return SPR_E_INVALID_ARG;
   spr_ctx* ctx = pop->ctx;
   return guarded(ctx, [&] {
     use_device(ctx);
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
-    if (pop->last && pop->last != s) {
-      // order after work previously enqueued on another stream
-      hipEvent_t ev;
-      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-      HIPCHK(hipEventRecord(ev, pop->last));
-      HIPCHK(hipStreamWaitEvent(s, ev, 0));
-      HIPCHK(hipEventDestroy(ev));
-    }
+    // order after work previously enqueued on another stream
+    if (pop->last && pop->last != s) HIPCHK(hipStreamWaitEvent(s, pop->done, 0));
     pop->last = s;
-    run_schedule(pop, sched, s);
+    try {
+      run_schedule(pop, sched, s);
+    } catch (...) {
+      (void)hipEventRecord(pop->done, s);
+      throw;
+    }
+    HIPCHK(hipEventRecord(pop->done, s));
   });
 }
 
@@ -1160,13 +1208,7 @@ spr_status spr_run_batch(spr_ctx* ctx, spr_pop* const* pops, const spr_sched* co
       size_t total = 0;
       for (int i : idx) {
         spr_pop* pop = pops[i];
-        if (pop->last && pop->last != s) {
-          hipEvent_t ev;
-          HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-          HIPCHK(hipEventRecord(ev, pop->last));
-          HIPCHK(hipStreamWaitEvent(s, ev, 0));
-          HIPCHK(hipEventDestroy(ev));
-        }
+        if (pop->last && pop->last != s) HIPCHK(hipStreamWaitEvent(s, pop->done, 0));
         total += pop->nslots;
       }
       const SizeKernels* K = pops[idx[0]]->K;
@@ -1178,7 +1220,7 @@ spr_status spr_run_batch(spr_ctx* ctx, spr_pop* const* pops, const spr_sched* co
       for (int i : idx) {
         spr_pop* pop = pops[i];
         HIPCHK(hipMemcpyAsync(w.desc + off, pop->desc, sizeof(SlotDesc) * pop->nslots, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipStreamSynchronize(pop->last ? pop->last : s));
+        HIPCHK(hipEventSynchronize(pop->done));
         std::vector<int> t = host_table(pop);
         for (int v : t) slots.push_back((int)off + v);
         off += pop->nslots;
@@ -1200,14 +1242,21 @@ spr_status spr_run_batch(spr_ctx* ctx, spr_pop* const* pops, const spr_sched* co
       g.maxv = w.maxv;
       g.timing = nullptr;
       g.chunk = chunk_for(ctx, kv.first, (int)total);
-      run_group_schedule(g, sch, s);
       for (int i : idx) pops[i]->last = s;
+      try {
+        run_group_schedule(g, sch, s);
+      } catch (...) {
+        for (int i : idx) (void)hipEventRecord(pops[i]->done, s);
+        throw;
+      }
+      for (int i : idx) HIPCHK(hipEventRecord(pops[i]->done, s));
     }
   });
 }
 
 spr_status spr_sync(spr_pop* pop) {
   if (!pop) return SPR_E_INVALID_ARG;
+  if (!live_has(pop)) return SPR_E_INVALID_ARG;
   spr_ctx* ctx = pop->ctx;
   return guarded(ctx, [&] {
     use_device(ctx);
@@ -1220,6 +1269,7 @@ spr_status spr_sync(spr_pop* pop) {
 
 spr_status spr_read(spr_pop* pop, float* rho, uint8_t* supp, double* err, uint32_t flags) {
   if (!pop) return SPR_E_INVALID_ARG;
+  if (!live_has(pop)) return SPR_E_INVALID_ARG;
   spr_ctx* ctx = pop->ctx;
   return guarded(ctx, [&] {
     use_device(ctx);
@@ -1254,6 +1304,7 @@ spr_status spr_read(spr_pop* pop, float* rho, uint8_t* supp, double* err, uint32
 
 spr_status spr_read_stats(spr_pop* pop, spr_gen_stats* out, int32_t max_n, int32_t* n_out) {
   if (!pop || !n_out || (max_n > 0 && !out)) return SPR_E_INVALID_ARG;
+  if (!live_has(pop)) return SPR_E_INVALID_ARG;
   spr_ctx* ctx = pop->ctx;
   return guarded(ctx, [&] {
     use_device(ctx);
@@ -1286,6 +1337,7 @@ spr_status spr_read_stats(spr_pop* pop, spr_gen_stats* out, int32_t max_n, int32
 
 spr_status spr_read_xover(spr_pop* pop, spr_xover_info* out, int32_t max_n) {
   if (!pop || !out) return SPR_E_INVALID_ARG;
+  if (!live_has(pop)) return SPR_E_INVALID_ARG;
   spr_ctx* ctx = pop->ctx;
   return guarded(ctx, [&] {
     use_device(ctx);
@@ -1323,6 +1375,7 @@ spr_status spr_read_xover(spr_pop* pop, spr_xover_info* out, int32_t max_n) {
 
 spr_status spr_timing_enable(spr_pop* pop, int32_t enable) {
   if (!pop) return SPR_E_INVALID_ARG;
+  if (!live_has(pop)) return SPR_E_INVALID_ARG;
   return guarded(pop->ctx, [&] {
     use_device(pop->ctx);
     sync_pop(pop);
@@ -1342,6 +1395,7 @@ spr_status spr_ctx_set_cache_budget(spr_ctx* ctx, uint64_t bytes) {
 
 spr_status spr_timing_read(spr_pop* pop, int32_t kernel, int64_t* launches, double* total_ms) {
   if (!pop || !launches || !total_ms || kernel < 0 || kernel >= SPR_KERNEL_COUNT) return SPR_E_INVALID_ARG;
+  if (!live_has(pop)) return SPR_E_INVALID_ARG;
   return guarded(pop->ctx, [&] {
     use_device(pop->ctx);
     sync_pop(pop);

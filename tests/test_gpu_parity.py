@@ -423,6 +423,8 @@ def test_mpr_one_generation_small(ctx, B):
             continue  # near-tie in selection
         if abs(err[p] - out["E"][p]) <= 1e-3 * out["E"][p]:
             ok += 1
+    pop.close()
+    sh.close()
     assert ok >= 1
 
 
