@@ -31,6 +31,7 @@ struct Phase {
 // fitness goes.  A launch may mix members of several shots of one size.
 struct SlotDesc {
   float2* X;             // real-space density, N*N complex
+  float2* T;             // the member's own row-transform buffer (launches with t_by_slot)
   uint32_t* S;           // support bits, W words
   const float* amp;      // measured modulus of its shot, FFT order, sign bit set = unknown
   double* E;             // fitness slot
@@ -58,6 +59,7 @@ struct RowIngestArgs {
   const SlotDesc* desc;  // per slot
   float2* T;             // out: row-FFT of the ingested density [member][N*N]
   int W;
+  int t_by_slot;         // 1: T is desc[slot].T instead of T + member*N*N
   int mode;              // IngestMode
   Phase ph;
   const float2* tw;
@@ -67,6 +69,7 @@ struct ColProjArgs {
   const int* slots;
   int nm;
   const SlotDesc* desc;  // measured modulus of each member's shot
+  int t_by_slot;
   const float2* T;       // row-FFT'd iterate [member][N*N]
   float2* Y;             // out: column-IFFT of the projected spectrum [member][N*N]
   const float2* tw;
@@ -79,6 +82,7 @@ struct RowUpdateArgs {
   const float2* Y;       // rowFFT(P_M x) from the column pass
   float2* T;             // in: rowFFT(x) (HIO/RAAR); out: next iterate's row FFT
   int W;
+  int t_by_slot;
   const IterParam* ip;   // per-member parameters, or null: the uniform ones below
   int alg;               // Alg
   float beta;
@@ -92,6 +96,7 @@ struct ColErrArgs {
   const int* slots;
   int nm;
   const SlotDesc* desc;
+  int t_by_slot;
   const float2* T;       // row-FFT of S*x [member][N*N]
   double* partial;       // out: [member][N/C] partial sums of Xi (|X| - M)^2
   const float2* tw;

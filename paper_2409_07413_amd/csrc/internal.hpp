@@ -1,0 +1,765 @@
+// Internal declarations of the host runtime shared by the C ABI (runtime.cpp)
+// and the serving engine (server.cpp): handle structures, launch groups and
+// the enqueueing helpers.  Helpers have internal linkage (one copy per
+// translation unit); the live-handle registry is a single inline object.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels_common.hpp"
+#include "spr.h"
+
+using namespace spr;
+
+// Work buffers of batched launches, per detector size, grown on demand.
+struct Workspace {
+  size_t members = 0;
+  float2* T = nullptr;
+  float2* Y = nullptr;
+  double* err_partial = nullptr;
+  float* block_max = nullptr;
+  float* maxv = nullptr;
+  SlotDesc* desc = nullptr;
+  int* slots = nullptr;
+  hipStream_t last = nullptr;  // stream of the last batch that used these buffers
+};
+
+struct spr_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  // iteration runs are split into member chunks whose two work buffers fit in
+  // this many bytes (0: no split), so that they stay in the memory-side cache
+  size_t cache_budget = (size_t)256 << 20;
+  std::string err;
+  std::map<int, float2*> tw;
+  std::map<int, Workspace> ws;
+  std::set<spr_shot*> shots;  // live shots and populations created on this context
+  std::set<spr_pop*> pops;
+  std::mutex mu;
+};
+
+struct spr_shot {
+  spr_ctx* ctx = nullptr;
+  int n = 0;
+  const SizeKernels* K = nullptr;
+  float* amp = nullptr;  // FFT order, sign bit = unknown
+  float amp_scale = 1.f;
+  double den = 0.0;      // sum of Xi M^2
+  int live = 0;
+};
+
+struct spr_pop {
+  spr_shot* shot = nullptr;
+  spr_ctx* ctx = nullptr;
+  const SizeKernels* K = nullptr;
+  int n = 0, P = 0, nslots = 0, W = 0;
+  bool memetic = false;
+  uint64_t seed = 0;
+  int gen_offset = 0;
+  float2 *X = nullptr, *T = nullptr, *Y = nullptr;
+  uint32_t* S = nullptr;
+  double* E = nullptr;
+  int* table = nullptr;
+  SlotDesc* desc = nullptr;  // per storage slot
+  double* err_partial = nullptr;
+  float* block_max = nullptr;
+  float* maxv = nullptr;
+  int* flags = nullptr;
+  PopScalars* scal = nullptr;
+  GenStatsDev* hist = nullptr;
+  int hist_cap = 4096;
+  float2* F = nullptr;
+  float2* Cc = nullptr;
+  ArgmaxRec* amax = nullptr;
+  AlignRec* align = nullptr;
+  int* abc = nullptr;
+  int* mapprm = nullptr;
+  uint8_t* stage = nullptr;
+  size_t stage_bytes = 0;
+  hipStream_t last = nullptr;
+  hipEvent_t done = nullptr;  // recorded after the population's latest enqueued work
+  // optional per-kernel timing: HIP events recorded around each launch
+  uint32_t timing = 0;  // bit k: time kernel k
+  struct Stamp {
+    int kernel;
+    hipEvent_t start, stop;
+  };
+  std::vector<Stamp> stamps;
+  std::vector<hipEvent_t> event_pool;
+  double kernel_ms[SPR_KERNEL_COUNT] = {};
+  int64_t kernel_launches[SPR_KERNEL_COUNT] = {};
+};
+
+struct spr_sched {
+  std::vector<spr_op> ops;
+};
+
+namespace spr_live {
+// Live handles of the process.  Destroy calls on unknown (already destroyed)
+// handles are rejected instead of touching freed memory, and a context being
+// destroyed first destroys the populations and shots still created on it.
+inline std::mutex g_live_mu;
+inline std::set<const void*> g_live;
+
+inline void live_add(const void* h) {
+  std::lock_guard<std::mutex> g(g_live_mu);
+  g_live.insert(h);
+}
+inline bool live_remove(const void* h) {
+  std::lock_guard<std::mutex> g(g_live_mu);
+  return g_live.erase(h) > 0;
+}
+inline bool live_has(const void* h) {
+  std::lock_guard<std::mutex> g(g_live_mu);
+  return g_live.count(h) > 0;
+}
+}  // namespace spr_live
+using namespace spr_live;
+
+namespace {
+
+struct Fail {
+  spr_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(spr_status code, const std::string& msg) { throw Fail{code, msg}; }
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) fail(SPR_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T_>
+T_* dalloc(size_t count) {
+  void* p = nullptr;
+  size_t bytes = std::max<size_t>(count * sizeof(T_), 256);
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(SPR_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  return static_cast<T_*>(p);
+}
+
+template <class T_>
+void dfree(T_*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+template <class Fn>
+spr_status guarded(spr_ctx* ctx, Fn&& fn) {
+  try {
+    fn();
+    return SPR_OK;
+  } catch (const Fail& f) {
+    if (ctx) ctx->err = f.msg;
+    return f.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->err = "host allocation failed";
+    return SPR_E_OOM;
+  } catch (...) {
+    if (ctx) ctx->err = "unexpected internal error";
+    return SPR_E_INVALID_ARG;
+  }
+}
+
+void use_device(spr_ctx* ctx) { HIPCHK(hipSetDevice(ctx->device)); }
+
+const float2* twiddles(spr_ctx* ctx, int n) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  auto it = ctx->tw.find(n);
+  if (it != ctx->tw.end()) return it->second;
+  std::vector<float2> h(n);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int e = 0; e < n; ++e) {
+    const double ang = two_pi * (double)e / (double)n;
+    h[e] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+  }
+  float2* d = dalloc<float2>(n);
+  HIPCHK(hipMemcpy(d, h.data(), n * sizeof(float2), hipMemcpyHostToDevice));
+  ctx->tw[n] = d;
+  return d;
+}
+
+Phase phase_of(double chi) {
+  Phase p;
+  p.c = 0.f;
+  p.s = 0.f;
+  if (!(chi > 0.0) || chi >= 1.0) {
+    p.mode = PHASE_OFF;
+  } else if (chi == 0.5) {
+    p.mode = PHASE_POS;
+  } else {
+    p.mode = PHASE_CONE;
+    const double th = chi * 3.14159265358979323846264338327950288;
+    p.c = (float)std::cos(th);
+    p.s = (float)std::sin(th);
+  }
+  return p;
+}
+
+void to_host(std::vector<uint8_t>& dst, const void* src, size_t bytes, bool device) {
+  dst.resize(bytes);
+  if (device) HIPCHK(hipMemcpy(dst.data(), src, bytes, hipMemcpyDeviceToHost));
+  else std::memcpy(dst.data(), src, bytes);
+}
+
+uint8_t* stage(spr_pop* pop, size_t bytes) {
+  if (pop->stage_bytes < bytes) {
+    dfree(pop->stage);
+    pop->stage = dalloc<uint8_t>(bytes);
+    pop->stage_bytes = bytes;
+  }
+  return pop->stage;
+}
+
+struct Scope {
+  const int* slots;
+  int nm;
+};
+
+Scope scope_of(spr_pop* pop, int scope) {
+  switch (scope) {
+    case SPR_SCOPE_ALL:
+      return {pop->table, pop->nslots};
+    case SPR_SCOPE_PARENTS:
+      return {pop->table, pop->P};
+    case SPR_SCOPE_CHILDREN:
+      if (!pop->memetic) fail(SPR_E_INVALID_ARG, "children scope on a population without children");
+      return {pop->table + pop->P, pop->P};
+    default:
+      fail(SPR_E_INVALID_ARG, "unknown scope " + std::to_string(scope));
+  }
+}
+
+void launch_ok(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(SPR_E_HIP, std::string("launch of ") + what + " failed: " + hipGetErrorString(e));
+}
+
+hipEvent_t pooled_event(spr_pop* pop) {
+  if (!pop->event_pool.empty()) {
+    hipEvent_t e = pop->event_pool.back();
+    pop->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
+// Launch through `fn`, bracketing it with events when timing is enabled.
+template <class Fn>
+void timed(spr_pop* pop, int kernel, hipStream_t s, const char* what, Fn&& fn) {
+  if (!(pop->timing & (1u << kernel))) {
+    launch_ok(fn(), what);
+    return;
+  }
+  hipEvent_t a = pooled_event(pop), b = pooled_event(pop);
+  HIPCHK(hipEventRecord(a, s));
+  launch_ok(fn(), what);
+  HIPCHK(hipEventRecord(b, s));
+  pop->stamps.push_back({kernel, a, b});
+}
+
+// Fold finished stamps into the per-kernel totals (after a synchronisation).
+void collect_stamps(spr_pop* pop) {
+  for (auto& st : pop->stamps) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, st.start, st.stop));
+    pop->kernel_ms[st.kernel] += ms;
+    pop->kernel_launches[st.kernel] += 1;
+    pop->event_pool.push_back(st.start);
+    pop->event_pool.push_back(st.stop);
+  }
+  pop->stamps.clear();
+}
+
+struct Iter {
+  int alg;
+  float beta;
+  double chi;
+};
+
+// A launch group: members of one size reached through slot descriptors, and
+// the work buffers they use.  A population's scope and a batch of shots both
+// run through groups.
+struct Group {
+  spr_ctx* ctx = nullptr;
+  const SizeKernels* K = nullptr;
+  int n = 0, W = 0;
+  const int* slots = nullptr;
+  int nm = 0;
+  const SlotDesc* desc = nullptr;
+  float2* T = nullptr;           // work buffers: >= chunk members (>= nm for smoothing/fitness)
+  float2* Y = nullptr;
+  double* err_partial = nullptr; // >= nm * n / C
+  float* block_max = nullptr;    // >= nm * smoothing blocks per member
+  float* maxv = nullptr;         // >= nm
+  int* flags = nullptr;
+  spr_pop* timing = nullptr;     // where launch timings are kept (may be null)
+  int chunk = 0;                 // members per iteration launch
+  int t_by_slot = 0;             // row transforms in each member's own buffer (desc.T)
+};
+
+int chunk_for(spr_ctx* ctx, int n, int nm) {
+  if (ctx->cache_budget == 0) return nm;
+  const size_t per_member = 2 * (size_t)n * n * sizeof(float2);
+  return (int)std::min<size_t>((size_t)nm, std::max<size_t>(1, ctx->cache_budget / per_member));
+}
+
+Group pop_group(spr_pop* pop, int scope) {
+  Scope sc = scope_of(pop, scope);
+  Group g;
+  g.ctx = pop->ctx;
+  g.K = pop->K;
+  g.n = pop->n;
+  g.W = pop->W;
+  g.slots = sc.slots;
+  g.nm = sc.nm;
+  g.desc = pop->desc;
+  g.T = pop->T;
+  g.Y = pop->Y;
+  g.err_partial = pop->err_partial;
+  g.block_max = pop->block_max;
+  g.maxv = pop->maxv;
+  g.flags = pop->flags;
+  g.timing = pop;
+  g.chunk = chunk_for(pop->ctx, pop->n, sc.nm);
+  return g;
+}
+
+template <class Fn>
+void launch_timed(spr_pop* tp, int kernel, hipStream_t s, const char* what, Fn&& fn) {
+  if (tp) timed(tp, kernel, s, what, fn);
+  else launch_ok(fn(), what);
+}
+
+// One Sequence over members slots[0..nm): ingest, then per iteration a column
+// pass and a row pass.
+void run_iterations_on(const Group& g, const std::vector<Iter>& its, const int* slots, int nm, hipStream_t s) {
+  const SizeKernels* K = g.K;
+  const float2* tw = twiddles(g.ctx, g.n);
+  RowIngestArgs ia{slots, nm, g.desc, g.T, g.W, g.t_by_slot,
+                   its[0].alg == ALG_ER ? INGEST_PC : INGEST_PLAIN, phase_of(its[0].chi), tw};
+  launch_timed(g.timing, SPR_KERNEL_ROW_INGEST, s, "row_ingest", [&] { return K->row_ingest(ia, s); });
+  for (size_t i = 0; i < its.size(); ++i) {
+    ColProjArgs ca{slots, nm, g.desc, g.t_by_slot, g.T, g.Y, tw};
+    launch_timed(g.timing, SPR_KERNEL_COL_PROJ, s, "col_proj", [&] { return K->col_proj(ca, s); });
+    const bool last = i + 1 == its.size();
+    RowUpdateArgs ra;
+    ra.slots = slots;
+    ra.nm = nm;
+    ra.desc = g.desc;
+    ra.Y = g.Y;
+    ra.T = g.T;
+    ra.W = g.W;
+    ra.t_by_slot = g.t_by_slot;
+    ra.ip = nullptr;
+    ra.alg = its[i].alg;
+    ra.beta = its[i].beta;
+    ra.ph = phase_of(its[i].chi);
+    ra.out_mode = last ? OUT_REAL : (its[i + 1].alg == ALG_ER ? OUT_T_PC : OUT_T_PLAIN);
+    ra.ph_next = last ? phase_of(1.0) : phase_of(its[i + 1].chi);
+    ra.tw = tw;
+    const int kid = ra.alg == ALG_ER ? SPR_KERNEL_ROW_UPDATE_ER : SPR_KERNEL_ROW_UPDATE_IA;
+    launch_timed(g.timing, kid, s, "row_update", [&] { return K->row_update(ra, s); });
+  }
+}
+
+// Members are independent inside a Sequence, so the run may proceed chunk by
+// chunk; with a cache budget the chunk's buffers stay cache-resident across
+// its iterations.
+void run_iterations(const Group& g, const std::vector<Iter>& its, hipStream_t s) {
+  if (its.empty() || g.nm == 0) return;
+  const int chunk = g.chunk > 0 ? g.chunk : g.nm;
+  for (int c0 = 0; c0 < g.nm; c0 += chunk) run_iterations_on(g, its, g.slots + c0, std::min(chunk, g.nm - c0), s);
+}
+
+void smooth(const Group& g, double sigma, hipStream_t s) {
+  SmoothArgs ra{};
+  SmoothColArgs ca{};
+  int r = 0;
+  std::vector<double> w(1, 1.0);
+  if (sigma > 0) {
+    r = (int)std::ceil(4.0 * sigma);
+    if (r > (MAX_TAPS - 1) / 2) fail(SPR_E_INVALID_ARG, "shrink-wrap sigma above 8 pixels is not supported");
+    w.assign(2 * r + 1, 0.0);
+    double sum = 0.0;
+    for (int k = -r; k <= r; ++k) {
+      w[k + r] = std::exp(-(double)(k * k) / (2.0 * sigma * sigma));
+      sum += w[k + r];
+    }
+    for (auto& v : w) v /= sum;
+  }
+  ra.slots = g.slots;
+  ra.nm = g.nm;
+  ra.n = g.n;
+  ra.r = r;
+  ra.desc = g.desc;
+  ra.out = reinterpret_cast<float*>(g.T);
+  ca.nm = g.nm;
+  ca.n = g.n;
+  ca.r = r;
+  ca.in = ra.out;
+  ca.out = reinterpret_cast<float*>(g.Y);
+  ca.block_max = g.block_max;
+  for (int k = 0; k <= 2 * r; ++k) ra.w[k] = ca.w[k] = (float)w[k];
+  MemberMaxArgs ma{g.nm, smooth_blocks_per_member(g.n), g.block_max, g.maxv};
+  launch_ok(launch_smooth(ra, ca, ma, s), "smooth");
+}
+
+void shrinkwrap(const Group& g, double sigma, double tau, hipStream_t s) {
+  if (g.nm == 0) return;
+  smooth(g, sigma, s);
+  ThresholdArgs ta{g.slots, g.nm, g.n, g.W, reinterpret_cast<const float*>(g.Y), g.maxv, tau, g.desc};
+  launch_ok(launch_threshold(ta, s), "threshold");
+}
+
+void support_area(const Group& g, double sigma, const double* alpha_src, int alpha_index, double alpha_abs,
+                  hipStream_t s) {
+  if (g.nm == 0) return;
+  smooth(g, sigma, s);
+  TopkArgs ta{};
+  ta.slots = g.slots;
+  ta.nm = g.nm;
+  ta.n = g.n;
+  ta.W = g.W;
+  ta.in = reinterpret_cast<const float*>(g.Y);
+  ta.alpha_src = alpha_src;
+  ta.alpha_index = alpha_index;
+  ta.alpha_abs = alpha_abs;
+  ta.desc = g.desc;
+  launch_ok(launch_topk(ta, s), "topk");
+}
+
+void get_error(const Group& g, hipStream_t s) {
+  if (g.nm == 0) return;
+  const SizeKernels* K = g.K;
+  const float2* tw = twiddles(g.ctx, g.n);
+  RowIngestArgs ia{g.slots, g.nm, g.desc, g.T, g.W, g.t_by_slot, INGEST_SMASK, phase_of(1.0), tw};
+  launch_ok(K->row_ingest(ia, s), "row_ingest");
+  ColErrArgs ea{g.slots, g.nm, g.desc, g.t_by_slot, g.T, g.err_partial, tw};
+  launch_ok(K->col_err(ea, s), "col_err");
+  ErrFinalArgs fa{g.err_partial, g.n / K->C, g.nm, g.slots, g.desc};
+  launch_ok(launch_err_final(fa, s), "err_final");
+}
+
+const double* alpha_source(spr_pop* pop, const spr_op& op, int& index, double& abs_alpha) {
+  index = 0;
+  abs_alpha = 0.0;
+  if (op.which == SPR_AREA_ABS) {
+    abs_alpha = op.alpha;
+    return nullptr;
+  }
+  if (op.which == SPR_AREA_BEST || op.which == SPR_AREA_EVAL) {
+    if (!pop) fail(SPR_E_INVALID_ARG, "areas from generation statistics need a population");
+    index = op.which;
+    return pop->scal->alpha;
+  }
+  fail(SPR_E_INVALID_ARG, "unknown support-area source");
+}
+
+void need_memetic(spr_pop* pop, const char* what) {
+  if (!pop->memetic) fail(SPR_E_INVALID_ARG, std::string(what) + " needs a population created with SPR_POP_MEMETIC");
+}
+
+void crossover(spr_pop* pop, const spr_op& op, hipStream_t s) {
+  need_memetic(pop, "CROSSOVER");
+  if (pop->P < 4) fail(SPR_E_INVALID_ARG, "crossover needs P >= 4");
+  const SizeKernels* K = pop->K;
+  const int n = pop->n, P = pop->P;
+  const size_t nn = (size_t)n * n;
+  const float2* tw = twiddles(pop->ctx, n);
+  int t_min = op.t_min > 0 ? op.t_min : 4;
+  int t_max = op.t_max > 0 ? op.t_max : std::max(t_min, n / 8);
+  if (t_max < t_min) fail(SPR_E_INVALID_ARG, "crossover t_max < t_min");
+  if (!(op.c_p >= 0.0 && op.c_p <= 1.0)) fail(SPR_E_INVALID_ARG, "crossover probability outside [0, 1]");
+  const int blocks = n / K->RWI;
+  if (!pop->F) {
+    pop->F = dalloc<float2>((size_t)P * nn);
+    pop->Cc = dalloc<float2>((size_t)6 * P * nn);
+    pop->amax = dalloc<ArgmaxRec>((size_t)6 * P * blocks);
+    pop->align = dalloc<AlignRec>((size_t)3 * P);
+    pop->abc = dalloc<int>((size_t)3 * P);
+    pop->mapprm = dalloc<int>((size_t)5 * P);
+  }
+  // parent spectra F[p] (unitary)
+  RowFftArgs r1{pop->table, pop->table, P, pop->X, pop->T, -1, 1.f, tw};
+  launch_ok(K->row_fft(r1, s), "row_fft");
+  ColFftArgs c1{pop->table, nullptr, P, pop->T, pop->F, -1, 1.f / (float)n, tw};
+  launch_ok(K->col_fft(c1, s), "col_fft");
+  ChoiceArgs ch{P, op.gen, t_min, t_max, pop->seed, pop->abc, pop->mapprm};
+  launch_ok(launch_choice(ch, s), "choice");
+  ColCorrArgs cc{3 * P, pop->abc, pop->F, pop->shot->amp, pop->Cc, tw};
+  launch_ok(K->col_corr(cc, s), "col_corr");
+  RowArgmaxArgs am{6 * P, pop->Cc, pop->amax, tw};
+  launch_ok(K->row_argmax(am, s), "row_argmax");
+  AlignArgs al{3 * P, blocks, n, pop->amax, pop->align};
+  launch_ok(launch_align(al, s), "align");
+  double thr = std::floor(op.c_p * 4294967296.0);
+  thr = std::min(std::max(thr, 0.0), 4294967296.0);
+  ColMixArgs mx{P, pop->abc, pop->mapprm, pop->align, pop->F, pop->table, pop->T, (float)op.c_w,
+                pop->seed, op.gen, (uint64_t)thr, 1.f / (float)n, tw};
+  launch_ok(K->col_mix(mx, s), "col_mix");
+  RowFftArgs r2{pop->table + P, pop->table + P, P, pop->T, pop->X, +1, 1.f, tw};
+  launch_ok(K->row_fft(r2, s), "row_fft");
+  SupportMixArgs sm{P, n, pop->W, pop->table, pop->abc, pop->align, pop->S};
+  launch_ok(launch_support_mix(sm, s), "support_mix");
+}
+
+GenStatsDev* record(spr_pop* pop, int gen) {
+  int g = gen - 1;
+  if (g < 0) g = 0;
+  return pop->hist + (g % pop->hist_cap);
+}
+
+void validate_op(const spr_op& o) {
+  switch (o.kind) {
+    case SPR_OP_ER:
+    case SPR_OP_HIO:
+    case SPR_OP_RAAR:
+      if (o.count < 0) fail(SPR_E_INVALID_ARG, "negative iteration count");
+      if (o.kind != SPR_OP_ER && !(o.beta > 0.0 && o.beta <= 1.0)) fail(SPR_E_INVALID_ARG, "beta outside (0, 1]");
+      break;
+    case SPR_OP_SHRINKWRAP:
+      if (!(o.sigma >= 0.0 && o.sigma <= 8.0)) fail(SPR_E_INVALID_ARG, "sigma outside [0, 8]");
+      if (!(o.tau >= 0.0 && o.tau <= 1.0)) fail(SPR_E_INVALID_ARG, "tau outside [0, 1]");
+      break;
+    case SPR_OP_SUPPORT_AREA:
+      if (!(o.sigma >= 0.0 && o.sigma <= 8.0)) fail(SPR_E_INVALID_ARG, "sigma outside [0, 8]");
+      if (o.which < 0 || o.which > 2) fail(SPR_E_INVALID_ARG, "unknown area source");
+      break;
+    case SPR_OP_GET_ERROR:
+      break;
+    case SPR_OP_STATS:
+      if (o.gen < 1 || o.gens < 1) fail(SPR_E_INVALID_ARG, "STATS needs gen >= 1 and gens >= 1");
+      break;
+    case SPR_OP_CROSSOVER:
+      if (o.gen < 1) fail(SPR_E_INVALID_ARG, "CROSSOVER needs gen >= 1");
+      if (!(o.c_w >= 0.0 && o.c_w <= 2.0)) fail(SPR_E_INVALID_ARG, "c_w outside [0, 2]");
+      break;
+    case SPR_OP_SELECT:
+      if (o.gen < 1) fail(SPR_E_INVALID_ARG, "SELECT needs gen >= 1");
+      break;
+    default:
+      fail(SPR_E_INVALID_ARG, "unknown op kind " + std::to_string(o.kind));
+  }
+  if (o.scope < 0 || o.scope > 2) fail(SPR_E_INVALID_ARG, "unknown scope");
+}
+
+void run_schedule(spr_pop* pop, const spr_sched* sch, hipStream_t s) {
+  const auto& ops = sch->ops;
+  for (const auto& o : ops) {
+    if ((o.kind == SPR_OP_CROSSOVER || o.kind == SPR_OP_SELECT || o.kind == SPR_OP_STATS ||
+         o.scope == SPR_SCOPE_CHILDREN) && !pop->memetic)
+      fail(SPR_E_INVALID_ARG, "schedule needs a population created with SPR_POP_MEMETIC");
+    if (o.kind == SPR_OP_CROSSOVER && pop->P < 4) fail(SPR_E_INVALID_ARG, "crossover needs P >= 4");
+  }
+  size_t i = 0;
+  while (i < ops.size()) {
+    const spr_op& o = ops[i];
+    if (o.kind == SPR_OP_ER || o.kind == SPR_OP_HIO || o.kind == SPR_OP_RAAR) {
+      std::vector<Iter> its;
+      const int scope = o.scope;
+      while (i < ops.size() &&
+             (ops[i].kind == SPR_OP_ER || ops[i].kind == SPR_OP_HIO || ops[i].kind == SPR_OP_RAAR) &&
+             ops[i].scope == scope) {
+        const spr_op& q = ops[i];
+        const int alg = q.kind == SPR_OP_ER ? ALG_ER : (q.kind == SPR_OP_HIO ? ALG_HIO : ALG_RAAR);
+        for (int c = 0; c < q.count; ++c) its.push_back({alg, (float)q.beta, q.chi});
+        ++i;
+      }
+      run_iterations(pop_group(pop, scope), its, s);
+      continue;
+    }
+    switch (o.kind) {
+      case SPR_OP_SHRINKWRAP:
+        shrinkwrap(pop_group(pop, o.scope), o.sigma, o.tau, s);
+        break;
+      case SPR_OP_SUPPORT_AREA: {
+        int idx;
+        double ab;
+        const double* src = alpha_source(pop, o, idx, ab);
+        support_area(pop_group(pop, o.scope), o.sigma, src, idx, ab, s);
+        break;
+      }
+      case SPR_OP_GET_ERROR:
+        get_error(pop_group(pop, o.scope), s);
+        break;
+      case SPR_OP_STATS: {
+        need_memetic(pop, "STATS");
+        StatsArgs sa{pop->P, pop->W, o.gen, o.gens, pop->table, pop->E, pop->S, pop->scal, record(pop, o.gen)};
+        launch_ok(launch_stats(sa, s), "stats");
+        break;
+      }
+      case SPR_OP_CROSSOVER:
+        crossover(pop, o, s);
+        break;
+      case SPR_OP_SELECT: {
+        need_memetic(pop, "SELECT");
+        SelectArgs se{pop->P, o.gen, pop->table, pop->E, record(pop, o.gen)};
+        launch_ok(launch_select(se, s), "select");
+        break;
+      }
+      default:
+        fail(SPR_E_INVALID_ARG, "unknown op kind");
+    }
+    ++i;
+  }
+}
+
+void sched_at(int g, int G, int j, int j_er, int j_end, double sigma, double sigma_end, double tau,
+              double tau_end, int& jg, int& jer, double& sg, double& tg) {
+  const double t = G <= 1 ? 0.0 : (double)(g - 1) / (double)(G - 1);
+  jg = (int)std::floor((double)j + t * (double)(j_end - j) + 0.5);
+  jer = j + j_er - jg;
+  sg = sigma + t * (sigma_end - sigma);
+  tg = tau + t * (tau_end - tau);
+}
+
+spr_op make_op(int kind) {
+  spr_op o;
+  std::memset(&o, 0, sizeof(o));
+  o.kind = kind;
+  o.chi = 0.5;
+  return o;
+}
+
+void push_seq(std::vector<spr_op>& ops, int alg, int jg, int jer, double beta, double chi) {
+  if (jg > 0) {
+    spr_op o = make_op(alg == SPR_ALG_RAAR ? SPR_OP_RAAR : SPR_OP_HIO);
+    o.count = jg;
+    o.beta = beta;
+    o.chi = chi;
+    ops.push_back(o);
+  }
+  if (jer > 0) {
+    spr_op o = make_op(SPR_OP_ER);
+    o.count = jer;
+    o.chi = chi;
+    ops.push_back(o);
+  }
+}
+
+void destroy_pop(spr_pop* p) {
+  for (auto& st : p->stamps) {
+    (void)hipEventDestroy(st.start);
+    (void)hipEventDestroy(st.stop);
+  }
+  p->stamps.clear();
+  for (auto e : p->event_pool) (void)hipEventDestroy(e);
+  p->event_pool.clear();
+  if (p->done) (void)hipEventDestroy(p->done);
+  p->done = nullptr;
+  dfree(p->X);
+  dfree(p->T);
+  dfree(p->Y);
+  dfree(p->S);
+  dfree(p->E);
+  dfree(p->table);
+  dfree(p->desc);
+  dfree(p->err_partial);
+  dfree(p->block_max);
+  dfree(p->maxv);
+  dfree(p->flags);
+  dfree(p->scal);
+  dfree(p->hist);
+  dfree(p->F);
+  dfree(p->Cc);
+  dfree(p->amax);
+  dfree(p->align);
+  dfree(p->abc);
+  dfree(p->mapprm);
+  dfree(p->stage);
+}
+
+std::vector<int> host_table(spr_pop* pop) {
+  std::vector<int> t(pop->nslots);
+  HIPCHK(hipMemcpy(t.data(), pop->table, sizeof(int) * pop->nslots, hipMemcpyDeviceToHost));
+  return t;
+}
+
+void sync_pop(spr_pop* pop) {
+  if (pop->done) HIPCHK(hipEventSynchronize(pop->done));
+  HIPCHK(hipStreamSynchronize(pop->ctx->stream));
+  if (!pop->stamps.empty()) collect_stamps(pop);
+}
+
+Workspace& workspace(spr_ctx* ctx, int n, size_t members, const SizeKernels* K) {
+  Workspace& w = ctx->ws[n];
+  if (w.members >= members) return w;
+  HIPCHK(hipDeviceSynchronize());  // the old buffers may still be in use
+  for (void* q : {(void*)w.T, (void*)w.Y, (void*)w.err_partial, (void*)w.block_max, (void*)w.maxv,
+                  (void*)w.desc, (void*)w.slots})
+    if (q) (void)hipFree(q);
+  w = Workspace();
+  const size_t nn = (size_t)n * n;
+  w.T = dalloc<float2>(members * nn);
+  w.Y = dalloc<float2>(members * nn);
+  w.err_partial = dalloc<double>(members * (n / K->C));
+  w.block_max = dalloc<float>(members * smooth_blocks_per_member(n));
+  w.maxv = dalloc<float>(members);
+  w.desc = dalloc<SlotDesc>(members);
+  w.slots = dalloc<int>(members);
+  w.members = members;
+  return w;
+}
+
+bool same_op(const spr_op& a, const spr_op& b) {
+  return a.kind == b.kind && a.count == b.count && a.scope == b.scope && a.which == b.which && a.gen == b.gen &&
+         a.gens == b.gens && a.t_min == b.t_min && a.t_max == b.t_max && a.beta == b.beta && a.chi == b.chi &&
+         a.sigma == b.sigma && a.tau == b.tau && a.alpha == b.alpha && a.c_p == b.c_p && a.c_w == b.c_w;
+}
+
+// Populations of one size advancing through one schedule together: every
+// operation is a single launch over all their members.
+void run_group_schedule(const Group& g, const spr_sched* sch, hipStream_t s) {
+  const auto& ops = sch->ops;
+  size_t i = 0;
+  while (i < ops.size()) {
+    const spr_op& o = ops[i];
+    if (o.kind == SPR_OP_ER || o.kind == SPR_OP_HIO || o.kind == SPR_OP_RAAR) {
+      std::vector<Iter> its;
+      while (i < ops.size() &&
+             (ops[i].kind == SPR_OP_ER || ops[i].kind == SPR_OP_HIO || ops[i].kind == SPR_OP_RAAR)) {
+        const spr_op& q = ops[i];
+        const int alg = q.kind == SPR_OP_ER ? ALG_ER : (q.kind == SPR_OP_HIO ? ALG_HIO : ALG_RAAR);
+        for (int c = 0; c < q.count; ++c) its.push_back({alg, (float)q.beta, q.chi});
+        ++i;
+      }
+      run_iterations(g, its, s);
+      continue;
+    }
+    switch (o.kind) {
+      case SPR_OP_SHRINKWRAP:
+        shrinkwrap(g, o.sigma, o.tau, s);
+        break;
+      case SPR_OP_SUPPORT_AREA:
+        if (o.which != SPR_AREA_ABS) fail(SPR_E_INVALID_ARG, "batched runs take absolute support areas only");
+        support_area(g, o.sigma, nullptr, 0, o.alpha, s);
+        break;
+      case SPR_OP_GET_ERROR:
+        get_error(g, s);
+        break;
+      default:
+        fail(SPR_E_INVALID_ARG, "batched runs take ER/HIO/RAAR, SHRINKWRAP, SUPPORT_AREA and GET_ERROR only");
+    }
+    ++i;
+  }
+}
+
+}  // namespace
+

@@ -135,9 +135,10 @@ __global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
     v[m] = z;
   }
   fft<N, -1, RowL>(v, lds + r * NR, t, a.tw);
+  float2* Tw = a.t_by_slot ? d.T + off : a.T + toff;
   if (valid) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) a.T[toff + t + T * m] = v[m];
+    for (int m = 0; m < E; ++m) Tw[t + T * m] = v[m];
   }
 }
 
@@ -150,9 +151,9 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
   const int c = tid % C, t = tid / C;
   const TileId id = col_tile_id();
   const int col = id.tile * C + c;
-  const float2* src = a.T + (size_t)id.img * NN;
   float2* dst = a.Y + (size_t)id.img * NN;
   const SlotDesc& d = a.desc[a.slots[id.img]];
+  const float2* src = a.t_by_slot ? d.T : a.T + (size_t)id.img * NN;
   const float* amp = d.amp;
   const float amp_scale = d.amp_scale;
   float2 v[E];
@@ -208,12 +209,13 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   }
 
   const bool ia = alg != ALG_ER;
+  float2* Tw = a.t_by_slot ? d.T + off : a.T + toff;
   float2 y[E], x[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) y[m] = valid ? a.Y[toff + t + T * m] : make_float2(0.f, 0.f);
   if (ia) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) x[m] = valid ? a.T[toff + t + T * m] : make_float2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) x[m] = valid ? Tw[t + T * m] : make_float2(0.f, 0.f);
   }
   TwSet<N> ws;
   load_twiddle_set<N>(ws, t, a.tw);
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   fft<N, -1, RowL>(xn, l, t, a.tw, ws);
   if (valid) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) a.T[toff + t + T * m] = xn[m];
+    for (int m = 0; m < E; ++m) Tw[t + T * m] = xn[m];
   }
 }
 
@@ -280,8 +282,8 @@ __global__ __launch_bounds__(C* T) void k_col_err(ColErrArgs a) {
   const int c = tid % C, t = tid / C;
   const TileId id = col_tile_id();
   const int col = id.tile * C + c;
-  const float2* src = a.T + (size_t)id.img * NN;
   const SlotDesc& d = a.desc[a.slots[id.img]];
+  const float2* src = a.t_by_slot ? d.T : a.T + (size_t)id.img * NN;
   float2 v[E];
   float mv[E];
 #pragma unroll
