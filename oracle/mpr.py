@@ -47,6 +47,27 @@ def to_fft_order(img):
     return np.fft.ifftshift(np.asarray(img))
 
 
+def random_phase_start(M, known, P, seed):
+    """Random-phase starting densities rho0_p = F^-1[Xi * M * exp(i phi_p)].
+
+    This start is not the paper's Initialize (projected spheres, initialisation
+    appendix); it is the classic random-phase start of the iterative methods
+    the paper builds on.  The phases come from the shared counter generator so
+    that both implementations produce the same start: at FFT-order pixel k
+    (row-major) of member p, u = Philox draw k of (seed, INIT, generation 0,
+    member p) and phi = 2 pi (u + 1/2) / 2^32.  Unknown pixels get 0.
+    """
+    M = np.asarray(M, dtype=np.float64)
+    n = M.shape[0]
+    out = np.empty((P, n, n), dtype=np.complex128)
+    two_pi = 2.0 * np.pi
+    for p in range(P):
+        u = philox.draws_array(seed, philox.PURPOSE_INIT, 0, p, n * n).astype(np.float64)
+        phi = (two_pi * (u + 0.5) / 4294967296.0).reshape(n, n)
+        out[p] = ifft2(np.where(known, M, 0.0) * np.exp(1j * phi))
+    return out
+
+
 # ----------------------------------------------------------------------------
 # Projectors
 # ----------------------------------------------------------------------------

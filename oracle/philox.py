@@ -32,6 +32,7 @@ W1 = 0xBB67AE85
 PURPOSE_CHOICE = 1    # RandomChoice: draws 0..2
 PURPOSE_MAPPARAM = 2  # CrossoverMap tile size, grid shift, rotation: draws 0..4
 PURPOSE_TILE = 3      # CrossoverMap tile election: block = tile key, word 0
+PURPOSE_INIT = 4      # random-phase start: draw = FFT-order pixel index, generation 0
 
 
 def _round(c, k):
@@ -75,3 +76,37 @@ def bernoulli_threshold(prob):
     """Integer threshold t with Bernoulli(prob) <=> u32 < t (t may equal 2^32)."""
     t = int(prob * 4294967296.0)
     return max(0, min(t, 1 << 32))
+
+
+def philox4x32_10_array(c0, c1, c2, c3, key):
+    """Element-wise Philox4x32-10 over arrays of counter words (NumPy uint64
+    arithmetic, the same rounds as ``philox4x32_10``).  Returns four uint32
+    arrays."""
+    import numpy as np
+
+    m = np.uint64(MASK32)
+    c = [np.asarray(v, dtype=np.uint64) & m for v in (c0, c1, c2, c3)]
+    c = np.broadcast_arrays(*c)
+    c = [np.array(v, dtype=np.uint64) for v in c]
+    k0, k1 = np.uint64(int(key[0]) & MASK32), np.uint64(int(key[1]) & MASK32)
+    for r in range(10):
+        if r:
+            k0 = np.uint64((int(k0) + W0) & MASK32)
+            k1 = np.uint64((int(k1) + W1) & MASK32)
+        p0 = np.uint64(M0) * c[0]
+        p1 = np.uint64(M1) * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & m
+        hi1, lo1 = p1 >> np.uint64(32), p1 & m
+        c = [(hi1 ^ c[1] ^ k0) & m, lo1, (hi0 ^ c[3] ^ k1) & m, lo0]
+    return [v.astype(np.uint32) for v in c]
+
+
+def draws_array(seed, purpose, generation, member, count):
+    """Draws 0..count-1 of the stream (seed, purpose, generation, member)."""
+    import numpy as np
+
+    idx = np.arange(count, dtype=np.uint64)
+    blocks = idx >> np.uint64(2)
+    words = philox4x32_10_array(blocks, int(member), int(generation), purpose, seed_key(seed))
+    out = np.stack(words, axis=-1)  # [draw][word of the draw's block]
+    return out[np.arange(count), (idx & np.uint64(3)).astype(np.int64)]

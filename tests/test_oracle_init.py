@@ -1,0 +1,80 @@
+"""Pins of the oracle's vectorised Philox and of the random-phase start."""
+
+import numpy as np
+
+from oracle import mpr, philox
+
+
+def test_vectorised_philox_matches_scalar_rounds():
+    rng = np.random.default_rng(5)
+    c = rng.integers(0, 2**32, size=(4, 64), dtype=np.uint64)
+    key = (0x9A3F17C2, 0x01234567)
+    out = philox.philox4x32_10_array(c[0], c[1], c[2], c[3], key)
+    for i in range(64):
+        ref = philox.philox4x32_10(tuple(int(v) for v in c[:, i]), key)
+        assert [int(o[i]) for o in out] == ref
+
+
+def test_vectorised_philox_known_answers():
+    # the same Random123 known-answer vectors that pin the scalar rounds
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        ctr, key, exp = v[0:4], v[4:6], v[6:10]
+        out = philox.philox4x32_10_array(*[np.array([x], dtype=np.uint64) for x in ctr], key)
+        assert [int(o[0]) for o in out] == exp
+
+
+def test_draws_array_follows_the_draw_convention():
+    d = philox.draws_array(2**40 + 17, philox.PURPOSE_INIT, 0, 5, 23)
+    assert [int(x) for x in d] == [philox.draw(2**40 + 17, philox.PURPOSE_INIT, 0, 5, i) for i in range(23)]
+
+
+def _shot(n, seed=3):
+    rng = np.random.default_rng(seed)
+    M = np.abs(rng.standard_normal((n, n))) + 0.1
+    known = np.ones((n, n), bool)
+    known[:3, :3] = False
+    known[-2:, :] = False
+    return M, known
+
+
+def test_random_phase_start_has_measured_modulus():
+    M, known = _shot(24)
+    x0 = mpr.random_phase_start(M, known, 3, seed=11)
+    for p in range(3):
+        X = mpr.fft2(x0[p])
+        assert np.allclose(np.abs(X)[known], M[known], rtol=1e-12, atol=1e-12)
+        assert np.abs(X[~known]).max() < 1e-12
+        # a point of the modulus set is left unchanged by P_M
+        assert np.allclose(mpr.proj_modulus(x0[p], M, known), x0[p], atol=1e-12)
+
+
+def test_random_phase_start_phases_uniform_and_member_distinct():
+    n = 64
+    M = np.ones((n, n))
+    known = np.ones((n, n), bool)
+    x0 = mpr.random_phase_start(M, known, 2, seed=7)
+    ph = np.angle(mpr.fft2(x0[0])).ravel() % (2 * np.pi)
+    hist, _ = np.histogram(ph, bins=16, range=(0, 2 * np.pi))
+    exp = ph.size / 16
+    chi2 = float(((hist - exp) ** 2 / exp).sum())
+    assert chi2 < 37.7  # 99.9% quantile of chi^2 with 15 degrees of freedom
+    assert not np.allclose(x0[0], x0[1])
+    again = mpr.random_phase_start(M, known, 2, seed=7)
+    np.testing.assert_array_equal(again, x0)
+    other = mpr.random_phase_start(M, known, 1, seed=8)
+    assert not np.allclose(other[0], x0[0])
+
+
+def test_random_phase_start_angle_matches_the_generator():
+    # at one known pixel the phase is the generator's draw mapped to [0, 2 pi)
+    M, known = _shot(16)
+    x0 = mpr.random_phase_start(M, known, 2, seed=99)
+    X = mpr.fft2(x0[1])
+    k = 5 * 16 + 9
+    u = philox.draw(99, philox.PURPOSE_INIT, 0, 1, k)
+    phi = 2 * np.pi * (u + 0.5) / 2**32
+    assert abs(np.exp(1j * np.angle(X.ravel()[k])) - np.exp(1j * phi)) < 1e-12
