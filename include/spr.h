@@ -59,6 +59,7 @@ typedef int32_t spr_status;
 #define SPR_LAYOUT_FFT 0x2u    /* amplitude/mask already in FFT order (DC at [0][0]) */
 #define SPR_POP_MEMETIC 0x4u   /* population also holds P children (needed by crossover/select) */
 #define SPR_READ_CHILDREN 0x8u /* spr_read/spr_pop_write act on the child population */
+#define SPR_INIT_RANDOM_PHASE 0x10u /* spr_pop_create: generate the random-phase start on the device */
 
 typedef struct spr_ctx spr_ctx;
 typedef struct spr_shot spr_shot;
@@ -103,6 +104,11 @@ spr_status spr_shot_destroy(spr_shot* shot);
 /* the memetic operators; gen_offset is the number of generations already run  */
 /* (resume).  SPR_POP_MEMETIC reserves the P children of Alg. crossover.       */
 /* Crossover needs P >= 4 (three distinct other parents).                      */
+/* With SPR_INIT_RANDOM_PHASE rho0 is ignored (may be NULL) and member p starts */
+/* at rho0_p = F^-1[Xi M e^{i phi}] (unitary inverse DFT), phi = 2 pi (u+1/2)/2^32 */
+/* with u = Philox draw k of (seed, purpose 4, generation 0, member p) at the   */
+/* FFT-order pixel k (row-major): the classic random-phase start; the paper's   */
+/* own Initialize (projected spheres, initialisation appendix) is separate.    */
 /* ------------------------------------------------------------------------- */
 spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const uint8_t* supp0,
                           int32_t supp_per_member, uint32_t flags, uint64_t seed,
@@ -259,6 +265,95 @@ spr_status spr_timing_read(spr_pop* pop, int32_t kernel, int64_t* launches, doub
 /* allowed to alias): forward exp(-2 pi i ...) / N, inverse exp(+...) / N.     */
 spr_status spr_fft2(spr_ctx* ctx, int32_t n, int32_t batch, const float* in, float* out,
                     int32_t inverse, void* hip_stream);
+
+/* ------------------------------------------------------------------------- */
+/* Serving: a request loop for streamed single shots of mixed detector sizes.  */
+/* Every admitted shot keeps its P-member population resident on the device   */
+/* and runs the server's schedule; the shots admitted at any moment advance   */
+/* together in ticks (continuous batching): in each tick every resident shot  */
+/* runs its next sequence of iterations and the support/fitness steps that    */
+/* follow it, with the members of all shots of one size and step batched into */
+/* the same launches.  Requests are admitted first come, first served, when a */
+/* shot slot and a range of the server's device-memory budget large enough    */
+/* for the shot's footprint (amplitudes, densities, row transforms, support    */
+/* bits, errors and its result record) are free; memory and slot return when  */
+/* the result has reached host memory.  Members only interact with their own  */
+/* shot's data, so a result is the same whichever shots share its ticks.      */
+/* ------------------------------------------------------------------------- */
+typedef struct spr_server spr_server;
+
+#define SPR_SERVER_MANUAL 0x1u      /* no engine thread: the caller drives spr_server_step */
+#define SPR_SERVER_ALL_MEMBERS 0x2u /* results carry every member, not only the best one */
+
+typedef struct spr_server_cfg {
+  uint64_t hbm_budget;    /* device bytes held by the server (work buffers + admitted shots) */
+  int32_t max_shots;      /* shots resident at once */
+  int32_t P;              /* members per shot */
+  const spr_sched* sched; /* per-shot schedule: ER/HIO/RAAR, SHRINKWRAP, SUPPORT_AREA with */
+                          /* SPR_AREA_ABS and GET_ERROR, scope ALL (copied at create)      */
+  uint32_t flags;         /* SPR_SERVER_* */
+  int32_t max_inflight;   /* ticks enqueued ahead of the device (0: 2) */
+  uint64_t max_queue;     /* waiting requests before submit returns SPR_E_BUSY (0: unbounded) */
+  double sim_bytes_per_s; /* ctx NULL only: modelled device bandwidth of the simulated executor */
+  double sim_launch_s;    /* ctx NULL only: modelled cost of one launch */
+} spr_server_cfg;
+
+typedef struct spr_shot_desc {
+  int32_t n;              /* detector size */
+  const float* amp;       /* N*N float32 M = sqrt(I), centred layout unless SPR_LAYOUT_FFT */
+  const uint8_t* mask;    /* N*N, 1 = measured */
+  const uint8_t* supp0;   /* N*N (broadcast) or P*N*N (supp_per_member) initial supports */
+  int32_t supp_per_member;
+  uint32_t flags;         /* SPR_LAYOUT_FFT; SPR_INIT_RANDOM_PHASE (else rho0 is the start) */
+  const float* rho0;      /* P*N*N complex start, or NULL with SPR_INIT_RANDOM_PHASE */
+  uint64_t seed;          /* keys the random-phase start */
+  double arrival;         /* < 0: stamped at submit; else the arrival time on the server clock */
+                          /* (the simulated executor admits no request before its arrival)  */
+} spr_shot_desc;
+
+typedef struct spr_result {
+  float* rho;             /* caller buffer or NULL: members * N*N complex */
+  uint8_t* supp;          /* caller buffer or NULL: members * N*N */
+  double* err;            /* caller buffer or NULL: P fitness values (Eq. error_calc) */
+  int32_t n, P;
+  int32_t members;        /* 1 (best member) or P (SPR_SERVER_ALL_MEMBERS) */
+  int32_t best;           /* member with the lowest error, ties to the lower index */
+  double t_arrival, t_admit, t_finish; /* seconds on the server clock */
+  spr_status status;      /* SPR_OK, or SPR_E_NUMERIC when a fitness value was not finite */
+  int32_t pad;
+} spr_result;
+
+typedef struct spr_server_stats {
+  double now;             /* server clock, seconds since create */
+  int64_t queued, active, finishing, done;
+  int64_t admitted, completed, ticks, launches;
+  int64_t max_active;     /* most shots resident at once */
+  uint64_t bytes_capacity, bytes_in_use, bytes_peak; /* shot memory of the budget */
+} spr_server_stats;
+
+/* ctx NULL selects the simulated executor: no device work, time advances by   */
+/* the modelled cost of each tick (for testing the scheduling logic; results  */
+/* carry no data).  Requires SPR_SERVER_MANUAL.  SPR_E_INVALID_ARG when the    */
+/* budget cannot hold the work buffers.                                        */
+spr_status spr_server_create(spr_ctx* ctx, const spr_server_cfg* cfg, spr_server** out);
+/* Copies the request and returns at once with its ticket.  SPR_E_ADMISSION    */
+/* when the shot could never fit the budget, SPR_E_BUSY when the queue is      */
+/* full, SPR_E_UNSUPPORTED_SIZE, SPR_E_NUMERIC / SPR_E_INVALID_ARG for bad data. */
+spr_status spr_server_submit(spr_server* sv, const spr_shot_desc* shot, uint64_t* ticket);
+/* SPR_E_NOT_READY until the shot is done; then fills *res (copying into its   */
+/* non-NULL buffers) and forgets the ticket.  Unknown ticket: SPR_E_INVALID_ARG. */
+spr_status spr_server_poll(spr_server* sv, uint64_t ticket, spr_result* res);
+/* SPR_SERVER_MANUAL: one round of the engine (collect finished shots, admit,  */
+/* plan and enqueue one tick).  *pending = requests not yet done.              */
+spr_status spr_server_step(spr_server* sv, int64_t* pending);
+/* Wait until every submitted request is done (driving the engine in manual    */
+/* mode); SPR_E_NOT_READY after timeout_s seconds (< 0: no limit).             */
+spr_status spr_server_drain(spr_server* sv, double timeout_s);
+spr_status spr_server_stats_get(spr_server* sv, spr_server_stats* st);
+const char* spr_server_last_error(const spr_server* sv);
+/* Stops the engine, waits for the device and frees everything (pending       */
+/* results included).                                                          */
+spr_status spr_server_destroy(spr_server* sv);
 
 #ifdef __cplusplus
 }

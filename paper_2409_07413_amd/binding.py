@@ -19,11 +19,15 @@ SPR_OK = 0
 STATUS = {0: "SPR_OK", -1: "SPR_E_INVALID_ARG", -2: "SPR_E_UNSUPPORTED_SIZE", -3: "SPR_E_OOM",
           -4: "SPR_E_HIP", -5: "SPR_E_NOT_READY", -6: "SPR_E_BUSY", -7: "SPR_E_NUMERIC",
           -8: "SPR_E_ADMISSION"}
+STATUS_NOT_READY = -5
+E_BUSY = -6
+E_ADMISSION = -8
 
 DEVICE_PTRS = 0x1
 LAYOUT_FFT = 0x2
 POP_MEMETIC = 0x4
 READ_CHILDREN = 0x8
+INIT_RANDOM_PHASE = 0x10
 
 OP_ER, OP_HIO, OP_RAAR, OP_SHRINKWRAP, OP_SUPPORT_AREA, OP_GET_ERROR, OP_STATS, OP_CROSSOVER, OP_SELECT = range(1, 10)
 ALG_HIO, ALG_RAAR = 1, 2
@@ -73,11 +77,41 @@ class XoverInfo(C.Structure):
                 ("phase", (C.c_float * 2) * 3), ("peak", (C.c_float * 2) * 3)]
 
 
+class ServerCfg(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("max_shots", C.c_int32), ("P", C.c_int32),
+                ("sched", C.c_void_p), ("flags", C.c_uint32), ("max_inflight", C.c_int32),
+                ("max_queue", C.c_uint64), ("sim_bytes_per_s", C.c_double), ("sim_launch_s", C.c_double)]
+
+
+class ShotDesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("amp", C.c_void_p), ("mask", C.c_void_p), ("supp0", C.c_void_p),
+                ("supp_per_member", C.c_int32), ("flags", C.c_uint32), ("rho0", C.c_void_p),
+                ("seed", C.c_uint64), ("arrival", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("rho", C.c_void_p), ("supp", C.c_void_p), ("err", C.c_void_p), ("n", C.c_int32),
+                ("P", C.c_int32), ("members", C.c_int32), ("best", C.c_int32), ("t_arrival", C.c_double),
+                ("t_admit", C.c_double), ("t_finish", C.c_double), ("status", C.c_int32), ("pad", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("now", C.c_double), ("queued", C.c_int64), ("active", C.c_int64), ("finishing", C.c_int64),
+                ("done", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64), ("ticks", C.c_int64),
+                ("launches", C.c_int64), ("max_active", C.c_int64), ("bytes_capacity", C.c_uint64),
+                ("bytes_in_use", C.c_uint64), ("bytes_peak", C.c_uint64)]
+
+
+SERVER_MANUAL = 0x1
+SERVER_ALL_MEMBERS = 0x2
+
 EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_supported_size",
            "spr_shot_create", "spr_shot_destroy", "spr_pop_create", "spr_pop_destroy", "spr_pop_write",
            "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
            "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
-           "spr_timing_enable", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch"]
+           "spr_timing_enable", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch",
+           "spr_server_create", "spr_server_submit", "spr_server_poll", "spr_server_step", "spr_server_drain",
+           "spr_server_stats_get", "spr_server_last_error", "spr_server_destroy"]
 
 KERNEL_ROW_INGEST, KERNEL_COL_PROJ, KERNEL_ROW_UPDATE_ER, KERNEL_ROW_UPDATE_IA = range(4)
 KERNEL_NAMES = {0: "k_row_ingest", 1: "k_col_proj", 2: "k_row_update(ER)", 3: "k_row_update(HIO/RAAR)"}
@@ -113,6 +147,14 @@ def _proto(lib):
         "spr_timing_read": (i32, [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
         "spr_ctx_set_cache_budget": (i32, [vp, C.c_uint64]),
         "spr_run_batch": (i32, [vp, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), i32, vp]),
+        "spr_server_create": (i32, [vp, C.POINTER(ServerCfg), pp]),
+        "spr_server_submit": (i32, [vp, C.POINTER(ShotDesc), C.POINTER(C.c_uint64)]),
+        "spr_server_poll": (i32, [vp, C.c_uint64, C.POINTER(Result)]),
+        "spr_server_step": (i32, [vp, C.POINTER(C.c_int64)]),
+        "spr_server_drain": (i32, [vp, C.c_double]),
+        "spr_server_stats_get": (i32, [vp, C.POINTER(ServerStats)]),
+        "spr_server_last_error": (C.c_char_p, [vp]),
+        "spr_server_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -220,6 +262,7 @@ class Context:
         self.lib = load()
         self._pops = weakref.WeakSet()
         self._shots = weakref.WeakSet()
+        self._servers = weakref.WeakSet()
         h = C.c_void_p()
         self._check(self.lib.spr_ctx_create(int(device), C.byref(h)), ctx=None)
         self.h = h
@@ -231,6 +274,8 @@ class Context:
     def close(self):
         """Destroy the context, closing its populations and shots first."""
         if getattr(self, "h", None):
+            for sv in list(getattr(self, "_servers", ())):
+                sv.close()
             for p in list(getattr(self, "_pops", ())):
                 p.close()
             for sh in list(getattr(self, "_shots", ())):
@@ -323,8 +368,9 @@ class Shot:
         except Exception:
             pass
 
-    def population(self, rho0, supp0, memetic=False, seed=0, gen_offset=0):
-        return Population(self, rho0, supp0, memetic, seed, gen_offset)
+    def population(self, rho0, supp0, memetic=False, seed=0, gen_offset=0, P=None):
+        """rho0 None: P members from the device-side random-phase start keyed by seed."""
+        return Population(self, rho0, supp0, memetic, seed, gen_offset, P)
 
 
 class Schedule:
@@ -353,17 +399,25 @@ class Schedule:
 
 
 class Population:
-    def __init__(self, shot, rho0, supp0, memetic, seed, gen_offset):
+    def __init__(self, shot, rho0, supp0, memetic, seed, gen_offset, P=None):
         self.shot = shot
         self.ctx = shot.ctx
-        self.P = int(rho0.shape[0])
         self.n = shot.n
-        pr, dr = _ptr(rho0)
         ps, ds = _ptr(supp0)
+        flags = POP_MEMETIC if memetic else 0
+        if rho0 is None:
+            if P is None:
+                raise ValueError("P is needed for the random-phase start")
+            self.P = int(P)
+            pr, dr = None, ds
+            flags |= INIT_RANDOM_PHASE
+        else:
+            self.P = int(rho0.shape[0])
+            pr, dr = _ptr(rho0)
         if dr != ds:
             raise ValueError("rho0 and supp0 must both be host or both be device arrays")
         per_member = 1 if supp0.ndim == 3 else 0
-        flags = (DEVICE_PTRS if dr else 0) | (POP_MEMETIC if memetic else 0)
+        flags |= DEVICE_PTRS if dr else 0
         h = C.c_void_p()
         self.ctx._check(self.ctx.lib.spr_pop_create(shot.h, self.P, pr, ps, per_member, flags,
                                                     int(seed) & 0xFFFFFFFFFFFFFFFF, int(gen_offset),
@@ -450,3 +504,102 @@ def op(kind, **kw):
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+class Server:
+    """Serving engine (continuous batching of streamed shots).
+
+    ctx None selects the simulated executor (modelled time, no device work;
+    manual stepping only).  submit() returns a ticket; poll(ticket) returns
+    None until the shot is done, then a dict with the result and its
+    arrival/admit/finish times (seconds on the server clock)."""
+
+    def __init__(self, ctx, sched, P, hbm_budget, max_shots, manual=False, all_members=False,
+                 max_inflight=0, max_queue=0, sim_bytes_per_s=0.0, sim_launch_s=0.0):
+        self.lib = load()
+        self.ctx = ctx
+        self.P = int(P)
+        self.all_members = bool(all_members)
+        cfg = ServerCfg(int(hbm_budget), int(max_shots), self.P, sched.h.value if isinstance(sched.h, C.c_void_p)
+                        else sched.h, (SERVER_MANUAL if manual else 0) | (SERVER_ALL_MEMBERS if all_members else 0),
+                        int(max_inflight), int(max_queue), float(sim_bytes_per_s), float(sim_launch_s))
+        h = C.c_void_p()
+        st = self.lib.spr_server_create(ctx.h if ctx else None, C.byref(cfg), C.byref(h))
+        check(st, ctx.h if ctx else None)
+        self.h = h
+        self._n = {}
+        if ctx is not None:
+            ctx._servers.add(self)
+
+    def _check(self, st):
+        if st != SPR_OK:
+            raw = self.lib.spr_server_last_error(self.h)
+            raise SprError(st, raw.decode() if raw else "")
+
+    def submit(self, amp, mask, supp0, rho0=None, seed=0, fft_order=False, arrival=None):
+        """Queue one shot (host arrays); rho0 None = device random-phase start."""
+        n = int(amp.shape[0])
+        amp = np.ascontiguousarray(amp, dtype=np.float32)
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        supp0 = np.ascontiguousarray(supp0, dtype=np.uint8)
+        flags = LAYOUT_FFT if fft_order else 0
+        if rho0 is None:
+            flags |= INIT_RANDOM_PHASE
+            rp = None
+        else:
+            rho0 = np.ascontiguousarray(rho0, dtype=np.complex64)
+            rp = rho0.ctypes.data
+        d = ShotDesc(n, amp.ctypes.data, mask.ctypes.data, supp0.ctypes.data, 1 if supp0.ndim == 3 else 0,
+                     flags, rp, int(seed) & 0xFFFFFFFFFFFFFFFF, -1.0 if arrival is None else float(arrival))
+        t = C.c_uint64()
+        self._check(self.lib.spr_server_submit(self.h, C.byref(d), C.byref(t)))
+        self._n[t.value] = n
+        return t.value
+
+    def poll(self, ticket, want_data=True):
+        if ticket not in self._n:
+            r = Result()
+            self._check(self.lib.spr_server_poll(self.h, int(ticket), C.byref(r)))
+        n = self._n[ticket]
+        m = self.P if self.all_members else 1
+        rho = np.empty((m, n, n), dtype=np.complex64) if want_data else None
+        supp = np.empty((m, n, n), dtype=np.uint8) if want_data else None
+        err = np.empty(self.P, dtype=np.float64)
+        r = Result(rho.ctypes.data if want_data else None, supp.ctypes.data if want_data else None,
+                   err.ctypes.data)
+        st = self.lib.spr_server_poll(self.h, int(ticket), C.byref(r))
+        if st == STATUS_NOT_READY:
+            return None
+        self._check(st)
+        del self._n[ticket]
+        return {"rho": rho, "supp": supp.astype(bool) if want_data else None, "err": err, "best": r.best,
+                "members": r.members, "t_arrival": r.t_arrival, "t_admit": r.t_admit, "t_finish": r.t_finish,
+                "status": r.status}
+
+    def step(self):
+        p = C.c_int64()
+        self._check(self.lib.spr_server_step(self.h, C.byref(p)))
+        return p.value
+
+    def drain(self, timeout=-1.0):
+        st = self.lib.spr_server_drain(self.h, float(timeout))
+        if st == STATUS_NOT_READY:
+            return False
+        self._check(st)
+        return True
+
+    def stats(self):
+        s = ServerStats()
+        self._check(self.lib.spr_server_stats_get(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.spr_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

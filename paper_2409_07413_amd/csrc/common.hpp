@@ -196,7 +196,7 @@ const SizeKernels* size_kernels(int n);
 // Weyl key increments 0x9E3779B9, 0xBB67AE85.  counter = (block, member,
 // generation, purpose); key = (seed low, seed high).
 // ---------------------------------------------------------------------------
-enum Purpose : uint32_t { PURPOSE_CHOICE = 1, PURPOSE_MAPPARAM = 2, PURPOSE_TILE = 3 };
+enum Purpose : uint32_t { PURPOSE_CHOICE = 1, PURPOSE_MAPPARAM = 2, PURPOSE_TILE = 3, PURPOSE_INIT = 4 };
 
 struct U4 {
   uint32_t v[4];

@@ -44,8 +44,9 @@ struct spr_ctx {
   std::string err;
   std::map<int, float2*> tw;
   std::map<int, Workspace> ws;
-  std::set<spr_shot*> shots;  // live shots and populations created on this context
+  std::set<spr_shot*> shots;  // live shots, populations and servers created on this context
   std::set<spr_pop*> pops;
+  std::set<spr_server*> servers;
   std::mutex mu;
 };
 
@@ -215,6 +216,28 @@ void to_host(std::vector<uint8_t>& dst, const void* src, size_t bytes, bool devi
   dst.resize(bytes);
   if (device) HIPCHK(hipMemcpy(dst.data(), src, bytes, hipMemcpyDeviceToHost));
   else std::memcpy(dst.data(), src, bytes);
+}
+
+// Measured modulus in FFT order with the mask in the sign bit (known <=>
+// stored value >= +0), and the normaliser sum of Xi M^2 of Eq. error_calc.
+double encode_shot(int n, const float* a, const uint8_t* mask, uint32_t flags, float* enc) {
+  double den = 0.0;
+  const int h = (flags & SPR_LAYOUT_FFT) ? 0 : n / 2;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      // FFT-order index (i, j) reads the centred image at (i + n/2, j + n/2) mod n
+      const size_t src = (size_t)((i + h) % n) * n + (size_t)((j + h) % n);
+      const float v = a[src];
+      if (mask[src] != 0) {
+        if (!std::isfinite(v) || v < 0.f) fail(SPR_E_NUMERIC, "measured amplitude is negative or not finite");
+        enc[(size_t)i * n + j] = v == 0.f ? 0.f : v;
+        den += (double)v * (double)v;
+      } else {
+        enc[(size_t)i * n + j] = -0.f;
+      }
+    }
+  if (!(den > 0.0)) fail(SPR_E_INVALID_ARG, "sum of measured M^2 must be positive");
+  return den;
 }
 
 uint8_t* stage(spr_pop* pop, size_t bytes) {
@@ -455,6 +478,20 @@ void get_error(const Group& g, hipStream_t s) {
   launch_ok(K->col_err(ea, s), "col_err");
   ErrFinalArgs fa{g.err_partial, g.n / K->C, g.nm, g.slots, g.desc};
   launch_ok(launch_err_final(fa, s), "err_final");
+}
+
+// Random-phase start of P members stored contiguously at X: Fourier-side
+// values, then the unitary inverse 2D transform in place.
+void random_phase_start(spr_ctx* ctx, const SizeKernels* K, int n, int P, const float* amp, float amp_scale,
+                        uint64_t seed, float2* X, hipStream_t s) {
+  if (P == 0) return;
+  const float2* tw = twiddles(ctx, n);
+  InitPhaseArgs ia{P, n, amp, amp_scale, seed, X};
+  launch_ok(launch_init_phase(ia, s), "init_phase");
+  ColFftArgs c{nullptr, nullptr, P, X, X, +1, 1.f, tw};
+  launch_ok(K->col_fft(c, s), "col_fft");
+  RowFftArgs r{nullptr, nullptr, P, X, X, +1, 1.f / (float)n, tw};
+  launch_ok(K->row_fft(r, s), "row_fft");
 }
 
 const double* alpha_source(spr_pop* pop, const spr_op& op, int& index, double& abs_alpha) {

@@ -2,6 +2,8 @@
 // thresholds, the exact top-k support (UpdateSupportSize), population
 // statistics, RandomChoice / crossover-map parameters, Reshift decisions,
 // support mixing, Select, and support packing.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels_common.hpp"
 
@@ -519,6 +521,62 @@ __global__ void k_unpack(PackArgs a) {
   a.bytes[gid] = bit_at(Sm, idx) ? 1 : 0;
 }
 
+// One Philox block per thread gives the phases of four consecutive pixels.
+// The angle and its sine/cosine are taken in FP64 and rounded once.
+__global__ void k_init_phase(InitPhaseArgs a) {
+  const long nn = (long)a.n * a.n;
+  const long nb = (nn + 3) / 4;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = blockIdx.y;
+  if (gid >= nb || m >= a.nm) return;
+  const U4 u = philox4x32_10((uint32_t)gid, (uint32_t)m, 0u, PURPOSE_INIT, (uint32_t)a.seed,
+                             (uint32_t)(a.seed >> 32));
+  float2* X = a.X + (size_t)m * nn;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const long k = gid * 4 + w;
+    if (k >= nn) break;
+    const float av = a.amp[k];
+    const double v = signbit(av) ? 0.0 : (double)av * (double)a.amp_scale;
+    const double phi = 6.283185307179586476925 * ((double)u.v[w] + 0.5) * 2.3283064365386962890625e-10;
+    double sn, cs;
+    sincos(phi, &sn, &cs);
+    X[k] = make_float2((float)(v * cs), (float)(v * sn));
+  }
+}
+
+__global__ void k_gather_best(GatherBestArgs a) {
+  __shared__ int sbest;
+  if (threadIdx.x == 0) {
+    int b = 0;
+    double bv = a.E[0];
+    for (int p = 1; p < a.P; ++p) {
+      const double e = a.E[p];
+      // strict: ties keep the lower index; a NaN never replaces, and is replaced
+      if (e < bv || (bv != bv && e == e)) {
+        bv = e;
+        b = p;
+      }
+    }
+    sbest = b;
+  }
+  __syncthreads();
+  const int best = sbest;
+  const long nn = (long)a.n * a.n;
+  const size_t offX = 32 + 8 * (size_t)a.P;
+  const size_t offS = offX + 8 * (size_t)nn;
+  float2* X = reinterpret_cast<float2*>(a.out + offX);
+  uint32_t* S = reinterpret_cast<uint32_t*>(a.out + offS);
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < nn) X[gid] = a.X[(size_t)best * nn + gid];
+  if (gid < a.W) S[gid] = a.S[(size_t)best * a.W + gid];
+  if (gid < a.P) reinterpret_cast<double*>(a.out + 32)[gid] = a.E[gid];
+  if (gid == 0) {
+    reinterpret_cast<int*>(a.out)[0] = best;
+    reinterpret_cast<int*>(a.out)[1] = *a.status;
+  }
+}
+
 inline unsigned blocks_for(long n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
 
 }  // namespace
@@ -573,6 +631,18 @@ hipError_t launch_support_mix(const SupportMixArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_support_mix, dim3(blocks_for((long)a.P * a.W, 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
+hipError_t launch_init_phase(const InitPhaseArgs& a, hipStream_t s) {
+  const long nb = ((long)a.n * a.n + 3) / 4;
+  hipLaunchKernelGGL(k_init_phase, dim3(blocks_for(nb, 256), a.nm), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_best(const GatherBestArgs& a, hipStream_t s) {
+  const long work = std::max<long>((long)a.n * a.n, std::max(a.W, a.P));
+  hipLaunchKernelGGL(k_gather_best, dim3(blocks_for(work, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack(const PackArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_pack, dim3(blocks_for((long)a.nm * a.W, 256)), dim3(256), 0, s, a);
   return hipGetLastError();

@@ -117,6 +117,28 @@ struct PackArgs {
   uint32_t* S;
 };
 
+// Random-phase start, Fourier side: X[m][k] = Xi M e^{i phi}, phi drawn from
+// (seed, INIT, generation 0, member m, draw k) at FFT-order pixel k.
+struct InitPhaseArgs {
+  int nm, n;
+  const float* amp;  // FFT order, sign bit set = unknown
+  float amp_scale;
+  uint64_t seed;
+  float2* X;         // [member][n*n], contiguous
+};
+
+// Best member of one shot (lowest E, ties to the lower index, non-finite E
+// never chosen over a finite one) gathered into one contiguous record:
+// [int best][int status][24 bytes pad][double E[P]][float2 X[n*n]][uint32 S[W]].
+struct GatherBestArgs {
+  int P, n, W;
+  const double* E;      // [P]
+  const float2* X;      // [P][n*n]
+  const uint32_t* S;    // [P][W]
+  const int* status;
+  unsigned char* out;
+};
+
 // Blocks per member of the column smoothing pass (size of the block-max array).
 int smooth_blocks_per_member(int n);
 
@@ -132,5 +154,7 @@ hipError_t launch_align(const AlignArgs& a, hipStream_t s);
 hipError_t launch_support_mix(const SupportMixArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 hipError_t launch_unpack(const PackArgs& a, hipStream_t s);
+hipError_t launch_init_phase(const InitPhaseArgs& a, hipStream_t s);
+hipError_t launch_gather_best(const GatherBestArgs& a, hipStream_t s);
 
 }  // namespace spr

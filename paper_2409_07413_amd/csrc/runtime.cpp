@@ -74,7 +74,9 @@ spr_status spr_ctx_create(int32_t hip_device, spr_ctx** out) {
 
 void spr_ctx_destroy(spr_ctx* ctx) {
   if (!ctx || !live_has(ctx)) return;
-  // populations first, then shots, still alive on this context
+  // servers, populations, then shots still alive on this context
+  std::vector<spr_server*> servers(ctx->servers.begin(), ctx->servers.end());
+  for (spr_server* sv : servers) spr_server_destroy(sv);
   std::vector<spr_pop*> pops;
   std::vector<spr_shot*> shots;
   for (spr_pop* p : ctx->pops) pops.push_back(p);
@@ -111,25 +113,8 @@ spr_status spr_shot_create(spr_ctx* ctx, int32_t n, const float* amp, const uint
     std::vector<uint8_t> ab, mb;
     to_host(ab, amp, nn * sizeof(float), dev);
     to_host(mb, mask, nn, dev);
-    const float* a = reinterpret_cast<const float*>(ab.data());
     std::vector<float> enc(nn);
-    double den = 0.0;
-    const int h = (flags & SPR_LAYOUT_FFT) ? 0 : n / 2;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        // FFT-order index (i, j) reads the centred image at (i + n/2, j + n/2) mod n
-        const size_t src = (size_t)((i + h) % n) * n + (size_t)((j + h) % n);
-        const bool known = mb[src] != 0;
-        const float v = a[src];
-        if (known) {
-          if (!std::isfinite(v) || v < 0.f) fail(SPR_E_NUMERIC, "measured amplitude is negative or not finite");
-          enc[(size_t)i * n + j] = v == 0.f ? 0.f : v;
-          den += (double)v * (double)v;
-        } else {
-          enc[(size_t)i * n + j] = -0.f;
-        }
-      }
-    if (!(den > 0.0)) fail(SPR_E_INVALID_ARG, "sum of measured M^2 must be positive");
+    const double den = encode_shot(n, reinterpret_cast<const float*>(ab.data()), mb.data(), flags, enc.data());
     spr_shot* sh = new spr_shot();
     sh->ctx = ctx;
     sh->n = n;
@@ -167,7 +152,8 @@ spr_status spr_shot_destroy(spr_shot* shot) {
 spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const uint8_t* supp0,
                           int32_t supp_per_member, uint32_t flags, uint64_t seed, int32_t gen_offset,
                           spr_pop** out) {
-  if (!shot || !out || !rho0 || !supp0) return SPR_E_INVALID_ARG;
+  const bool init_phase = (flags & SPR_INIT_RANDOM_PHASE) != 0;
+  if (!shot || !out || (!rho0 && !init_phase) || !supp0) return SPR_E_INVALID_ARG;
   if (!live_has(shot)) return SPR_E_INVALID_ARG;
   *out = nullptr;
   spr_ctx* ctx = shot->ctx;
@@ -219,14 +205,20 @@ spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const ui
       HIPCHK(hipMemcpy(pop->desc, dh.data(), ns * sizeof(SlotDesc), hipMemcpyHostToDevice));
       std::vector<double> e(ns, std::numeric_limits<double>::infinity());
       HIPCHK(hipMemcpy(pop->E, e.data(), ns * sizeof(double), hipMemcpyHostToDevice));
-      HIPCHK(hipMemset(pop->flags, 0, sizeof(int)));
-      HIPCHK(hipMemset(pop->scal, 0, sizeof(PopScalars)));
-      HIPCHK(hipMemset(pop->hist, 0, sizeof(GenStatsDev) * pop->hist_cap));
-      HIPCHK(hipMemset(pop->S, 0, ns * pop->W * sizeof(uint32_t)));
-      HIPCHK(hipMemset(pop->X, 0, ns * nn * sizeof(float2)));
+      // on the context stream, ahead of the start-up kernels below
+      hipStream_t cs = ctx->stream;
+      HIPCHK(hipMemsetAsync(pop->flags, 0, sizeof(int), cs));
+      HIPCHK(hipMemsetAsync(pop->scal, 0, sizeof(PopScalars), cs));
+      HIPCHK(hipMemsetAsync(pop->hist, 0, sizeof(GenStatsDev) * pop->hist_cap, cs));
+      HIPCHK(hipMemsetAsync(pop->S, 0, ns * pop->W * sizeof(uint32_t), cs));
+      HIPCHK(hipMemsetAsync(pop->X, 0, ns * nn * sizeof(float2), cs));
+      HIPCHK(hipStreamSynchronize(cs));
       const bool dev = flags & SPR_DEVICE_PTRS;
-      HIPCHK(hipMemcpy(pop->X, rho0, (size_t)P * nn * sizeof(float2),
-                       dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+      if (init_phase) random_phase_start(ctx, pop->K, pop->n, P, shot->amp, shot->amp_scale, seed, pop->X,
+                                         ctx->stream);
+      else
+        HIPCHK(hipMemcpy(pop->X, rho0, (size_t)P * nn * sizeof(float2),
+                         dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
       const size_t sb = supp_per_member ? (size_t)P * nn : nn;
       uint8_t* st = stage(pop, sb);
       HIPCHK(hipMemcpy(st, supp0, sb, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
