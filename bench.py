@@ -70,7 +70,7 @@ def kernel_sources_digest():
     """Digest of the sources that define the iteration kernels and their launch."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("fft.hpp", "kernels_n.hip", "common.hpp", "runtime.cpp"):
+    for f in ("fft.hpp", "kernels_n.hip", "common.hpp", "internal.hpp", "runtime.cpp"):
         h.update(open(os.path.join(ROOT, "paper_2409_07413_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -123,6 +123,139 @@ def _oracle_member(a):
     return 0
 
 
+# ---------------------------------------------------------------------------
+# Serving: streamed single shots of mixed sizes (Poisson arrivals)
+# ---------------------------------------------------------------------------
+SERVE_SIZES = (256, 384, 512, 768, 1024)
+SERVE_P = 32
+SERVE_G = 25          # 25 blocks of 20 iterations = 500 per member
+SERVE_POOL = 3        # distinct synthetic shots per size, drawn at random per arrival
+
+
+def serve_sched(B, ctx):
+    """Per shot: 25 blocks of HIO (beta 0.9)^j then ER^(20-j), j 16 -> 0, each
+    followed by shrink-wrap (sigma 2 -> 1, tau 0.10); GetError at the end."""
+    return B.sched_plain(ctx, alg=B.ALG_HIO, G=SERVE_G, j=16, j_er=4, j_end=0, beta=0.9, chi=0.5,
+                         sigma=2.0, sigma_end=1.0, tau=0.10, tau_end=0.10)
+
+
+def serving_pool():
+    """5 ellipses (semi-axes 4-15 px) in a 40-px disk, 1e6 photons, 8x8 beamstop;
+    start support a centred 48 x 48 square; random-phase starts on the device."""
+    from paper_2409_07413_amd import synth
+    pool, supp = {}, {}
+    for n in SERVE_SIZES:
+        pool[n] = []
+        for k in range(SERVE_POOL):
+            sh = synth.shot(n, "ellipses", 1005 + 101 * k + n, 1e6, beamstop=8, gap=0)
+            pool[n].append((sh["amp"].astype(np.float32), sh["mask"].astype(np.uint8)))
+        supp[n] = synth.centred_square(n, 48).astype(np.uint8)
+    return pool, supp
+
+
+def serving_stream(rate, count, seed=4005):
+    rng = np.random.default_rng([seed, int(round(rate * 1000)), count])
+    gaps = rng.exponential(1.0 / rate, size=count)
+    gaps[0] = 0.0
+    return np.cumsum(gaps), rng.choice(SERVE_SIZES, size=count), rng.integers(0, SERVE_POOL, size=count)
+
+
+def _latency_summary(lat, first_arrival, finishes, count, member_px):
+    lat = np.asarray(lat)
+    span = max(finishes) - first_arrival
+    return {"shots": count, "shots_per_s": count / span, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "max_ms": float(lat.max() * 1e3), "makespan_s": span,
+            "member_iterations_per_s": SERVE_P * 20 * SERVE_G * count / span,
+            "iteration_pixels_per_s": SERVE_P * 20 * SERVE_G * member_px / span}
+
+
+def run_served(ctx, B, pool, supp, stream, max_shots, budget, warm=True):
+    """Served form: continuous batching in the library's engine thread."""
+    arrivals, sizes, picks = stream
+    sched = serve_sched(B, ctx)
+    sv = B.Server(ctx, sched, P=SERVE_P, hbm_budget=budget, max_shots=max_shots)
+    if warm:  # one shot of every size through the engine first (pinned pool, kernels)
+        ts = [sv.submit(pool[n][0][0], pool[n][0][1], supp[n], seed=1) for n in SERVE_SIZES]
+        sv.drain(300.0)
+        for t in ts:
+            sv.poll(t, want_data=False)
+    off = sv.stats()["now"] - time.perf_counter()
+    t0 = time.perf_counter() + 0.02
+    tickets = []
+    for i, (a, n, k) in enumerate(zip(arrivals, sizes, picks)):
+        target = t0 + a
+        d = target - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        amp, mask = pool[int(n)][int(k)]
+        tickets.append(sv.submit(amp, mask, supp[int(n)], seed=5000 + i, arrival=target + off))
+    if not sv.drain(600.0):
+        raise RuntimeError("served stream did not finish")
+    res = [sv.poll(t, want_data=False) for t in tickets]
+    st = sv.stats()
+    sv.close()
+    sched.close()
+    lat = [r["t_finish"] - r["t_arrival"] for r in res]
+    out = _latency_summary(lat, min(r["t_arrival"] for r in res), [r["t_finish"] for r in res], len(res),
+                           float(sum(int(n) ** 2 for n in sizes)))
+    out.update({"max_resident": st["max_active"], "ticks": st["ticks"], "launches": st["launches"],
+                "peak_shot_bytes": st["bytes_peak"], "max_shots": max_shots})
+    return out
+
+
+def run_plain_fifo(ctx, B, pool, supp, stream, warm=True):
+    """Comparator: one shot at a time in arrival order (FIFO), the same kernels
+    through spr_run, a fresh shot and population per request, no batching."""
+    arrivals, sizes, picks = stream
+    sched = serve_sched(B, ctx)
+
+    def one(n, amp, mask, seed):
+        sh = ctx.shot(amp, mask)
+        pop = sh.population(None, supp[n], seed=seed, P=SERVE_P)
+        pop.run(sched)
+        err = pop.errors()
+        pop.read_member(int(np.argmin(err)))
+        pop.close()
+        sh.close()
+
+    if warm:
+        for n in SERVE_SIZES:
+            one(n, pool[n][0][0], pool[n][0][1], 1)
+    t0 = time.perf_counter() + 0.02
+    lat, fin = [], []
+    for i, (a, n, k) in enumerate(zip(arrivals, sizes, picks)):
+        target = t0 + a
+        d = target - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        amp, mask = pool[int(n)][int(k)]
+        one(int(n), amp, mask, 5000 + i)
+        f = time.perf_counter()
+        lat.append(f - target)
+        fin.append(f - t0)
+    sched.close()
+    return _latency_summary(lat, 0.0, fin, len(lat), float(sum(int(n) ** 2 for n in sizes)))
+
+
+def serving_leg(ctx, B, rates, count, max_shots, budget, forms=("served", "plain"), log=None):
+    pool, supp = serving_pool()
+    out = []
+    for rate, cnt in zip(rates, count):
+        stream = serving_stream(rate, cnt)
+        rec = {"rate_per_s": rate}
+        for form in forms:
+            if form == "served":
+                rec["served"] = run_served(ctx, B, pool, supp, stream, max_shots, budget)
+            else:
+                rec["plain"] = run_plain_fifo(ctx, B, pool, supp, stream)
+            if log:
+                log(f"serving rate {rate}/s, {cnt} shots, {form}: "
+                    + json.dumps({k: round(v, 3) for k, v in rec[form].items() if isinstance(v, float)}))
+        out.append(rec)
+    return out
+
+
 def copy_calibration():
     """A plain copy kernel of known size: 256 MiB read + 256 MiB written per
     launch (torch copy_, a hipMemcpy device-to-device kernel).  Its FETCH_SIZE /
@@ -154,9 +287,39 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of 256 MiB (reference for HBM counters) and exit")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving leg (one JSON line per rate on stderr, summary on stdout)")
+    ap.add_argument("--serve-rates", type=str, default="50,5",
+                    help="Poisson arrival rates (shots/s) of the serving leg")
+    ap.add_argument("--serve-shots", type=str, default="60,20", help="shots per rate")
+    ap.add_argument("--serve-max-shots", type=int, default=8, help="shots resident at once in the server")
+    ap.add_argument("--serve-budget-gib", type=float, default=48.0, help="device memory of the server")
+    ap.add_argument("--serve-forms", type=str, default="served,plain")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    counts = [int(c) for c in args.serve_shots.split(",")]
+    if len(counts) == 1:
+        counts = counts * len(rates)
+    forms = tuple(args.serve_forms.split(","))
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    if args.serve_only:
+        import torch  # noqa: F401
+        from paper_2409_07413_amd import binding as B
+        ctx = B.Context(0)
+        res = serving_leg(ctx, B, rates, counts, args.serve_max_shots, int(args.serve_budget_gib * (1 << 30)),
+                          forms, log)
+        print(json.dumps({"serving": res, "config": {
+            "workload": "serving stream: Poisson arrivals, sizes uniform over 256..1024 (5 sizes), "
+                        "5 ellipses in a 40-px disk, 1e6 photons, 8x8 beamstop, P=32, 500 iterations",
+            "max_shots": args.serve_max_shots, "budget_gib": args.serve_budget_gib}}), flush=True)
+        ctx.close()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus above 1 is not "
@@ -231,7 +394,7 @@ def main():
     pct_hbm = step_bytes / wall / (HBM_PEAK_GBS * 1e9)
     dom = B.KERNEL_COL_PROJ
     out = {
-        "metric": "member-iterations/s at 512^2 pop 64 (% HBM peak)",
+        "metric": "member-iterations/s at 512^2 pop 64 (% HBM peak); p50/p99 shot latency",
         "value": value,
         "unit": "member-iterations/s",
         "n_gpus": 1,
@@ -263,6 +426,17 @@ def main():
     }
     pop.close()
     shot.close()
+    if not args.no_serve:
+        srv = serving_leg(ctx, B, rates, counts, args.serve_max_shots, int(args.serve_budget_gib * (1 << 30)),
+                          forms, log)
+        out["serving"] = {"workload": "Poisson arrivals, sizes uniform over {256,384,512,768,1024}, "
+                                      "5 ellipses in a 40-px disk, 1e6 photons, 8x8 beamstop, P=32, "
+                                      "500 iterations (25 x [HIO^j ER^(20-j), shrink-wrap]) + GetError; "
+                                      "served = continuous batching, plain = FIFO one shot at a time",
+                          "max_shots": args.serve_max_shots, "rates": srv}
+        if "served" in srv[0]:
+            out["shot_latency_p50_ms"] = srv[0]["served"]["p50_ms"]
+            out["shot_latency_p99_ms"] = srv[0]["served"]["p99_ms"]
     if base is not None:
         out["cpu_baseline"] = base
         out["gpu_over_oracle"] = value / base["value"]

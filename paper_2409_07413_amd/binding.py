@@ -110,7 +110,7 @@ EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_suppo
            "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
            "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
            "spr_timing_enable", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch",
-           "spr_server_create", "spr_server_submit", "spr_server_poll", "spr_server_step", "spr_server_drain",
+           "spr_read_member", "spr_server_create", "spr_server_submit", "spr_server_poll", "spr_server_step", "spr_server_drain",
            "spr_server_stats_get", "spr_server_last_error", "spr_server_destroy"]
 
 KERNEL_ROW_INGEST, KERNEL_COL_PROJ, KERNEL_ROW_UPDATE_ER, KERNEL_ROW_UPDATE_IA = range(4)
@@ -147,6 +147,7 @@ def _proto(lib):
         "spr_timing_read": (i32, [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
         "spr_ctx_set_cache_budget": (i32, [vp, C.c_uint64]),
         "spr_run_batch": (i32, [vp, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), i32, vp]),
+        "spr_read_member": (i32, [vp, i32, vp, vp, u32]),
         "spr_server_create": (i32, [vp, C.POINTER(ServerCfg), pp]),
         "spr_server_submit": (i32, [vp, C.POINTER(ShotDesc), C.POINTER(C.c_uint64)]),
         "spr_server_poll": (i32, [vp, C.c_uint64, C.POINTER(Result)]),
@@ -452,6 +453,22 @@ class Population:
         self.ctx._check(self.ctx.lib.spr_read(self.h, rho.ctypes.data, supp.ctypes.data,
                                               err.ctypes.data, flags))
         return rho, supp.astype(bool), err
+
+    def read_member(self, member, children=False):
+        """Host copies of one member: rho (N,N) complex64, supp (N,N) bool."""
+        n = self.n
+        rho = np.empty((n, n), dtype=np.complex64)
+        supp = np.empty((n, n), dtype=np.uint8)
+        flags = READ_CHILDREN if children else 0
+        self.ctx._check(self.ctx.lib.spr_read_member(self.h, int(member), rho.ctypes.data, supp.ctypes.data,
+                                                     flags))
+        return rho, supp.astype(bool)
+
+    def errors(self):
+        """Fitness of the parents (P,) float64."""
+        err = np.empty(self.P, dtype=np.float64)
+        self.ctx._check(self.ctx.lib.spr_read(self.h, None, None, err.ctypes.data, 0))
+        return err
 
     def read_into(self, rho=None, supp=None, err=None, children=False):
         """Read into caller tensors/arrays (all host or all device)."""

@@ -64,10 +64,12 @@ SPR_DEFINE_PLAN(96, 24, 16, 3, 4, 8)
 SPR_DEFINE_PLAN(128, 8, 16, 2, 8, 8)
 SPR_DEFINE_PLAN(192, 24, 16, 3, 8, 8)
 SPR_DEFINE_PLAN(256, 8, 16, 4, 8, 8)
-SPR_DEFINE_PLAN(384, 24, 16, 3, 2, 8, 8)
 SPR_DEFINE_PLAN(512, 8, 8, 8, 8, 8)
-SPR_DEFINE_PLAN(768, 24, 8, 3, 4, 8, 8)
-SPR_DEFINE_PLAN(1024, 16, 8, 16, 8, 8)
+// 384 and 768: twelve elements per thread (radix-3 pass, then radix 4/2)
+// keep the row kernels at two waves per SIMD; 1024: the radix-16 pass last.
+SPR_DEFINE_PLAN(384, 12, 16, 3, 4, 4, 4, 2)
+SPR_DEFINE_PLAN(768, 12, 8, 3, 4, 4, 4, 4)
+SPR_DEFINE_PLAN(1024, 16, 8, 8, 8, 16)
 
 // ---------------------------------------------------------------------------
 // Small DFT butterflies, in place: a[k] <- sum_r a[r] exp(DIR 2 pi i r k / R)

@@ -41,10 +41,13 @@ constexpr size_t NN = (size_t)N * N;
 #ifndef SPR_ROW_WAVE
 #define SPR_ROW_WAVE 1
 #endif
-// Row transforms: one row per T lanes (T divides 64, so a row never spans two
-// wavefronts); the column tile interleaves C transforms across the workgroup.
-static_assert(64 % T == 0, "row transforms must not straddle wavefronts");
-using RowL = Lds<1, SPR_ROW_PAD, SPR_ROW_WAVE != 0>;
+// Row transforms: one row per T lanes; rows held within one wavefront (T
+// divides 64) synchronise their LDS exchanges per wave, longer rows (T a
+// multiple of 64) the workgroup.  The column tile interleaves C transforms
+// across the workgroup.
+constexpr bool kRowWave = SPR_ROW_WAVE != 0 && 64 % T == 0;
+static_assert(kRowWave || T % 64 == 0, "a row transform must fill whole wavefronts or fit in one");
+using RowL = Lds<1, SPR_ROW_PAD, kRowWave>;
 using ColL = Lds<C, 0, false>;
 constexpr int NR = RowL::span(N);  // LDS elements per row
 static_assert(N % C == 0, "column tile must divide N");

@@ -558,6 +558,33 @@ spr_status spr_read(spr_pop* pop, float* rho, uint8_t* supp, double* err, uint32
   });
 }
 
+spr_status spr_read_member(spr_pop* pop, int32_t member, float* rho, uint8_t* supp, uint32_t flags) {
+  if (!pop || !live_has(pop)) return SPR_E_INVALID_ARG;
+  spr_ctx* ctx = pop->ctx;
+  return guarded(ctx, [&] {
+    if (member < 0 || member >= pop->P) fail(SPR_E_INVALID_ARG, "member out of range");
+    use_device(ctx);
+    sync_pop(pop);
+    const bool kids = flags & SPR_READ_CHILDREN;
+    if (kids) need_memetic(pop, "reading children");
+    const bool dev = flags & SPR_DEVICE_PTRS;
+    const size_t nn = (size_t)pop->n * pop->n;
+    const int slot_index = (kids ? pop->P : 0) + member;
+    int slot = 0;
+    HIPCHK(hipMemcpy(&slot, pop->table + slot_index, sizeof(int), hipMemcpyDeviceToHost));
+    if (rho)
+      HIPCHK(hipMemcpy(rho, pop->X + (size_t)slot * nn, nn * sizeof(float2),
+                       dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    if (supp) {
+      uint8_t* st = stage(pop, nn);
+      PackArgs pa{pop->table + slot_index, 1, pop->n, pop->W, 0, st, pop->S};
+      launch_ok(launch_unpack(pa, ctx->stream), "unpack");
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      HIPCHK(hipMemcpy(supp, st, nn, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    }
+  });
+}
+
 spr_status spr_read_stats(spr_pop* pop, spr_gen_stats* out, int32_t max_n, int32_t* n_out) {
   if (!pop || !n_out || (max_n > 0 && !out)) return SPR_E_INVALID_ARG;
   if (!live_has(pop)) return SPR_E_INVALID_ARG;

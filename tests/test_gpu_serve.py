@@ -147,3 +147,19 @@ def test_server_rejects(ctx, B):
         sv.submit(big.amp32, big.mask8, big.supp8[0], seed=1)  # 4 members of 1024^2 do not fit
     assert e.value.code == B.E_ADMISSION
     sv.close()
+
+
+def test_read_member(ctx, B):
+    c = Case(64, 4, seed=91)
+    sh, pop = c.population(ctx)
+    pop.run(B.sched_ops([B.op(B.OP_ER, count=3, chi=0.5), B.op(B.OP_SHRINKWRAP, sigma=1.0, tau=0.1)], ctx))
+    rho, supp, err = pop.read()
+    for p in range(4):
+        r1, s1 = pop.read_member(p)
+        np.testing.assert_array_equal(r1, rho[p])
+        np.testing.assert_array_equal(s1, supp[p])
+    with pytest.raises(B.SprError):
+        pop.read_member(4)
+    np.testing.assert_array_equal(pop.errors(), err)
+    pop.close()
+    sh.close()
