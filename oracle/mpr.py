@@ -47,6 +47,22 @@ def to_fft_order(img):
     return np.fft.ifftshift(np.asarray(img))
 
 
+def fp16_modulus(M, known):
+    """The measured modulus as the FP16 storage represents it.
+
+    The paper fixes no storage precision.  The reading taken: the values kept
+    are M / s rounded to the nearest FP16 number (ties to even), with s the
+    power of two that puts the largest measured M / s in [2^13, 2^14]; the
+    arithmetic then uses s * fp16(M / s).  Unknown pixels are irrelevant.
+    Returns (M_stored, s) in float64.
+    """
+    M = np.asarray(M, dtype=np.float64)
+    mx = float(M[known].max()) if np.any(known) else 0.0
+    s = 2.0 ** (int(np.ceil(np.log2(mx))) - 14) if mx > 0 else 1.0
+    q = (M / s).astype(np.float16).astype(np.float64) * s
+    return np.where(known, q, M), s
+
+
 def random_phase_start(M, known, P, seed):
     """Random-phase starting densities rho0_p = F^-1[Xi * M * exp(i phi_p)].
 

@@ -78,3 +78,34 @@ def test_random_phase_start_angle_matches_the_generator():
     u = philox.draw(99, philox.PURPOSE_INIT, 0, 1, k)
     phi = 2 * np.pi * (u + 0.5) / 2**32
     assert abs(np.exp(1j * np.angle(X.ravel()[k])) - np.exp(1j * phi)) < 1e-12
+
+
+def test_fp16_modulus_scale_and_rounding_bound():
+    rng = np.random.default_rng(9)
+    M = rng.uniform(0.0, 3.0e5, size=(32, 32))
+    known = rng.random((32, 32)) > 0.1
+    Mq, s = mpr.fp16_modulus(M, known)
+    assert np.log2(s) == int(np.log2(s))           # a power of two
+    top = M[known].max() / s
+    assert 2.0 ** 13 <= top <= 2.0 ** 14            # largest value in the top binade
+    k = known & (M / s >= 2.0 ** -14)               # normal FP16 range
+    assert np.all(np.abs(Mq[k] - M[k]) <= 2.0 ** -11 * M[k])   # half-ulp bound of 11-bit significands
+    assert np.array_equal(Mq[~known], M[~known])
+
+
+def test_fp16_modulus_exact_values_unchanged():
+    # integers below 2^11 times a power of two are FP16 numbers
+    M = np.arange(64, dtype=np.float64).reshape(8, 8) * 16.0
+    M[0, 0] = 2.0 ** 14 * 16.0 / 2.0        # largest value 2^17 -> s = 2^3
+    known = np.ones((8, 8), bool)
+    Mq, s = mpr.fp16_modulus(M, known)
+    assert s == 8.0
+    np.testing.assert_array_equal(Mq, M)
+
+
+def test_fp16_modulus_rounds_ties_to_even():
+    # with s = 1: 2049 lies halfway between 2048 and 2050 -> 2048 (even significand)
+    M = np.array([[2.0 ** 14, 2049.0], [2051.0, 1.0]])
+    Mq, s = mpr.fp16_modulus(M, np.ones((2, 2), bool))
+    assert s == 1.0
+    assert Mq[0, 1] == 2048.0 and Mq[1, 0] == 2052.0 and Mq[1, 1] == 1.0
