@@ -256,6 +256,84 @@ def serving_leg(ctx, B, rates, count, max_shots, budget, forms=("served", "plain
     return out
 
 
+# ---------------------------------------------------------------------------
+# Precision: FP16 against FP32 storage of the measured modulus
+# ---------------------------------------------------------------------------
+def precision_study(ctx, B, generations=20, sample=4):
+    """512^2 clustered-sphere shot, P = 64 sphere starts.  For each storage:
+    the error against the FP64 oracle (exact modulus) of one RAAR step, of 20
+    ER iterations and of their Eq. error_calc fitness on `sample` members; the
+    throughput of MPR generations; and a full MPR run (`generations` x 100
+    iterations) whose final best density and fitness are compared between the
+    two storages, beside the divergence of two FP32 runs whose starts differ by
+    FP32 rounding (how far any FP32 evaluation can drift on this trajectory)."""
+    from oracle import mpr
+    sh0, rho0, supp0 = make_inputs()
+    M = mpr.to_fft_order(sh0["amp"].astype(np.float32).astype(np.float64))
+    known = mpr.to_fft_order(sh0["mask"])
+    S = supp0.astype(bool)
+    x0 = rho0.astype(np.complex128)
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    ref_raar = [mpr.raar(x0[p], S, M, known, 0.5, 0.9) for p in range(sample)]
+    ref_er = [mpr.sequence(x0[p], S, M, known, 0.5, "HIO", 0.9, 0, 20) for p in range(sample)]
+    ref_e = [mpr.get_error(x, S, M, known) for x in ref_er]
+    out = {"workload": "512x512 clustered spheres (1e8 photons, 24x24 beamstop, 4-px gap), P=64 sphere starts",
+           "sample_members": sample}
+    finals = {}
+    for name, fp16 in (("fp32", False), ("fp16", True)):
+        shot = ctx.shot(sh0["amp"].astype(np.float32), sh0["mask"].astype(np.uint8), fp16=fp16)
+        rec = {}
+        pop = shot.population(rho0[:sample], supp0)
+        pop.run(B.sched_ops([B.op(B.OP_RAAR, count=1, beta=0.9, chi=0.5)], ctx))
+        rho, _, _ = pop.read()
+        rec["raar_step_rel_l2_max"] = max(rel(rho[p], ref_raar[p]) for p in range(sample))
+        pop.close()
+        pop = shot.population(rho0[:sample], supp0)
+        pop.run(B.sched_ops([B.op(B.OP_ER, count=20, chi=0.5), B.op(B.OP_GET_ERROR)], ctx))
+        rho, _, err = pop.read()
+        rec["er20_rel_l2_max"] = max(rel(rho[p], ref_er[p]) for p in range(sample))
+        rec["er20_fitness_rel_max"] = max(abs(err[p] - ref_e[p]) / ref_e[p] for p in range(sample))
+        pop.close()
+        # full MPR run from the same starts
+        runs = [("main", rho0)]
+        if not fp16:
+            rng = np.random.default_rng(77)
+            eps = np.finfo(np.float32).eps * np.abs(rho0).max()
+            pert = (rho0 + eps * (rng.standard_normal(rho0.shape) + 1j * rng.standard_normal(rho0.shape))
+                    ).astype(np.complex64)
+            runs.append(("perturbed", pert))
+        for tag, start in runs:
+            pop = shot.population(start, supp0, memetic=True, seed=3004)
+            G = generations
+            scheds = [B.sched_mpr(ctx, **mpr_params(g, G, g == 1)) for g in range(1, G + 1)]
+            t0 = time.perf_counter()
+            for sc in scheds:
+                pop.run(sc)
+            pop.sync()
+            dt = time.perf_counter() - t0
+            rho, supp, err = pop.read()
+            b = int(np.argmin(err))
+            finals[(name, tag)] = (rho[b], float(err[b]))
+            if tag == "main":
+                rec["mpr_member_iterations_per_s"] = 2 * P * (R * (J + J_ER) + J_EVAL) * G / dt
+                rec["mpr_best_fitness"] = float(err[b])
+            pop.close()
+        shot.close()
+        out[name] = rec
+    a32, e32 = finals[("fp32", "main")]
+    a16, e16 = finals[("fp16", "main")]
+    ap, ep = finals[("fp32", "perturbed")]
+    out["mpr_generations"] = generations
+    out["mpr_final_best_rel_l2_fp16_vs_fp32"] = rel(a16, a32)
+    out["mpr_final_best_fitness_rel_fp16_vs_fp32"] = abs(e16 - e32) / e32
+    out["mpr_final_best_rel_l2_fp32_perturbed_vs_fp32"] = rel(ap, a32)
+    out["mpr_final_best_fitness_rel_fp32_perturbed_vs_fp32"] = abs(ep - e32) / e32
+    return out
+
+
 def copy_calibration():
     """A plain copy kernel of known size: 256 MiB read + 256 MiB written per
     launch (torch copy_, a hipMemcpy device-to-device kernel).  Its FETCH_SIZE /
@@ -293,12 +371,22 @@ def main():
     ap.add_argument("--serve-rates", type=str, default="50,5",
                     help="Poisson arrival rates (shots/s) of the serving leg")
     ap.add_argument("--serve-shots", type=str, default="60,20", help="shots per rate")
-    ap.add_argument("--serve-max-shots", type=int, default=8, help="shots resident at once in the server")
+    ap.add_argument("--serve-max-shots", type=int, default=2, help="shots resident at once in the server")
     ap.add_argument("--serve-budget-gib", type=float, default=48.0, help="device memory of the server")
     ap.add_argument("--serve-forms", type=str, default="served,plain")
+    ap.add_argument("--precision", action="store_true",
+                    help="run the FP16-versus-FP32 modulus storage study and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.precision:
+        import torch  # noqa: F401
+        from paper_2409_07413_amd import binding as B
+        ctx = B.Context(0)
+        ctx.set_cache_budget(CACHE_BUDGET)
+        print(json.dumps({"precision": precision_study(ctx, B)}), flush=True)
+        ctx.close()
         return
     rates = [float(r) for r in args.serve_rates.split(",")]
     counts = [int(c) for c in args.serve_shots.split(",")]

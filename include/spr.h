@@ -60,6 +60,7 @@ typedef int32_t spr_status;
 #define SPR_POP_MEMETIC 0x4u   /* population also holds P children (needed by crossover/select) */
 #define SPR_READ_CHILDREN 0x8u /* spr_read/spr_pop_write act on the child population */
 #define SPR_INIT_RANDOM_PHASE 0x10u /* spr_pop_create: generate the random-phase start on the device */
+#define SPR_AMP_FP16 0x20u     /* shot: store the measured modulus in FP16 (see spr_shot_create) */
 
 typedef struct spr_ctx spr_ctx;
 typedef struct spr_shot spr_shot;
@@ -88,6 +89,10 @@ spr_status spr_ctx_set_cache_budget(spr_ctx* ctx, uint64_t bytes);
 /* diffraction pattern (section "The phase problem...", Eq. pm_full).         */
 /* amp: N*N float32, finite, >= 0 where measured.  mask: N*N uint8.            */
 /* The sum of Xi M^2 must be positive (it normalises Eq. error_calc).          */
+/* SPR_AMP_FP16: the library keeps M / s in FP16 (2 bytes per pixel, rounded  */
+/* to nearest even), with s the power of two that puts the largest measured   */
+/* M / s in [2^13, 2^14]; kernels multiply by s after loading.  All other     */
+/* arithmetic is unchanged (FP32 transforms, FP64 reductions).                */
 /* Errors: SPR_E_INVALID_ARG, SPR_E_NUMERIC (non-finite or negative measured   */
 /* amplitude), SPR_E_UNSUPPORTED_SIZE, SPR_E_OOM, SPR_E_HIP.                   */
 /* ------------------------------------------------------------------------- */
@@ -231,6 +236,9 @@ typedef struct spr_gen_stats {
 /* rho P*N*N complex, supp P*N*N uint8, err P doubles; any may be NULL.         */
 /* With SPR_DEVICE_PTRS the buffers are device memory.  Waits for the work.     */
 spr_status spr_read(spr_pop* pop, float* rho, uint8_t* supp, double* err, uint32_t flags);
+/* One parent (or child with SPR_READ_CHILDREN) into caller buffers: rho N*N  */
+/* complex, supp N*N uint8; either may be NULL.  member in [0, P).            */
+spr_status spr_read_member(spr_pop* pop, int32_t member, float* rho, uint8_t* supp, uint32_t flags);
 /* Generation records, oldest first; at most max_n; *n_out gets the count. */
 spr_status spr_read_stats(spr_pop* pop, spr_gen_stats* out, int32_t max_n, int32_t* n_out);
 
@@ -304,7 +312,7 @@ typedef struct spr_shot_desc {
   const uint8_t* mask;    /* N*N, 1 = measured */
   const uint8_t* supp0;   /* N*N (broadcast) or P*N*N (supp_per_member) initial supports */
   int32_t supp_per_member;
-  uint32_t flags;         /* SPR_LAYOUT_FFT; SPR_INIT_RANDOM_PHASE (else rho0 is the start) */
+  uint32_t flags;         /* SPR_LAYOUT_FFT, SPR_AMP_FP16; SPR_INIT_RANDOM_PHASE (else rho0 is the start) */
   const float* rho0;      /* P*N*N complex start, or NULL with SPR_INIT_RANDOM_PHASE */
   uint64_t seed;          /* keys the random-phase start */
   double arrival;         /* < 0: stamped at submit; else the arrival time on the server clock */

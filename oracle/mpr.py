@@ -53,14 +53,16 @@ def fp16_modulus(M, known):
     The paper fixes no storage precision.  The reading taken: the values kept
     are M / s rounded to the nearest FP16 number (ties to even), with s the
     power of two that puts the largest measured M / s in [2^13, 2^14]; the
-    arithmetic then uses s * fp16(M / s).  Unknown pixels are irrelevant.
-    Returns (M_stored, s) in float64.
+    arithmetic then uses s * fp16(M / s) everywhere the modulus enters, the
+    normaliser sum Xi M^2 of Eq. error_calc included.  Unknown pixels are
+    irrelevant.  Returns (M_stored, s) in float64.
     """
     M = np.asarray(M, dtype=np.float64)
     mx = float(M[known].max()) if np.any(known) else 0.0
     s = 2.0 ** (int(np.ceil(np.log2(mx))) - 14) if mx > 0 else 1.0
-    q = (M / s).astype(np.float16).astype(np.float64) * s
-    return np.where(known, q, M), s
+    q = M.copy()
+    q[known] = (M[known] / s).astype(np.float16).astype(np.float64) * s
+    return q, s
 
 
 def random_phase_start(M, known, P, seed):

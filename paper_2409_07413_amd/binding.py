@@ -28,6 +28,7 @@ LAYOUT_FFT = 0x2
 POP_MEMETIC = 0x4
 READ_CHILDREN = 0x8
 INIT_RANDOM_PHASE = 0x10
+AMP_FP16 = 0x20
 
 OP_ER, OP_HIO, OP_RAAR, OP_SHRINKWRAP, OP_SUPPORT_AREA, OP_GET_ERROR, OP_STATS, OP_CROSSOVER, OP_SELECT = range(1, 10)
 ALG_HIO, ALG_RAAR = 1, 2
@@ -307,9 +308,10 @@ class Context:
     def supported(self, n):
         return bool(self.lib.spr_supported_size(int(n)))
 
-    def shot(self, amp, mask, fft_order=False):
-        """amp: N x N float32 (centred unless fft_order); mask: N x N uint8 (1 = measured)."""
-        return Shot(self, amp, mask, fft_order)
+    def shot(self, amp, mask, fft_order=False, fp16=False):
+        """amp: N x N float32 (centred unless fft_order); mask: N x N uint8 (1 = measured).
+        fp16: keep the modulus in FP16 on the device (power-of-two scaled)."""
+        return Shot(self, amp, mask, fft_order, fp16)
 
     def sched_ops(self, ops):
         return sched_ops(ops, self)
@@ -343,14 +345,14 @@ class Context:
 
 
 class Shot:
-    def __init__(self, ctx, amp, mask, fft_order=False):
+    def __init__(self, ctx, amp, mask, fft_order=False, fp16=False):
         self.ctx = ctx
         self.n = int(amp.shape[-1])
         pa, da = _ptr(amp)
         pm, dm = _ptr(mask)
         if da != dm:
             raise ValueError("amp and mask must both be host or both be device arrays")
-        flags = (DEVICE_PTRS if da else 0) | (LAYOUT_FFT if fft_order else 0)
+        flags = (DEVICE_PTRS if da else 0) | (LAYOUT_FFT if fft_order else 0) | (AMP_FP16 if fp16 else 0)
         h = C.c_void_p()
         ctx._check(ctx.lib.spr_shot_create(ctx.h, self.n, pa, pm, flags, C.byref(h)))
         self.h = h
@@ -553,13 +555,13 @@ class Server:
             raw = self.lib.spr_server_last_error(self.h)
             raise SprError(st, raw.decode() if raw else "")
 
-    def submit(self, amp, mask, supp0, rho0=None, seed=0, fft_order=False, arrival=None):
+    def submit(self, amp, mask, supp0, rho0=None, seed=0, fft_order=False, arrival=None, fp16=False):
         """Queue one shot (host arrays); rho0 None = device random-phase start."""
         n = int(amp.shape[0])
         amp = np.ascontiguousarray(amp, dtype=np.float32)
         mask = np.ascontiguousarray(mask, dtype=np.uint8)
         supp0 = np.ascontiguousarray(supp0, dtype=np.uint8)
-        flags = LAYOUT_FFT if fft_order else 0
+        flags = (LAYOUT_FFT if fft_order else 0) | (AMP_FP16 if fp16 else 0)
         if rho0 is None:
             flags |= INIT_RANDOM_PHASE
             rp = None

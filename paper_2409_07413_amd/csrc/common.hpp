@@ -1,6 +1,7 @@
 // Shared declarations of the MPR hot-path library: kernel argument blocks,
 // the per-size kernel table, Philox4x32-10 and small device helpers.
 #pragma once
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -34,12 +35,18 @@ struct SlotDesc {
   float2* T;             // the member's own row-transform buffer (launches with t_by_slot)
   uint32_t* S;           // support bits, W words
   const float* amp;      // measured modulus of its shot, FFT order, sign bit set = unknown
+  const __half* amp16;   // or the same stored as M / amp_scale in FP16 (amp then null)
   double* E;             // fitness slot
   double den;            // sum of Xi M^2 of its shot
   int* flags;            // status word of its population (bit 0: non-finite fitness)
   float amp_scale;
   int pad;
 };
+
+// Stored amplitude i (FP32 or FP16 storage; the sign bit marks unknown pixels).
+__device__ __forceinline__ float amp_load(const float* a32, const __half* a16, size_t i) {
+  return a16 ? __half2float(a16[i]) : a32[i];
+}
 
 // Per-member iteration parameters (members at different schedule positions).
 struct IterParam {
@@ -129,7 +136,8 @@ struct ColCorrArgs {
   int npairs;            // 3 P
   const int* abc;        // [P][3] chosen parents (population indices)
   const float2* F;       // parent spectra, indexed by population index [P][N*N]
-  const float* amp;      // mask = sign bit
+  const float* amp;      // mask = sign bit (FP32 or FP16 storage)
+  const __half* amp16;
   float2* C;             // out: [pair][2][N*N] column-IFFT of Xi conj(Xq) Xp and Xi Xq Xp
   const float2* tw;
 };

@@ -55,6 +55,7 @@ struct spr_shot {
   int n = 0;
   const SizeKernels* K = nullptr;
   float* amp = nullptr;  // FFT order, sign bit = unknown
+  __half* amp16 = nullptr;  // FP16 storage of amp / amp_scale instead (SPR_AMP_FP16)
   float amp_scale = 1.f;
   double den = 0.0;      // sum of Xi M^2
   int live = 0;
@@ -238,6 +239,29 @@ double encode_shot(int n, const float* a, const uint8_t* mask, uint32_t flags, f
     }
   if (!(den > 0.0)) fail(SPR_E_INVALID_ARG, "sum of measured M^2 must be positive");
   return den;
+}
+
+// FP16 storage of the encoded modulus: M / s rounded to nearest even, with s
+// the power of two that puts the largest measured value in [2^13, 2^14], so
+// that no stored value overflows and small ones stay clear of the subnormal
+// range; the sign bit (unknown pixels) is kept.
+// The normaliser of Eq. error_calc is recomputed from the stored values, so
+// that numerator and denominator see the same modulus.
+float fp16_encode(const float* enc, size_t nn, std::vector<__half>& out, double& den) {
+  float mx = 0.f;
+  for (size_t k = 0; k < nn; ++k)
+    if (!std::signbit(enc[k])) mx = std::max(mx, enc[k]);
+  const float s = mx > 0.f ? std::ldexp(1.0f, (int)std::ceil(std::log2((double)mx)) - 14) : 1.0f;
+  out.resize(nn);
+  den = 0.0;
+  for (size_t k = 0; k < nn; ++k) {
+    out[k] = __float2half(std::signbit(enc[k]) ? -0.0f : enc[k] / s);
+    if (!std::signbit(enc[k])) {
+      const double v = (double)__half2float(out[k]) * (double)s;
+      den += v * v;
+    }
+  }
+  return s;
 }
 
 uint8_t* stage(spr_pop* pop, size_t bytes) {
@@ -482,11 +506,11 @@ void get_error(const Group& g, hipStream_t s) {
 
 // Random-phase start of P members stored contiguously at X: Fourier-side
 // values, then the unitary inverse 2D transform in place.
-void random_phase_start(spr_ctx* ctx, const SizeKernels* K, int n, int P, const float* amp, float amp_scale,
-                        uint64_t seed, float2* X, hipStream_t s) {
+void random_phase_start(spr_ctx* ctx, const SizeKernels* K, int n, int P, const float* amp, const __half* amp16,
+                        float amp_scale, uint64_t seed, float2* X, hipStream_t s) {
   if (P == 0) return;
   const float2* tw = twiddles(ctx, n);
-  InitPhaseArgs ia{P, n, amp, amp_scale, seed, X};
+  InitPhaseArgs ia{P, n, amp, amp16, amp_scale, seed, X};
   launch_ok(launch_init_phase(ia, s), "init_phase");
   ColFftArgs c{nullptr, nullptr, P, X, X, +1, 1.f, tw};
   launch_ok(K->col_fft(c, s), "col_fft");
@@ -540,7 +564,7 @@ void crossover(spr_pop* pop, const spr_op& op, hipStream_t s) {
   launch_ok(K->col_fft(c1, s), "col_fft");
   ChoiceArgs ch{P, op.gen, t_min, t_max, pop->seed, pop->abc, pop->mapprm};
   launch_ok(launch_choice(ch, s), "choice");
-  ColCorrArgs cc{3 * P, pop->abc, pop->F, pop->shot->amp, pop->Cc, tw};
+  ColCorrArgs cc{3 * P, pop->abc, pop->F, pop->shot->amp, pop->shot->amp16, pop->Cc, tw};
   launch_ok(K->col_corr(cc, s), "col_corr");
   RowArgmaxArgs am{6 * P, pop->Cc, pop->amax, tw};
   launch_ok(K->row_argmax(am, s), "row_argmax");

@@ -536,7 +536,7 @@ __global__ void k_init_phase(InitPhaseArgs a) {
   for (int w = 0; w < 4; ++w) {
     const long k = gid * 4 + w;
     if (k >= nn) break;
-    const float av = a.amp[k];
+    const float av = amp_load(a.amp, a.amp16, k);
     const double v = signbit(av) ? 0.0 : (double)av * (double)a.amp_scale;
     const double phi = 6.283185307179586476925 * ((double)u.v[w] + 0.5) * 2.3283064365386962890625e-10;
     double sn, cs;

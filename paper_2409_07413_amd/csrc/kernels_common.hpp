@@ -122,6 +122,7 @@ struct PackArgs {
 struct InitPhaseArgs {
   int nm, n;
   const float* amp;  // FFT order, sign bit set = unknown
+  const __half* amp16;  // or FP16 storage of M / amp_scale (amp then null)
   float amp_scale;
   uint64_t seed;
   float2* X;         // [member][n*n], contiguous

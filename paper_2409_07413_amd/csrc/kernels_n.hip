@@ -157,14 +157,13 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
   float2* dst = a.Y + (size_t)id.img * NN;
   const SlotDesc& d = a.desc[a.slots[id.img]];
   const float2* src = a.t_by_slot ? d.T : a.T + (size_t)id.img * NN;
-  const float* amp = d.amp;
   const float amp_scale = d.amp_scale;
   float2 v[E];
   float mv[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = src[(size_t)(t + T * m) * N + col];
 #pragma unroll
-  for (int m = 0; m < E; ++m) mv[m] = amp[(size_t)(t + T * m) * N + col];
+  for (int m = 0; m < E; ++m) mv[m] = amp_load(d.amp, d.amp16, (size_t)(t + T * m) * N + col);
   TwSet<N> ws;
   load_twiddle_set<N>(ws, t, a.tw);
   fft<N, -1, ColL>(v, lds + c, t, a.tw, ws);
@@ -292,7 +291,7 @@ __global__ __launch_bounds__(C* T) void k_col_err(ColErrArgs a) {
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = src[(size_t)(t + T * m) * N + col];
 #pragma unroll
-  for (int m = 0; m < E; ++m) mv[m] = d.amp[(size_t)(t + T * m) * N + col];
+  for (int m = 0; m < E; ++m) mv[m] = amp_load(d.amp, d.amp16, (size_t)(t + T * m) * N + col);
   fft<N, -1, ColL>(v, lds + c, t, a.tw);
   const float inv = 1.0f / (float)N;
   double acc = 0.0;
@@ -383,7 +382,7 @@ __global__ __launch_bounds__(C* T) void k_col_corr(ColCorrArgs a) {
   for (int m = 0; m < E; ++m) {
     const size_t i = (size_t)(t + T * m) * N + col;
     const float2 xq = Xq[i], xp = Xp[i];
-    const bool known = !signbit(a.amp[i]);
+    const bool known = !signbit(amp_load(a.amp, a.amp16, i));
     v1[m] = known ? cmul(cconj(xq), xp) : make_float2(0.f, 0.f);
     v2[m] = known ? cmul(xq, xp) : make_float2(0.f, 0.f);
   }

@@ -114,18 +114,31 @@ spr_status spr_shot_create(spr_ctx* ctx, int32_t n, const float* amp, const uint
     to_host(ab, amp, nn * sizeof(float), dev);
     to_host(mb, mask, nn, dev);
     std::vector<float> enc(nn);
-    const double den = encode_shot(n, reinterpret_cast<const float*>(ab.data()), mb.data(), flags, enc.data());
+    double den = encode_shot(n, reinterpret_cast<const float*>(ab.data()), mb.data(), flags, enc.data());
+    std::vector<__half> h16;
+    float scale16 = 1.f;
+    if (flags & SPR_AMP_FP16) {
+      scale16 = fp16_encode(enc.data(), nn, h16, den);
+      if (!(den > 0.0)) fail(SPR_E_INVALID_ARG, "sum of measured M^2 must be positive");
+    }
     spr_shot* sh = new spr_shot();
     sh->ctx = ctx;
     sh->n = n;
     sh->K = K;
     sh->den = den;
     try {
-      sh->amp = dalloc<float>(nn);
-      HIPCHK(hipMemcpy(sh->amp, enc.data(), nn * sizeof(float), hipMemcpyHostToDevice));
+      if (flags & SPR_AMP_FP16) {
+        sh->amp_scale = scale16;
+        sh->amp16 = dalloc<__half>(nn);
+        HIPCHK(hipMemcpy(sh->amp16, h16.data(), nn * sizeof(__half), hipMemcpyHostToDevice));
+      } else {
+        sh->amp = dalloc<float>(nn);
+        HIPCHK(hipMemcpy(sh->amp, enc.data(), nn * sizeof(float), hipMemcpyHostToDevice));
+      }
       (void)twiddles(ctx, n);
     } catch (...) {
       dfree(sh->amp);
+      dfree(sh->amp16);
       delete sh;
       throw;
     }
@@ -145,6 +158,7 @@ spr_status spr_shot_destroy(spr_shot* shot) {
   shot->ctx->shots.erase(shot);
   (void)hipSetDevice(shot->ctx->device);
   dfree(shot->amp);
+  dfree(shot->amp16);
   delete shot;
   return SPR_OK;
 }
@@ -196,6 +210,7 @@ spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const ui
         dh[i].X = pop->X + i * nn;
         dh[i].S = pop->S + i * pop->W;
         dh[i].amp = shot->amp;
+        dh[i].amp16 = shot->amp16;
         dh[i].E = pop->E + i;
         dh[i].den = shot->den;
         dh[i].flags = pop->flags;
@@ -214,7 +229,7 @@ spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const ui
       HIPCHK(hipMemsetAsync(pop->X, 0, ns * nn * sizeof(float2), cs));
       HIPCHK(hipStreamSynchronize(cs));
       const bool dev = flags & SPR_DEVICE_PTRS;
-      if (init_phase) random_phase_start(ctx, pop->K, pop->n, P, shot->amp, shot->amp_scale, seed, pop->X,
+      if (init_phase) random_phase_start(ctx, pop->K, pop->n, P, shot->amp, shot->amp16, shot->amp_scale, seed, pop->X,
                                          ctx->stream);
       else
         HIPCHK(hipMemcpy(pop->X, rho0, (size_t)P * nn * sizeof(float2),

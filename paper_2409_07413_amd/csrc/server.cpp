@@ -120,6 +120,8 @@ class PinnedPool {
 
 struct ShotData {
   std::vector<float> enc;  // FFT order, sign bit = unknown
+  std::vector<__half> enc16;  // SPR_AMP_FP16: FP16 storage of enc / amp_scale (enc then empty)
+  float amp_scale = 1.f;
   double den = 0;
   std::vector<uint8_t> supp;
   int supp_per_member = 0;
@@ -453,17 +455,22 @@ class HipExec : public Exec {
       desc[m].X = dev<float2>(L.X) + (size_t)m * nn;
       desc[m].T = dev<float2>(L.T) + (size_t)m * nn;
       desc[m].S = dev<uint32_t>(L.S) + (size_t)m * W;
-      desc[m].amp = dev<float>(L.amp);
+      desc[m].amp = d->enc16.empty() ? dev<float>(L.amp) : nullptr;
+      desc[m].amp16 = d->enc16.empty() ? nullptr : dev<__half>(L.amp);
       desc[m].E = dev<double>(L.E) + m;
       desc[m].den = d->den;
       desc[m].flags = dev<int>(L.status);
-      desc[m].amp_scale = 1.f;
+      desc[m].amp_scale = d->amp_scale;
       desc[m].pad = 0;
     }
     double* E0 = reinterpret_cast<double*>(u + o_E);
     for (int m = 0; m < P; ++m) E0[m] = std::numeric_limits<double>::infinity();
     std::memset(u + o_st, 0, 16);
-    std::memcpy(u + o_amp, d->enc.data(), 4 * nn);
+    const size_t amp_bytes = d->enc16.empty() ? 4 * nn : 2 * nn;
+    if (d->enc16.empty()) std::memcpy(u + o_amp, d->enc.data(), amp_bytes);
+    else std::memcpy(u + o_amp, d->enc16.data(), amp_bytes);
+    const float amp_scale = d->amp_scale;
+    const bool fp16 = !d->enc16.empty();
     std::memcpy(u + o_supp, d->supp.data(), sb);
     if (!d->rho0.empty()) std::memcpy(u + o_rho, d->rho0.data(), 8 * nn * P);
     const int slot0 = r->slot * P;
@@ -475,7 +482,7 @@ class HipExec : public Exec {
                             hipMemcpyHostToDevice, s_));
       HIPCHK(hipMemcpyAsync(base_ + L.E, u + o_E, 8 * (size_t)P, hipMemcpyHostToDevice, s_));
       HIPCHK(hipMemcpyAsync(base_ + L.status, u + o_st, 16, hipMemcpyHostToDevice, s_));
-      HIPCHK(hipMemcpyAsync(base_ + L.amp, u + o_amp, 4 * nn, hipMemcpyHostToDevice, s_));
+      HIPCHK(hipMemcpyAsync(base_ + L.amp, u + o_amp, amp_bytes, hipMemcpyHostToDevice, s_));
       // supports through the first work buffer, as many members at a time as fit
       const int per = bcast ? P : (int)std::max<size_t>(1, std::min<size_t>(P, ws_bytes_ / nn));
       for (int m0 = 0; m0 < P; m0 += per) {
@@ -486,7 +493,8 @@ class HipExec : public Exec {
         launch(launch_pack(pa, s_), "pack");
       }
       if (init) {
-        random_phase_start(ctx_, size_kernels(n), n, P, dev<float>(L.amp), 1.f, seed, dev<float2>(L.X), s_);
+        random_phase_start(ctx_, size_kernels(n), n, P, fp16 ? nullptr : dev<float>(L.amp),
+                           fp16 ? dev<__half>(L.amp) : nullptr, amp_scale, seed, dev<float2>(L.X), s_);
         launches += 3;
       } else {
         HIPCHK(hipMemcpyAsync(base_ + L.X, u + o_rho, 8 * nn * P, hipMemcpyHostToDevice, s_));
@@ -816,6 +824,11 @@ spr_status spr_server_submit(spr_server* sv, const spr_shot_desc* sd, uint64_t* 
       d = std::make_shared<ShotData>();
       d->enc.resize(nn);
       d->den = encode_shot(n, sd->amp, sd->mask, sd->flags, d->enc.data());
+      if (sd->flags & SPR_AMP_FP16) {
+        d->amp_scale = fp16_encode(d->enc.data(), nn, d->enc16, d->den);
+        if (!(d->den > 0.0)) fail(SPR_E_INVALID_ARG, "sum of measured M^2 must be positive");
+        std::vector<float>().swap(d->enc);
+      }
       d->supp_per_member = sd->supp_per_member ? 1 : 0;
       d->supp.assign(sd->supp0, sd->supp0 + (d->supp_per_member ? nn * P : nn));
       if (!init) d->rho0.assign(sd->rho0, sd->rho0 + 2 * nn * P);
