@@ -275,6 +275,28 @@ spr_status spr_fft2(spr_ctx* ctx, int32_t n, int32_t batch, const float* in, flo
                     int32_t inverse, void* hip_stream);
 
 /* ------------------------------------------------------------------------- */
+/* Graphs: the launches of a schedule recorded once into a HIP graph and      */
+/* replayed with one call, for schedules whose per-launch host cost matters   */
+/* (small detectors, short sequences, many populations).                      */
+/* A graph replays exactly the recorded launches: the same schedule (with its */
+/* generation numbers) on the same populations and buffers.  spr_pop_destroy  */
+/* returns SPR_E_BUSY while a graph references the population.                */
+/* ------------------------------------------------------------------------- */
+typedef struct spr_graph spr_graph;
+
+/* Records `sched` on `pop` (waits for the population's earlier work; nothing */
+/* runs).  Crossover buffers are allocated here.                              */
+spr_status spr_graph_create(spr_pop* pop, const spr_sched* sched, spr_graph** out);
+/* Records a batch as spr_run_batch would run it (same rules); the graph owns */
+/* its work buffers and the member order of the populations at creation.      */
+spr_status spr_graph_create_batch(spr_ctx* ctx, spr_pop* const* pops, const spr_sched* const* scheds, int32_t n,
+                                  spr_graph** out);
+/* Enqueues one replay on hip_stream (NULL = the context stream), ordered     */
+/* after the populations' earlier work.                                       */
+spr_status spr_graph_launch(spr_graph* g, void* hip_stream);
+spr_status spr_graph_destroy(spr_graph* g);
+
+/* ------------------------------------------------------------------------- */
 /* Serving: a request loop for streamed single shots of mixed detector sizes.  */
 /* Every admitted shot keeps its P-member population resident on the device   */
 /* and runs the server's schedule; the shots admitted at any moment advance   */

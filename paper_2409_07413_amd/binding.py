@@ -111,7 +111,8 @@ EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_suppo
            "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
            "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
            "spr_timing_enable", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch",
-           "spr_read_member", "spr_server_create", "spr_server_submit", "spr_server_poll", "spr_server_step", "spr_server_drain",
+           "spr_read_member", "spr_graph_create", "spr_graph_create_batch", "spr_graph_launch",
+           "spr_graph_destroy", "spr_server_create", "spr_server_submit", "spr_server_poll", "spr_server_step", "spr_server_drain",
            "spr_server_stats_get", "spr_server_last_error", "spr_server_destroy"]
 
 KERNEL_ROW_INGEST, KERNEL_COL_PROJ, KERNEL_ROW_UPDATE_ER, KERNEL_ROW_UPDATE_IA = range(4)
@@ -149,6 +150,10 @@ def _proto(lib):
         "spr_ctx_set_cache_budget": (i32, [vp, C.c_uint64]),
         "spr_run_batch": (i32, [vp, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), i32, vp]),
         "spr_read_member": (i32, [vp, i32, vp, vp, u32]),
+        "spr_graph_create": (i32, [vp, vp, pp]),
+        "spr_graph_create_batch": (i32, [vp, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), i32, pp]),
+        "spr_graph_launch": (i32, [vp, vp]),
+        "spr_graph_destroy": (i32, [vp]),
         "spr_server_create": (i32, [vp, C.POINTER(ServerCfg), pp]),
         "spr_server_submit": (i32, [vp, C.POINTER(ShotDesc), C.POINTER(C.c_uint64)]),
         "spr_server_poll": (i32, [vp, C.c_uint64, C.POINTER(Result)]),
@@ -265,6 +270,7 @@ class Context:
         self._pops = weakref.WeakSet()
         self._shots = weakref.WeakSet()
         self._servers = weakref.WeakSet()
+        self._graphs = weakref.WeakSet()
         h = C.c_void_p()
         self._check(self.lib.spr_ctx_create(int(device), C.byref(h)), ctx=None)
         self.h = h
@@ -278,6 +284,8 @@ class Context:
         if getattr(self, "h", None):
             for sv in list(getattr(self, "_servers", ())):
                 sv.close()
+            for g in list(getattr(self, "_graphs", ())):
+                g.close()
             for p in list(getattr(self, "_pops", ())):
                 p.close()
             for sh in list(getattr(self, "_shots", ())):
@@ -304,6 +312,15 @@ class Context:
         ph = (C.c_void_p * n)(*[p.h.value if isinstance(p.h, C.c_void_p) else p.h for p in pops])
         sh = (C.c_void_p * n)(*[s.h.value if isinstance(s.h, C.c_void_p) else s.h for s in scheds])
         self._check(self.lib.spr_run_batch(self.h, ph, sh, n, _stream_ptr(stream)))
+
+    def graph_batch(self, pops, scheds):
+        """Capture a batch (as run_batch would run it) into a replayable graph."""
+        n = len(pops)
+        ph = (C.c_void_p * n)(*[p.h.value if isinstance(p.h, C.c_void_p) else p.h for p in pops])
+        sh = (C.c_void_p * n)(*[s.h.value if isinstance(s.h, C.c_void_p) else s.h for s in scheds])
+        h = C.c_void_p()
+        self._check(self.lib.spr_graph_create_batch(self.h, ph, sh, n, C.byref(h)))
+        return Graph(self, h, pops)
 
     def supported(self, n):
         return bool(self.lib.spr_supported_size(int(n)))
@@ -430,6 +447,9 @@ class Population:
 
     def close(self):
         if getattr(self, "h", None):
+            for g in list(getattr(self.ctx, "_graphs", ())):
+                if self in g.pops:
+                    g.close()
             self.ctx.lib.spr_pop_destroy(self.h)
             self.h = None
 
@@ -455,6 +475,12 @@ class Population:
         self.ctx._check(self.ctx.lib.spr_read(self.h, rho.ctypes.data, supp.ctypes.data,
                                               err.ctypes.data, flags))
         return rho, supp.astype(bool), err
+
+    def graph(self, sched):
+        """Capture sched on this population into a replayable graph."""
+        h = C.c_void_p()
+        self.ctx._check(self.ctx.lib.spr_graph_create(self.h, sched.h, C.byref(h)))
+        return Graph(self.ctx, h, [self])
 
     def read_member(self, member, children=False):
         """Host copies of one member: rho (N,N) complex64, supp (N,N) bool."""
@@ -616,6 +642,31 @@ class Server:
         if getattr(self, "h", None):
             self.lib.spr_server_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A schedule captured into a HIP graph; launch() replays it."""
+
+    def __init__(self, ctx, h, pops):
+        self.ctx = ctx
+        self.h = h
+        self.pops = list(pops)
+        ctx._graphs.add(self)
+
+    def launch(self, stream=None):
+        self.ctx._check(self.ctx.lib.spr_graph_launch(self.h, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.spr_graph_destroy(self.h)
+            self.h = None
+            self.pops = []
 
     def __del__(self):
         try:

@@ -43,6 +43,7 @@ def _jobs():
     jobs.append((os.path.join(CSRC, "kernels_common.hip"), os.path.join(OBJ, "kernels_common.o"), []))
     jobs.append((os.path.join(CSRC, "runtime.cpp"), os.path.join(OBJ, "runtime.o"), ["-x", "hip"]))
     jobs.append((os.path.join(CSRC, "server.cpp"), os.path.join(OBJ, "server.o"), ["-x", "hip"]))
+    jobs.append((os.path.join(CSRC, "graph.cpp"), os.path.join(OBJ, "graph.o"), ["-x", "hip"]))
     return jobs
 
 

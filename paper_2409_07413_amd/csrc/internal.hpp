@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <map>
 #include <mutex>
@@ -47,6 +48,7 @@ struct spr_ctx {
   std::set<spr_shot*> shots;  // live shots, populations and servers created on this context
   std::set<spr_pop*> pops;
   std::set<spr_server*> servers;
+  std::set<spr_graph*> graphs;
   std::mutex mu;
 };
 
@@ -67,6 +69,7 @@ struct spr_pop {
   const SizeKernels* K = nullptr;
   int n = 0, P = 0, nslots = 0, W = 0;
   bool memetic = false;
+  int graphs = 0;  // captured graphs that replay work on this population
   uint64_t seed = 0;
   int gen_offset = 0;
   float2 *X = nullptr, *T = nullptr, *Y = nullptr;
@@ -759,23 +762,15 @@ void sync_pop(spr_pop* pop) {
   if (!pop->stamps.empty()) collect_stamps(pop);
 }
 
+void workspace_alloc(Workspace& w, int n, size_t members, const SizeKernels* K);
+void workspace_free(Workspace& w);
+
 Workspace& workspace(spr_ctx* ctx, int n, size_t members, const SizeKernels* K) {
   Workspace& w = ctx->ws[n];
   if (w.members >= members) return w;
   HIPCHK(hipDeviceSynchronize());  // the old buffers may still be in use
-  for (void* q : {(void*)w.T, (void*)w.Y, (void*)w.err_partial, (void*)w.block_max, (void*)w.maxv,
-                  (void*)w.desc, (void*)w.slots})
-    if (q) (void)hipFree(q);
-  w = Workspace();
-  const size_t nn = (size_t)n * n;
-  w.T = dalloc<float2>(members * nn);
-  w.Y = dalloc<float2>(members * nn);
-  w.err_partial = dalloc<double>(members * (n / K->C));
-  w.block_max = dalloc<float>(members * smooth_blocks_per_member(n));
-  w.maxv = dalloc<float>(members);
-  w.desc = dalloc<SlotDesc>(members);
-  w.slots = dalloc<int>(members);
-  w.members = members;
+  workspace_free(w);
+  workspace_alloc(w, n, members, K);
   return w;
 }
 
@@ -820,6 +815,118 @@ void run_group_schedule(const Group& g, const spr_sched* sch, hipStream_t s) {
     }
     ++i;
   }
+}
+
+// Crossover buffers allocated ahead of a capture (no allocation may happen
+// while a stream is being captured).
+void prepare_buffers(spr_pop* pop, const spr_sched* sch) {
+  for (const auto& o : sch->ops)
+    if (o.kind == SPR_OP_CROSSOVER && pop->memetic && pop->P >= 4 && !pop->F) {
+      const int n = pop->n, P = pop->P;
+      const size_t nn = (size_t)n * n;
+      const int blocks = n / pop->K->RWI;
+      pop->F = dalloc<float2>((size_t)P * nn);
+      pop->Cc = dalloc<float2>((size_t)6 * P * nn);
+      pop->amax = dalloc<ArgmaxRec>((size_t)6 * P * blocks);
+      pop->align = dalloc<AlignRec>((size_t)3 * P);
+      pop->abc = dalloc<int>((size_t)3 * P);
+      pop->mapprm = dalloc<int>((size_t)5 * P);
+    }
+}
+
+// Populations of one size in a batch: their schedule and where their
+// descriptors and slot list live.
+struct BatchGroup {
+  int n = 0;
+  std::vector<int> idx;  // indices into the batch
+  const spr_sched* sched = nullptr;
+  Group g;
+};
+
+// Validate a batch and group it by size; descriptors and slot lists are
+// written (synchronously) into the given workspaces, one per size.
+std::vector<BatchGroup> plan_batch(spr_ctx* ctx, spr_pop* const* pops, const spr_sched* const* scheds, int n,
+                                   const std::function<Workspace&(int, size_t, const SizeKernels*)>& ws_for) {
+  std::map<int, std::vector<int>> by_size;
+  for (int i = 0; i < n; ++i) {
+    if (!pops[i] || !scheds[i]) fail(SPR_E_INVALID_ARG, "null population or schedule");
+    if (!live_has(pops[i])) fail(SPR_E_INVALID_ARG, "population already destroyed");
+    if (pops[i]->ctx != ctx) fail(SPR_E_INVALID_ARG, "population of another context");
+    for (int j = 0; j < i; ++j)
+      if (pops[j] == pops[i]) fail(SPR_E_INVALID_ARG, "population listed twice");
+    for (const auto& o : scheds[i]->ops)
+      if (o.scope != SPR_SCOPE_ALL) fail(SPR_E_INVALID_ARG, "batched runs act on every member (scope ALL)");
+    by_size[pops[i]->n].push_back(i);
+  }
+  std::vector<BatchGroup> out;
+  for (auto& kv : by_size) {
+    BatchGroup bg;
+    bg.n = kv.first;
+    bg.idx = kv.second;
+    bg.sched = scheds[bg.idx[0]];
+    for (int i : bg.idx) {
+      const auto& a = scheds[i]->ops;
+      if (a.size() != bg.sched->ops.size()) fail(SPR_E_INVALID_ARG, "schedules of one size must be equal");
+      for (size_t k = 0; k < a.size(); ++k)
+        if (!same_op(a[k], bg.sched->ops[k])) fail(SPR_E_INVALID_ARG, "schedules of one size must be equal");
+    }
+    size_t total = 0;
+    for (int i : bg.idx) total += pops[i]->nslots;
+    const SizeKernels* K = pops[bg.idx[0]]->K;
+    Workspace& w = ws_for(bg.n, total, K);
+    std::vector<int> slots;
+    std::vector<SlotDesc> descs;
+    size_t off = 0;
+    for (int i : bg.idx) {
+      spr_pop* pop = pops[i];
+      sync_pop(pop);
+      std::vector<SlotDesc> d(pop->nslots);
+      HIPCHK(hipMemcpy(d.data(), pop->desc, sizeof(SlotDesc) * pop->nslots, hipMemcpyDeviceToHost));
+      descs.insert(descs.end(), d.begin(), d.end());
+      std::vector<int> t = host_table(pop);
+      for (int v : t) slots.push_back((int)off + v);
+      off += pop->nslots;
+    }
+    HIPCHK(hipMemcpy(w.desc, descs.data(), sizeof(SlotDesc) * descs.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(w.slots, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice));
+    Group& g = bg.g;
+    g.ctx = ctx;
+    g.K = K;
+    g.n = bg.n;
+    g.W = pops[bg.idx[0]]->W;
+    g.slots = w.slots;
+    g.nm = (int)total;
+    g.desc = w.desc;
+    g.T = w.T;
+    g.Y = w.Y;
+    g.err_partial = w.err_partial;
+    g.block_max = w.block_max;
+    g.maxv = w.maxv;
+    g.timing = nullptr;
+    g.chunk = chunk_for(ctx, bg.n, (int)total);
+    out.push_back(bg);
+  }
+  return out;
+}
+
+// Work buffers of a batch of `members` members of size n.
+void workspace_alloc(Workspace& w, int n, size_t members, const SizeKernels* K) {
+  const size_t nn = (size_t)n * n;
+  w.T = dalloc<float2>(members * nn);
+  w.Y = dalloc<float2>(members * nn);
+  w.err_partial = dalloc<double>(members * (n / K->C));
+  w.block_max = dalloc<float>(members * smooth_blocks_per_member(n));
+  w.maxv = dalloc<float>(members);
+  w.desc = dalloc<SlotDesc>(members);
+  w.slots = dalloc<int>(members);
+  w.members = members;
+}
+
+void workspace_free(Workspace& w) {
+  for (void* q : {(void*)w.T, (void*)w.Y, (void*)w.err_partial, (void*)w.block_max, (void*)w.maxv,
+                  (void*)w.desc, (void*)w.slots})
+    if (q) (void)hipFree(q);
+  w = Workspace();
 }
 
 }  // namespace

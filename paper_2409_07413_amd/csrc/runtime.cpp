@@ -77,6 +77,8 @@ void spr_ctx_destroy(spr_ctx* ctx) {
   // servers, populations, then shots still alive on this context
   std::vector<spr_server*> servers(ctx->servers.begin(), ctx->servers.end());
   for (spr_server* sv : servers) spr_server_destroy(sv);
+  std::vector<spr_graph*> graphs(ctx->graphs.begin(), ctx->graphs.end());
+  for (spr_graph* g : graphs) spr_graph_destroy(g);
   std::vector<spr_pop*> pops;
   std::vector<spr_shot*> shots;
   for (spr_pop* p : ctx->pops) pops.push_back(p);
@@ -87,12 +89,7 @@ void spr_ctx_destroy(spr_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->tw) (void)hipFree(kv.second);
-  for (auto& kv : ctx->ws) {
-    Workspace& w = kv.second;
-    for (void* q : {(void*)w.T, (void*)w.Y, (void*)w.err_partial, (void*)w.block_max, (void*)w.maxv,
-                    (void*)w.desc, (void*)w.slots})
-      if (q) (void)hipFree(q);
-  }
+  for (auto& kv : ctx->ws) workspace_free(kv.second);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -254,7 +251,12 @@ spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const ui
 }
 
 spr_status spr_pop_destroy(spr_pop* pop) {
-  if (!pop || !live_remove(pop)) return SPR_E_INVALID_ARG;
+  if (!pop || !live_has(pop)) return SPR_E_INVALID_ARG;
+  if (pop->graphs > 0) {
+    pop->ctx->err = "population still has captured graphs";
+    return SPR_E_BUSY;
+  }
+  live_remove(pop);
   pop->ctx->pops.erase(pop);
   (void)hipSetDevice(pop->ctx->device);
   if (pop->done) (void)hipEventSynchronize(pop->done);
@@ -456,71 +458,26 @@ spr_status spr_run_batch(spr_ctx* ctx, spr_pop* const* pops, const spr_sched* co
   return guarded(ctx, [&] {
     use_device(ctx);
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
-    std::map<int, std::vector<int>> by_size;
-    for (int i = 0; i < n; ++i) {
-      if (!pops[i] || !scheds[i]) fail(SPR_E_INVALID_ARG, "null population or schedule");
-      if (pops[i]->ctx != ctx) fail(SPR_E_INVALID_ARG, "population of another context");
-      for (int j = 0; j < i; ++j)
-        if (pops[j] == pops[i]) fail(SPR_E_INVALID_ARG, "population listed twice");
-      for (const auto& o : scheds[i]->ops)
-        if (o.scope != SPR_SCOPE_ALL) fail(SPR_E_INVALID_ARG, "batched runs act on every member (scope ALL)");
-      by_size[pops[i]->n].push_back(i);
-    }
-    for (auto& kv : by_size) {
-      const std::vector<int>& idx = kv.second;
-      const spr_sched* sch = scheds[idx[0]];
-      for (int i : idx) {
-        const auto& a = scheds[i]->ops;
-        if (a.size() != sch->ops.size()) fail(SPR_E_INVALID_ARG, "schedules of one size must be equal");
-        for (size_t k = 0; k < a.size(); ++k)
-          if (!same_op(a[k], sch->ops[k])) fail(SPR_E_INVALID_ARG, "schedules of one size must be equal");
-      }
-      // order after each population's earlier work, then gather its slots
-      size_t total = 0;
-      for (int i : idx) {
-        spr_pop* pop = pops[i];
-        if (pop->last && pop->last != s) HIPCHK(hipStreamWaitEvent(s, pop->done, 0));
-        total += pop->nslots;
-      }
-      const SizeKernels* K = pops[idx[0]]->K;
-      Workspace& w = workspace(ctx, kv.first, total, K);
-      if (w.last && w.last != s) HIPCHK(hipStreamSynchronize(w.last));
-      w.last = s;
-      std::vector<int> slots;
-      size_t off = 0;
-      for (int i : idx) {
-        spr_pop* pop = pops[i];
-        HIPCHK(hipMemcpyAsync(w.desc + off, pop->desc, sizeof(SlotDesc) * pop->nslots, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipEventSynchronize(pop->done));
-        std::vector<int> t = host_table(pop);
-        for (int v : t) slots.push_back((int)off + v);
-        off += pop->nslots;
-      }
-      HIPCHK(hipMemcpyAsync(w.slots, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice, s));
-      HIPCHK(hipStreamSynchronize(s));  // the host slot list goes out of scope
-      Group g;
-      g.ctx = ctx;
-      g.K = K;
-      g.n = kv.first;
-      g.W = pops[idx[0]]->W;
-      g.slots = w.slots;
-      g.nm = (int)total;
-      g.desc = w.desc;
-      g.T = w.T;
-      g.Y = w.Y;
-      g.err_partial = w.err_partial;
-      g.block_max = w.block_max;
-      g.maxv = w.maxv;
-      g.timing = nullptr;
-      g.chunk = chunk_for(ctx, kv.first, (int)total);
-      for (int i : idx) pops[i]->last = s;
+    // descriptors and slot lists of every size group go into the context's
+    // work buffers; earlier batches on other streams must be done with them
+    for (auto& kv : ctx->ws)
+      if (kv.second.last && kv.second.last != s) HIPCHK(hipStreamSynchronize(kv.second.last));
+    std::vector<BatchGroup> groups =
+        plan_batch(ctx, pops, scheds, n, [&](int sz, size_t members, const SizeKernels* K) -> Workspace& {
+          Workspace& w = workspace(ctx, sz, members, K);
+          if (w.last) HIPCHK(hipStreamSynchronize(w.last));
+          w.last = s;
+          return w;
+        });
+    for (auto& bg : groups) {
+      for (int i : bg.idx) pops[i]->last = s;
       try {
-        run_group_schedule(g, sch, s);
+        run_group_schedule(bg.g, bg.sched, s);
       } catch (...) {
-        for (int i : idx) (void)hipEventRecord(pops[i]->done, s);
+        for (int i : bg.idx) (void)hipEventRecord(pops[i]->done, s);
         throw;
       }
-      for (int i : idx) HIPCHK(hipEventRecord(pops[i]->done, s));
+      for (int i : bg.idx) HIPCHK(hipEventRecord(pops[i]->done, s));
     }
   });
 }
