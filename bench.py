@@ -170,11 +170,11 @@ def _latency_summary(lat, first_arrival, finishes, count, member_px):
             "iteration_pixels_per_s": SERVE_P * 20 * SERVE_G * member_px / span}
 
 
-def run_served(ctx, B, pool, supp, stream, max_shots, budget, warm=True):
+def run_served(ctx, B, pool, supp, stream, max_shots, budget, warm=True, shortest=False):
     """Served form: continuous batching in the library's engine thread."""
     arrivals, sizes, picks = stream
     sched = serve_sched(B, ctx)
-    sv = B.Server(ctx, sched, P=SERVE_P, hbm_budget=budget, max_shots=max_shots)
+    sv = B.Server(ctx, sched, P=SERVE_P, hbm_budget=budget, max_shots=max_shots, shortest_first=shortest)
     if warm:  # one shot of every size through the engine first (pinned pool, kernels)
         ts = [sv.submit(pool[n][0][0], pool[n][0][1], supp[n], seed=1) for n in SERVE_SIZES]
         sv.drain(300.0)
@@ -200,7 +200,8 @@ def run_served(ctx, B, pool, supp, stream, max_shots, budget, warm=True):
     out = _latency_summary(lat, min(r["t_arrival"] for r in res), [r["t_finish"] for r in res], len(res),
                            float(sum(int(n) ** 2 for n in sizes)))
     out.update({"max_resident": st["max_active"], "ticks": st["ticks"], "launches": st["launches"],
-                "peak_shot_bytes": st["bytes_peak"], "max_shots": max_shots})
+                "peak_shot_bytes": st["bytes_peak"], "max_shots": max_shots,
+                "policy": "shortest-first" if shortest else "all"})
     return out
 
 
@@ -238,7 +239,7 @@ def run_plain_fifo(ctx, B, pool, supp, stream, warm=True):
     return _latency_summary(lat, 0.0, fin, len(lat), float(sum(int(n) ** 2 for n in sizes)))
 
 
-def serving_leg(ctx, B, rates, count, max_shots, budget, forms=("served", "plain"), log=None):
+def serving_leg(ctx, B, rates, count, max_shots, budget, forms=("served", "plain"), log=None, shortest=False):
     pool, supp = serving_pool()
     out = []
     for rate, cnt in zip(rates, count):
@@ -246,7 +247,7 @@ def serving_leg(ctx, B, rates, count, max_shots, budget, forms=("served", "plain
         rec = {"rate_per_s": rate}
         for form in forms:
             if form == "served":
-                rec["served"] = run_served(ctx, B, pool, supp, stream, max_shots, budget)
+                rec["served"] = run_served(ctx, B, pool, supp, stream, max_shots, budget, shortest=shortest)
             else:
                 rec["plain"] = run_plain_fifo(ctx, B, pool, supp, stream)
             if log:
@@ -334,6 +335,91 @@ def precision_study(ctx, B, generations=20, sample=4):
     return out
 
 
+# ---------------------------------------------------------------------------
+# Iteration kernels by detector size; captured versus eager schedules
+# ---------------------------------------------------------------------------
+SIZE_SWEEP = ((256, 128), (384, 64), (512, 64), (512, 128), (768, 28), (768, 64), (1024, 16), (1024, 64))
+
+
+def size_sweep(ctx, B, iters=20):
+    """Per size: RAAR^iters then ER^iters on `members` random members, one
+    launch chunk (the member count is the chunk), every iteration kernel
+    timed with HIP events; GB/s from the algorithmic bytes per launch."""
+    import torch  # noqa: F401
+    rng = np.random.default_rng(0)
+    out = []
+    for n, members in SIZE_SWEEP:
+        amp = np.abs(rng.standard_normal((n, n))).astype(np.float32)
+        from paper_2409_07413_amd import synth
+        mask = synth.beamstop_gap_mask(n, 24, 4).astype(np.uint8)
+        rho = (rng.standard_normal((members, n, n)) + 1j * rng.standard_normal((members, n, n))).astype(np.complex64)
+        supp = synth.centred_square(n, n // 3).astype(np.uint8)
+        ctx.set_cache_budget(members * 2 * n * n * 8)
+        shot = ctx.shot(amp, mask)
+        pop = shot.population(rho, supp)
+        s = B.sched_ops([B.op(B.OP_RAAR, count=iters, beta=0.9), B.op(B.OP_ER, count=iters)], ctx)
+        pop.run(s)
+        pop.sync()
+        pop.timing(True)
+        for _ in range(3):
+            pop.run(s)
+        pop.sync()
+        rec = {"n": n, "members_per_launch": members,
+               "resident_bytes": members * 2 * n * n * 8}
+        for k in range(4):
+            nl, ms = pop.timing_read(k)
+            if nl:
+                us = ms / nl * 1e3
+                rec[B.KERNEL_NAMES[k]] = {"avg_us": round(us, 2), "GBps": round(
+                    algorithmic_bytes_per_px(k, members) * n * n * members / (us * 1e-6) / 1e9, 1)}
+        out.append(rec)
+        pop.close()
+        shot.close()
+        s.close()
+    ctx.set_cache_budget(CACHE_BUDGET)
+    return out
+
+
+def graph_study(ctx, B, passes=10):
+    """The plain schedule (10 blocks of HIO^j ER^(20-j), shrink-wrap each) run
+    eagerly and replayed from a captured graph on twin populations."""
+    import torch
+    from paper_2409_07413_amd import synth
+    out = []
+    for n, P in ((128, 8), (256, 32), (512, 64)):
+        sh0 = synth.shot(n, "ellipses", 1001, 1e6, beamstop=8)
+        shot = ctx.shot(sh0["amp"].astype(np.float32), sh0["mask"].astype(np.uint8))
+        supp = synth.centred_square(n, 48).astype(np.uint8)
+        s = B.sched_plain(ctx, alg=B.ALG_HIO, G=10, j=16, j_er=4, j_end=0, beta=0.9, chi=0.5, sigma=2.0,
+                          sigma_end=1.0, tau=0.1, tau_end=0.1)
+        pa = shot.population(None, supp, seed=1, P=P)
+        pb = shot.population(None, supp, seed=1, P=P)
+        g = pb.graph(s)
+        stream = torch.cuda.Stream()
+        for _ in range(2):
+            pa.run(s, stream)
+            g.launch(stream)
+        rec = {"n": n, "P": P}
+        for tag, fn in (("eager", lambda: pa.run(s, stream)), ("graph", lambda: g.launch(stream))):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(passes):
+                fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / passes
+            rec[tag + "_ms_per_200_iterations"] = dt * 1e3
+            rec[tag + "_member_iterations_per_s"] = P * 200 / dt
+        ra, rb = pa.read(), pb.read()
+        rec["bit_equal"] = bool(all(np.array_equal(u, v) for u, v in zip(ra, rb)))
+        out.append(rec)
+        g.close()
+        pa.close()
+        pb.close()
+        shot.close()
+        s.close()
+    return out
+
+
 def copy_calibration():
     """A plain copy kernel of known size: 256 MiB read + 256 MiB written per
     launch (torch copy_, a hipMemcpy device-to-device kernel).  Its FETCH_SIZE /
@@ -371,14 +457,31 @@ def main():
     ap.add_argument("--serve-rates", type=str, default="50,5",
                     help="Poisson arrival rates (shots/s) of the serving leg")
     ap.add_argument("--serve-shots", type=str, default="60,20", help="shots per rate")
-    ap.add_argument("--serve-max-shots", type=int, default=2, help="shots resident at once in the server")
+    ap.add_argument("--serve-max-shots", type=int, default=4, help="shots resident at once in the server")
     ap.add_argument("--serve-budget-gib", type=float, default=48.0, help="device memory of the server")
     ap.add_argument("--serve-forms", type=str, default="served,plain")
+    ap.add_argument("--serve-policy", choices=("shortest", "all"), default="shortest",
+                    help="ticks advance the shots of the least remaining work first, or every resident shot")
     ap.add_argument("--precision", action="store_true",
                     help="run the FP16-versus-FP32 modulus storage study and exit")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="time the iteration kernels at every served detector size and exit")
+    ap.add_argument("--graph-study", action="store_true",
+                    help="compare captured-graph replays with eager schedule runs and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.size_sweep or args.graph_study:
+        import torch  # noqa: F401
+        from paper_2409_07413_amd import binding as B
+        ctx = B.Context(0)
+        ctx.set_cache_budget(CACHE_BUDGET)
+        if args.size_sweep:
+            print(json.dumps({"size_sweep": size_sweep(ctx, B)}), flush=True)
+        else:
+            print(json.dumps({"graph_study": graph_study(ctx, B)}), flush=True)
+        ctx.close()
         return
     if args.precision:
         import torch  # noqa: F401
@@ -402,11 +505,12 @@ def main():
         from paper_2409_07413_amd import binding as B
         ctx = B.Context(0)
         res = serving_leg(ctx, B, rates, counts, args.serve_max_shots, int(args.serve_budget_gib * (1 << 30)),
-                          forms, log)
+                          forms, log, shortest=args.serve_policy == "shortest")
         print(json.dumps({"serving": res, "config": {
             "workload": "serving stream: Poisson arrivals, sizes uniform over 256..1024 (5 sizes), "
                         "5 ellipses in a 40-px disk, 1e6 photons, 8x8 beamstop, P=32, 500 iterations",
-            "max_shots": args.serve_max_shots, "budget_gib": args.serve_budget_gib}}), flush=True)
+            "max_shots": args.serve_max_shots, "budget_gib": args.serve_budget_gib,
+            "policy": args.serve_policy}}), flush=True)
         ctx.close()
         return
     if args.gpus != 1:
@@ -516,7 +620,7 @@ def main():
     shot.close()
     if not args.no_serve:
         srv = serving_leg(ctx, B, rates, counts, args.serve_max_shots, int(args.serve_budget_gib * (1 << 30)),
-                          forms, log)
+                          forms, log, shortest=args.serve_policy == "shortest")
         out["serving"] = {"workload": "Poisson arrivals, sizes uniform over {256,384,512,768,1024}, "
                                       "5 ellipses in a 40-px disk, 1e6 photons, 8x8 beamstop, P=32, "
                                       "500 iterations (25 x [HIO^j ER^(20-j), shrink-wrap]) + GetError; "

@@ -314,6 +314,12 @@ typedef struct spr_server spr_server;
 
 #define SPR_SERVER_MANUAL 0x1u      /* no engine thread: the caller drives spr_server_step */
 #define SPR_SERVER_ALL_MEMBERS 0x2u /* results carry every member, not only the best one */
+/* Each tick advances only the shots of one size: that of the resident shot  */
+/* with the least remaining work (modelled at 4 TB/s) less the time it has    */
+/* waited since arrival.  Small shots then pass large ones instead of moving  */
+/* at their pace, and the waiting time keeps large ones from starving.       */
+/* Without it every resident shot advances in every tick.                    */
+#define SPR_SERVER_SHORTEST_FIRST 0x4u
 
 typedef struct spr_server_cfg {
   uint64_t hbm_budget;    /* device bytes held by the server (work buffers + admitted shots) */

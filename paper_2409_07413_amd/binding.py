@@ -105,6 +105,7 @@ class ServerStats(C.Structure):
 
 SERVER_MANUAL = 0x1
 SERVER_ALL_MEMBERS = 0x2
+SERVER_SHORTEST_FIRST = 0x4
 
 EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_supported_size",
            "spr_shot_create", "spr_shot_destroy", "spr_pop_create", "spr_pop_destroy", "spr_pop_write",
@@ -560,13 +561,14 @@ class Server:
     arrival/admit/finish times (seconds on the server clock)."""
 
     def __init__(self, ctx, sched, P, hbm_budget, max_shots, manual=False, all_members=False,
-                 max_inflight=0, max_queue=0, sim_bytes_per_s=0.0, sim_launch_s=0.0):
+                 max_inflight=0, max_queue=0, sim_bytes_per_s=0.0, sim_launch_s=0.0, shortest_first=False):
         self.lib = load()
         self.ctx = ctx
         self.P = int(P)
         self.all_members = bool(all_members)
         cfg = ServerCfg(int(hbm_budget), int(max_shots), self.P, sched.h.value if isinstance(sched.h, C.c_void_p)
-                        else sched.h, (SERVER_MANUAL if manual else 0) | (SERVER_ALL_MEMBERS if all_members else 0),
+                        else sched.h, (SERVER_MANUAL if manual else 0) | (SERVER_ALL_MEMBERS if all_members else 0)
+                        | (SERVER_SHORTEST_FIRST if shortest_first else 0),
                         int(max_inflight), int(max_queue), float(sim_bytes_per_s), float(sim_launch_s))
         h = C.c_void_p()
         st = self.lib.spr_server_create(ctx.h if ctx else None, C.byref(cfg), C.byref(h))

@@ -157,11 +157,19 @@ struct TickPlan {
   bool empty() const { return started.empty() && rounds.empty() && ending.empty(); }
 };
 
+// Which resident shots a tick advances.
+enum TickPolicy {
+  POLICY_ALL = 0,       // every resident shot (lockstep continuous batching)
+  POLICY_SHORTEST = 1,  // the shots of one size: that of the shot with the least remaining
+                        // work, less the time it has waited (aging), first
+};
+
 class Scheduler {
  public:
   Scheduler(const Program& prog, int max_shots, int P, size_t shot_bytes_base, size_t shot_bytes,
-            bool all_members, size_t max_queue)
-      : prog_(prog), P_(P), all_members_(all_members), max_queue_(max_queue), free_slots_() {
+            bool all_members, size_t max_queue, int policy = POLICY_ALL, double bytes_per_s = 4e12)
+      : prog_(prog), P_(P), all_members_(all_members), max_queue_(max_queue), policy_(policy),
+        bytes_per_s_(bytes_per_s), free_slots_() {
     arena_.reset(shot_bytes_base, shot_bytes);
     for (int s = max_shots - 1; s >= 0; --s) free_slots_.push_back(s);
   }
@@ -219,14 +227,35 @@ class Scheduler {
     return out;
   }
 
-  // Plan one tick: every active shot runs its steps up to and including one
-  // sequence (or to its end); steps of equal kind, size and parameters taken
-  // by several shots in the same round become one launch.
-  TickPlan plan(const std::vector<Req*>& started) {
+  // Modelled seconds of device work left for a request (iterations dominate).
+  double remaining_s(const Req* r) const {
+    double its = 0;
+    for (size_t k = (size_t)r->pc; k < prog_.steps.size(); ++k)
+      if (prog_.steps[k].kind == STEP_SEQ) its += prog_.steps[k].nit;
+    return its * (double)r->n * r->n * P_ * 40.0 / bytes_per_s_;
+  }
+
+  // Plan one tick: every advancing shot runs its steps up to and including
+  // one sequence (or to its end); steps of equal kind, size and parameters
+  // taken by several shots in the same round become one launch.
+  TickPlan plan(const std::vector<Req*>& started, double now = 0.0) {
     TickPlan tp;
     tp.id = ++tick_id_;
     tp.started = started;
     std::vector<char> did_seq(active_.size(), 0), stop(active_.size(), 0);
+    if (policy_ == POLICY_SHORTEST && !active_.empty()) {
+      size_t pick = 0;
+      double best = 0;
+      for (size_t i = 0; i < active_.size(); ++i) {
+        const double key = remaining_s(active_[i]) - (now - active_[i]->t_arrival);
+        if (i == 0 || key < best) {
+          best = key;
+          pick = i;
+        }
+      }
+      for (size_t i = 0; i < active_.size(); ++i)
+        if (active_[i]->n != active_[pick]->n) stop[i] = 1;  // waits for a later tick
+    }
     const auto& steps = prog_.steps;
     for (;;) {
       std::map<std::tuple<int, int, int, double, double, double>, size_t> key_of;
@@ -293,6 +322,8 @@ class Scheduler {
   int P_;
   bool all_members_;
   size_t max_queue_;
+  int policy_;
+  double bytes_per_s_;
   Arena arena_;
   std::vector<int> free_slots_;
   std::deque<Req*> queue_;

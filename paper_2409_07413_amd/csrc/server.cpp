@@ -722,7 +722,7 @@ bool engine_round(spr_server* sv) {
   }
   std::vector<Req*> started = sv->sch->admit(sv->ex->now());
   if (sv->sch->active() > 0) {
-    TickPlan tp = sv->sch->plan(started);
+    TickPlan tp = sv->sch->plan(started, sv->ex->now());
     sv->ex->issue(tp);
     did = true;
   }
@@ -791,7 +791,9 @@ spr_status spr_server_create(spr_ctx* ctx, const spr_server_cfg* cfg, spr_server
       base = 0;
       cap = he->budget() - he->reserved();
     }
-    sv->sch.reset(new Scheduler(sv->prog, cfg->max_shots, cfg->P, base, cap, all, (size_t)cfg->max_queue));
+    const int policy = (cfg->flags & SPR_SERVER_SHORTEST_FIRST) ? POLICY_SHORTEST : POLICY_ALL;
+    sv->sch.reset(new Scheduler(sv->prog, cfg->max_shots, cfg->P, base, cap, all, (size_t)cfg->max_queue, policy,
+                                ctx ? 4e12 : cfg->sim_bytes_per_s));
   });
   if (st != SPR_OK) {
     if (ctx) ctx->err = sv->err;

@@ -15,9 +15,9 @@ def sched():
                          sigma_end=1.0, tau=0.1, tau_end=0.1)
 
 
-def server(budget=64 << 20, max_shots=8, P=4, **kw):
+def server(budget=64 << 20, max_shots=8, P=4, launch_s=5e-6, **kw):
     return B.Server(None, sched(), P=P, hbm_budget=budget, max_shots=max_shots, manual=True,
-                    sim_bytes_per_s=1e12, sim_launch_s=5e-6, **kw)
+                    sim_bytes_per_s=1e12, sim_launch_s=launch_s, **kw)
 
 
 def shot(n):
@@ -181,3 +181,46 @@ def test_invalid_configurations():
     memetic = B.sched_ops([B.op(B.OP_SELECT, gen=1)])
     with pytest.raises(B.SprError):
         B.Server(None, memetic, P=4, hbm_budget=1 << 20, max_shots=2, manual=True, sim_bytes_per_s=1e12)
+
+
+def test_shortest_first_lets_small_shots_pass():
+    # bandwidth-dominated model (negligible launch cost), sizes 16x apart in pixels
+    def run_pair(shortest):
+        sv = server(max_shots=2, shortest_first=shortest, launch_s=1e-9)
+        big = sv.submit(*shot(128), arrival=0.0)
+        small = sv.submit(*shot(32), arrival=1e-9)
+        run(sv)
+        rb, rs = sv.poll(big, want_data=False), sv.poll(small, want_data=False)
+        sv.close()
+        return rb, rs
+
+    def alone(n):
+        sv = server(launch_s=1e-9)
+        t = sv.submit(*shot(n), arrival=0.0)
+        run(sv)
+        r = sv.poll(t, want_data=False)
+        sv.close()
+        return r["t_finish"] - r["t_arrival"]
+
+    lat = lambda r: r["t_finish"] - r["t_arrival"]  # noqa: E731
+    rb0, rs0 = run_pair(False)
+    rb1, rs1 = run_pair(True)
+    # lockstep: the small shot advances one sequence per tick of the big one
+    assert lat(rs0) > 0.5 * alone(128)
+    # shortest first: it waits for the big shot's tick in progress, then runs alone
+    assert lat(rs1) <= alone(32) + alone(128) / 3 * 1.05
+    assert rs1["t_finish"] < rb1["t_finish"]
+    # the big shot is delayed by about the small one's work
+    assert lat(rb1) <= alone(128) + alone(32) * 1.05
+
+
+def test_shortest_first_does_not_starve_large_shots():
+    sv = server(max_shots=2, shortest_first=True)
+    big = sv.submit(*shot(96), arrival=0.0)
+    svc = 3e-5  # arrivals of small shots closer than their own service time: a persistent queue
+    smalls = [sv.submit(*shot(32), arrival=1e-6 + k * svc) for k in range(60)]
+    run(sv)
+    rb = sv.poll(big, want_data=False)
+    last = max(sv.poll(t, want_data=False)["t_finish"] for t in smalls)
+    assert rb["t_finish"] < last  # aging lets the large shot through before the stream of small ones ends
+    sv.close()
