@@ -65,10 +65,12 @@ SPR_DEFINE_PLAN(128, 8, 16, 2, 8, 8)
 SPR_DEFINE_PLAN(192, 24, 16, 3, 8, 8)
 SPR_DEFINE_PLAN(256, 8, 16, 4, 8, 8)
 SPR_DEFINE_PLAN(512, 8, 8, 8, 8, 8)
-// 384 and 768: twelve elements per thread (radix-3 pass, then radix 4/2)
-// keep the row kernels at two waves per SIMD; 1024: the radix-16 pass last.
-SPR_DEFINE_PLAN(384, 12, 16, 3, 4, 4, 4, 2)
-SPR_DEFINE_PLAN(768, 12, 8, 3, 4, 4, 4, 4)
+// 384 and 768: twelve elements per thread with the radix-3 pass last, so
+// that the strides of the earlier passes divide T (one twiddle set per pass,
+// kept in registers) and the first exchange is not a stride-3 pattern;
+// 1024: the radix-16 pass last.
+SPR_DEFINE_PLAN(384, 12, 16, 4, 4, 4, 2, 3)
+SPR_DEFINE_PLAN(768, 12, 8, 4, 4, 4, 4, 3)
 SPR_DEFINE_PLAN(1024, 16, 8, 8, 8, 16)
 
 // ---------------------------------------------------------------------------
@@ -227,10 +229,21 @@ template <bool WAVE> __device__ __forceinline__ void lds_sync() {
 // Per-thread twiddle set: the twiddles of every pass after the first, for the
 // butterflies of thread t, in the forward direction.  A kernel that runs
 // several transforms (inverse ones use the conjugates) loads them once.
+// A pass whose stride NS (product of the earlier radices) divides T gives
+// every butterfly j = t + k T of a thread the same twiddles (j mod NS =
+// t mod NS): they are formed once per pass instead of once per butterfly.
+template <int N> __host__ __device__ constexpr int pass_ns(int pass) {
+  using P = Plan<N>;
+  int ns = 1;
+  for (int p = 0; p < pass; ++p) ns *= P::radix(p);
+  return ns;
+}
+template <int N> __host__ __device__ constexpr bool tw_shared(int pass) { return Plan<N>::T % pass_ns<N>(pass) == 0; }
 template <int N, int PASS> __host__ __device__ constexpr int tw_offset() {
   using P = Plan<N>;
   int off = 0;
-  for (int p = 1; p < PASS && p < P::passes(); ++p) off += (P::E / P::radix(p)) * (P::radix(p) - 1);
+  for (int p = 1; p < PASS && p < P::passes(); ++p)
+    off += (tw_shared<N>(p) ? 1 : P::E / P::radix(p)) * (P::radix(p) - 1);
   return off;
 }
 template <int N> __host__ __device__ constexpr int tw_count() { return tw_offset<N, 64>(); }
@@ -238,8 +251,11 @@ template <int N> __host__ __device__ constexpr int tw_count() { return tw_offset
 #ifndef SPR_TWSET
 #define SPR_TWSET 1
 #endif
+#ifndef SPR_TWSET_MAX
+#define SPR_TWSET_MAX 20
+#endif
 template <int N> constexpr bool tw_in_regs() {
-  return SPR_TWSET && tw_count<N>() > 0 && tw_count<N>() <= 16;
+  return SPR_TWSET && tw_count<N>() > 0 && tw_count<N>() <= SPR_TWSET_MAX;
 }
 
 template <int N> struct TwSet {
@@ -253,8 +269,9 @@ __device__ __forceinline__ void fill_tw(TwSet<N>& s, int t, const float2* __rest
     constexpr int R = P::radix(PASS), NB = P::E / R, T = P::T;
     if constexpr (PASS > 0) {
       constexpr int step = N / (NS * R);
+      constexpr int NK = tw_shared<N>(PASS) ? 1 : NB;
 #pragma unroll
-      for (int k = 0; k < NB; ++k) {
+      for (int k = 0; k < NK; ++k) {
         float2 w[R];
         twiddles_for<R, -1>(tw, ((t + k * T) % NS) * step, w);
 #pragma unroll
@@ -282,6 +299,11 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[Plan<N>::E], float2* lds,
     constexpr int NB = E / R;
     constexpr bool LAST = (PASS == P::passes() - 1);
     static_assert(E % R == 0, "plan: E must be a multiple of every radix");
+    constexpr bool SHARED = tw_shared<N>(PASS);
+    constexpr int step = N / (NS * R);
+    // twiddles common to all butterflies of the thread (stride dividing T)
+    float2 wsh[R];
+    if constexpr (NS > 1 && SHARED && !PRE) twiddles_for<R, DIR>(tw, (t % NS) * step, wsh);
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
       const int j = t + k * T;
@@ -290,13 +312,16 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[Plan<N>::E], float2* lds,
       for (int r = 0; r < R; ++r) a[r] = v[k + r * NB];
       if constexpr (NS > 1) {
         if constexpr (PRE) {
+          constexpr int KS = SHARED ? 0 : 1;
 #pragma unroll
           for (int r = 1; r < R; ++r) {
-            const float2 w = ws->w[tw_offset<N, PASS>() + k * (R - 1) + r - 1];
+            const float2 w = ws->w[tw_offset<N, PASS>() + KS * k * (R - 1) + r - 1];
             a[r] = cmul(a[r], DIR < 0 ? w : cconj(w));
           }
+        } else if constexpr (SHARED) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) a[r] = cmul(a[r], wsh[r]);
         } else {
-          constexpr int step = N / (NS * R);
           float2 w[R];
           twiddles_for<R, DIR>(tw, (j % NS) * step, w);
 #pragma unroll
