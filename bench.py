@@ -420,6 +420,88 @@ def graph_study(ctx, B, passes=10):
     return out
 
 
+# ---------------------------------------------------------------------------
+# Batched uneven shots: autotuned kernels, one launch per size and step
+# ---------------------------------------------------------------------------
+def batch_study(ctx, B, shots=32, P_batch=32, G=50):
+    """32 shots of sizes drawn from {256,...,1024}, P = 32 each, 1000 iterations
+    (50 blocks of HIO^j ER^(20-j) with shrink-wrap) + GetError: (1) one
+    population at a time (spr_run), (2) all shots in one batch (spr_run_batch:
+    members of one size share every launch), (3) the batch replayed from a
+    captured graph; kernels and member chunks tuned per size first."""
+    import torch  # noqa: F401
+    from paper_2409_07413_amd import synth
+    rng = np.random.default_rng(1003)
+    sizes = rng.choice(SERVE_SIZES, size=shots)
+    photons = 10.0 ** rng.uniform(6.0, 8.0, size=shots)
+    tuning = {int(n): ctx.autotune(int(n), P_batch * int((sizes == n).sum())) for n in sorted(set(sizes))}
+    data = []
+    for i, (n, ph) in enumerate(zip(sizes, photons)):
+        sh = synth.shot(int(n), "ellipses", 1003 + 7 * i, float(ph), beamstop=8)
+        data.append((int(n), sh["amp"].astype(np.float32), sh["mask"].astype(np.uint8)))
+    supp = {n: synth.centred_square(n, 48).astype(np.uint8) for n in SERVE_SIZES}
+
+    def make():
+        out = []
+        for i, (n, amp, mask) in enumerate(data):
+            shot = ctx.shot(amp, mask)
+            out.append((shot, shot.population(None, supp[n], seed=9000 + i, P=P_batch)))
+        return out
+
+    sched = B.sched_plain(ctx, alg=B.ALG_HIO, G=G, j=16, j_er=4, j_end=0, beta=0.9, chi=0.5, sigma=2.0,
+                          sigma_end=1.0, tau=0.10, tau_end=0.10)
+    member_its = shots * P_batch * 20 * G
+    px_its = sum(n * n for n, _, _ in data) * P_batch * 20 * G
+    res = {"shots": shots, "P": P_batch, "iterations": 20 * G, "sizes": [int(n) for n in sizes],
+           "tuning": {str(k): {"variant": v["variant"], "chunk_members": v["chunk_members"]} for k, v in tuning.items()}}
+    import torch
+    # (1) one population at a time
+    pops = make()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _, pop in pops:
+        pop.run(sched)
+    for _, pop in pops:
+        pop.sync()
+    res["one_at_a_time_s"] = time.perf_counter() - t0
+    first = [pop.errors() for _, pop in pops]
+    for shot, pop in pops:
+        pop.close()
+        shot.close()
+    # (2) one batch, eager
+    pops = make()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.run_batch([p for _, p in pops], [sched] * shots)
+    for _, pop in pops:
+        pop.sync()
+    res["batch_s"] = time.perf_counter() - t0
+    res["batch_equals_one_at_a_time"] = bool(all(np.array_equal(a, pop.errors()) for a, (_, pop) in zip(first, pops)))
+    for shot, pop in pops:
+        pop.close()
+        shot.close()
+    # (3) the batch from a captured graph
+    pops = make()
+    g = ctx.graph_batch([p for _, p in pops], [sched] * shots)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.launch()
+    for _, pop in pops:
+        pop.sync()
+    res["graph_s"] = time.perf_counter() - t0
+    res["graph_equals_one_at_a_time"] = bool(all(np.array_equal(a, pop.errors()) for a, (_, pop) in zip(first, pops)))
+    g.close()
+    for shot, pop in pops:
+        pop.close()
+        shot.close()
+    sched.close()
+    for k in ("one_at_a_time", "batch", "graph"):
+        t = res[k + "_s"]
+        res[k] = {"member_iterations_per_s": member_its / t, "iteration_pixels_per_s": px_its / t,
+                  "pct_hbm_peak_iterations": px_its * 40.0 / t / (HBM_PEAK_GBS * 1e9)}
+    return res
+
+
 def copy_calibration():
     """A plain copy kernel of known size: 256 MiB read + 256 MiB written per
     launch (torch copy_, a hipMemcpy device-to-device kernel).  Its FETCH_SIZE /
@@ -468,9 +550,19 @@ def main():
                     help="time the iteration kernels at every served detector size and exit")
     ap.add_argument("--graph-study", action="store_true",
                     help="compare captured-graph replays with eager schedule runs and exit")
+    ap.add_argument("--batch-study", action="store_true",
+                    help="32 uneven shots: one at a time, one batch, one captured batch (after tuning) and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.batch_study:
+        import torch  # noqa: F401
+        from paper_2409_07413_amd import binding as B
+        ctx = B.Context(0)
+        ctx.set_cache_budget(CACHE_BUDGET)
+        print(json.dumps({"batch_study": batch_study(ctx, B)}), flush=True)
+        ctx.close()
         return
     if args.size_sweep or args.graph_study:
         import torch  # noqa: F401

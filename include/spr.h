@@ -84,6 +84,30 @@ int32_t spr_supported_size(int32_t n);
 /* results do not depend on it.  0 = one chunk.                                  */
 spr_status spr_ctx_set_cache_budget(spr_ctx* ctx, uint64_t bytes);
 
+/* Tuning.  Sizes 256, 384, 512, 768 and 1024 are compiled twice: variant 0  */
+/* (the default plan) and variant 1 (the other column-tile width, or for 1024 */
+/* the other radix order).  spr_ctx_autotune times RAAR iterations on        */
+/* `members` synthetic members of size n for every variant and member-chunk  */
+/* candidate (all members, the chunk whose two work buffers fit 256 MiB, half */
+/* of it), keeps the fastest on the context and reports every candidate.     */
+/* The variant applies to shots (and their populations) created afterwards;  */
+/* the chunk to every later iteration run of that size.  Results do not      */
+/* depend on the choice beyond floating-point rounding of the transform.     */
+#define SPR_TUNE_MAX 16
+typedef struct spr_tune_result {
+  int32_t n, variant, chunk_members, candidates;
+  double member_iterations_per_s;    /* of the choice */
+  int32_t cand_variant[SPR_TUNE_MAX];
+  int32_t cand_chunk[SPR_TUNE_MAX];
+  double cand_rate[SPR_TUNE_MAX];    /* member-iterations/s */
+} spr_tune_result;
+/* Number of compiled kernel variants of size n (0 if unsupported). */
+int32_t spr_size_variants(int32_t n);
+spr_status spr_ctx_autotune(spr_ctx* ctx, int32_t n, int32_t members, spr_tune_result* out);
+/* Set the choice by hand (chunk_members 0: the cache-budget rule). */
+spr_status spr_ctx_set_variant(spr_ctx* ctx, int32_t n, int32_t variant, int32_t chunk_members);
+spr_status spr_ctx_get_tuning(spr_ctx* ctx, int32_t n, int32_t* variant, int32_t* chunk_members);
+
 /* ------------------------------------------------------------------------- */
 /* Shot: the measured modulus M = sqrt(I) and mask Xi (1 = measured) of one    */
 /* diffraction pattern (section "The phase problem...", Eq. pm_full).         */

@@ -103,6 +103,12 @@ class ServerStats(C.Structure):
                 ("bytes_in_use", C.c_uint64), ("bytes_peak", C.c_uint64)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("n", C.c_int32), ("variant", C.c_int32), ("chunk_members", C.c_int32), ("candidates", C.c_int32),
+                ("member_iterations_per_s", C.c_double), ("cand_variant", C.c_int32 * 16),
+                ("cand_chunk", C.c_int32 * 16), ("cand_rate", C.c_double * 16)]
+
+
 SERVER_MANUAL = 0x1
 SERVER_ALL_MEMBERS = 0x2
 SERVER_SHORTEST_FIRST = 0x4
@@ -112,7 +118,8 @@ EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_suppo
            "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
            "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
            "spr_timing_enable", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch",
-           "spr_read_member", "spr_graph_create", "spr_graph_create_batch", "spr_graph_launch",
+           "spr_read_member", "spr_size_variants", "spr_ctx_autotune", "spr_ctx_set_variant",
+           "spr_ctx_get_tuning", "spr_graph_create", "spr_graph_create_batch", "spr_graph_launch",
            "spr_graph_destroy", "spr_server_create", "spr_server_submit", "spr_server_poll", "spr_server_step", "spr_server_drain",
            "spr_server_stats_get", "spr_server_last_error", "spr_server_destroy"]
 
@@ -151,6 +158,10 @@ def _proto(lib):
         "spr_ctx_set_cache_budget": (i32, [vp, C.c_uint64]),
         "spr_run_batch": (i32, [vp, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), i32, vp]),
         "spr_read_member": (i32, [vp, i32, vp, vp, u32]),
+        "spr_size_variants": (i32, [i32]),
+        "spr_ctx_autotune": (i32, [vp, i32, i32, C.POINTER(TuneResult)]),
+        "spr_ctx_set_variant": (i32, [vp, i32, i32, i32]),
+        "spr_ctx_get_tuning": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32)]),
         "spr_graph_create": (i32, [vp, vp, pp]),
         "spr_graph_create_batch": (i32, [vp, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), i32, pp]),
         "spr_graph_launch": (i32, [vp, vp]),
@@ -313,6 +324,23 @@ class Context:
         ph = (C.c_void_p * n)(*[p.h.value if isinstance(p.h, C.c_void_p) else p.h for p in pops])
         sh = (C.c_void_p * n)(*[s.h.value if isinstance(s.h, C.c_void_p) else s.h for s in scheds])
         self._check(self.lib.spr_run_batch(self.h, ph, sh, n, _stream_ptr(stream)))
+
+    def autotune(self, n, members):
+        """Time every kernel variant and member chunk of size n; keep the fastest."""
+        r = TuneResult()
+        self._check(self.lib.spr_ctx_autotune(self.h, int(n), int(members), C.byref(r)))
+        cands = [{"variant": r.cand_variant[i], "chunk_members": r.cand_chunk[i],
+                  "member_iterations_per_s": r.cand_rate[i]} for i in range(r.candidates)]
+        return {"n": r.n, "variant": r.variant, "chunk_members": r.chunk_members,
+                "member_iterations_per_s": r.member_iterations_per_s, "candidates": cands}
+
+    def set_variant(self, n, variant, chunk_members=0):
+        self._check(self.lib.spr_ctx_set_variant(self.h, int(n), int(variant), int(chunk_members)))
+
+    def tuning(self, n):
+        v, c = C.c_int32(), C.c_int32()
+        self._check(self.lib.spr_ctx_get_tuning(self.h, int(n), C.byref(v), C.byref(c)))
+        return v.value, c.value
 
     def graph_batch(self, pops, scheds):
         """Capture a batch (as run_batch would run it) into a replayable graph."""

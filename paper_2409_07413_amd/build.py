@@ -1,6 +1,7 @@
 """Build libspr.so (HIP for gfx950) in-tree.
 
-Every per-size kernel object is compiled from kernels_n.hip with -DSPR_N=<n>;
+Every per-size kernel object is compiled from kernels_n.hip with -DSPR_N=<n>
+(and -DSPR_VARIANT=<v> for the sizes with a tunable alternative plan);
 objects are compiled in parallel and linked with hipcc into
 paper_2409_07413_amd/libspr.so.  Run ``python -m paper_2409_07413_amd.build``.
 """
@@ -17,6 +18,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspr.so")
 
 SIZES = (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024)
+# sizes compiled with an alternative plan (variant 1) for the run-time tuner
+VARIANT_SIZES = (256, 384, 512, 768, 1024)
 ARCH = os.environ.get("SPR_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # extra compile definitions and an alternative output path (tuning builds)
@@ -39,7 +42,9 @@ FLAGS = [
 def _jobs():
     jobs = []
     for n in SIZES:
-        jobs.append((os.path.join(CSRC, "kernels_n.hip"), os.path.join(OBJ, f"kernels_{n}.o"), [f"-DSPR_N={n}"]))
+        for v in ((0, 1) if n in VARIANT_SIZES else (0,)):
+            jobs.append((os.path.join(CSRC, "kernels_n.hip"), os.path.join(OBJ, f"kernels_{n}_{v}.o"),
+                         [f"-DSPR_N={n}", f"-DSPR_VARIANT={v}"]))
     jobs.append((os.path.join(CSRC, "kernels_common.hip"), os.path.join(OBJ, "kernels_common.o"), []))
     jobs.append((os.path.join(CSRC, "runtime.cpp"), os.path.join(OBJ, "runtime.o"), ["-x", "hip"]))
     jobs.append((os.path.join(CSRC, "server.cpp"), os.path.join(OBJ, "server.o"), ["-x", "hip"]))

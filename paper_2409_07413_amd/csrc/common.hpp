@@ -197,7 +197,10 @@ struct SizeKernels {
   hipError_t (*col_mix)(const ColMixArgs&, hipStream_t);
 };
 
-const SizeKernels* size_kernels(int n);
+// Compiled kernels of size n: variant 0 (default plan) or another variant
+// (size_variants(n) of them); null for an unsupported size or variant.
+const SizeKernels* size_kernels(int n, int variant = 0);
+int size_variants(int n);
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): multipliers 0xD2511F53, 0xCD9E8D57,

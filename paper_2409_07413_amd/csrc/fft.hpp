@@ -63,15 +63,30 @@ SPR_DEFINE_PLAN(64, 8, 16, 8, 8)
 SPR_DEFINE_PLAN(96, 24, 16, 3, 4, 8)
 SPR_DEFINE_PLAN(128, 8, 16, 2, 8, 8)
 SPR_DEFINE_PLAN(192, 24, 16, 3, 8, 8)
-SPR_DEFINE_PLAN(256, 8, 16, 4, 8, 8)
-SPR_DEFINE_PLAN(512, 8, 8, 8, 8, 8)
 // 384 and 768: twelve elements per thread with the radix-3 pass last, so
 // that the strides of the earlier passes divide T (one twiddle set per pass,
 // kept in registers) and the first exchange is not a stride-3 pattern;
 // 1024: the radix-16 pass last.
+//
+// Variant 1 of the served sizes is the alternative that a run-time tuner
+// weighs against the default: the other column-tile width (256 to 768) or
+// the other radix order (1024).
+#ifndef SPR_VARIANT
+#define SPR_VARIANT 0
+#endif
+#if SPR_VARIANT == 1
+SPR_DEFINE_PLAN(256, 8, 8, 4, 8, 8)
+SPR_DEFINE_PLAN(512, 8, 16, 8, 8, 8)
+SPR_DEFINE_PLAN(384, 12, 8, 4, 4, 4, 2, 3)
+SPR_DEFINE_PLAN(768, 12, 16, 4, 4, 4, 4, 3)
+SPR_DEFINE_PLAN(1024, 16, 8, 16, 8, 8)
+#else
+SPR_DEFINE_PLAN(256, 8, 16, 4, 8, 8)
+SPR_DEFINE_PLAN(512, 8, 8, 8, 8, 8)
 SPR_DEFINE_PLAN(384, 12, 16, 4, 4, 4, 2, 3)
 SPR_DEFINE_PLAN(768, 12, 8, 4, 4, 4, 4, 3)
 SPR_DEFINE_PLAN(1024, 16, 8, 8, 8, 16)
+#endif
 
 // ---------------------------------------------------------------------------
 // Small DFT butterflies, in place: a[k] <- sum_r a[r] exp(DIR 2 pi i r k / R)

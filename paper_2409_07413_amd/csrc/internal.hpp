@@ -42,6 +42,10 @@ struct spr_ctx {
   // iteration runs are split into member chunks whose two work buffers fit in
   // this many bytes (0: no split), so that they stay in the memory-side cache
   size_t cache_budget = (size_t)256 << 20;
+  // per-size choices of the tuner (or of the caller): kernel variant for
+  // shots created from now on, members per iteration launch (0: the budget rule)
+  std::map<int, int> variant;
+  std::map<int, int> chunk_members;
   std::string err;
   std::map<int, float2*> tw;
   std::map<int, Workspace> ws;
@@ -182,6 +186,12 @@ spr_status guarded(spr_ctx* ctx, Fn&& fn) {
 }
 
 void use_device(spr_ctx* ctx) { HIPCHK(hipSetDevice(ctx->device)); }
+
+// Kernels of size n in the variant selected on the context (default 0).
+const SizeKernels* ctx_kernels(spr_ctx* ctx, int n) {
+  auto it = ctx->variant.find(n);
+  return size_kernels(n, it == ctx->variant.end() ? 0 : it->second);
+}
 
 const float2* twiddles(spr_ctx* ctx, int n) {
   std::lock_guard<std::mutex> g(ctx->mu);
@@ -365,6 +375,8 @@ struct Group {
 };
 
 int chunk_for(spr_ctx* ctx, int n, int nm) {
+  auto it = ctx->chunk_members.find(n);
+  if (it != ctx->chunk_members.end() && it->second > 0) return std::min(nm, it->second);
   if (ctx->cache_budget == 0) return nm;
   const size_t per_member = 2 * (size_t)n * n * sizeof(float2);
   return (int)std::min<size_t>((size_t)nm, std::max<size_t>(1, ctx->cache_budget / per_member));
@@ -873,6 +885,8 @@ std::vector<BatchGroup> plan_batch(spr_ctx* ctx, spr_pop* const* pops, const spr
     size_t total = 0;
     for (int i : bg.idx) total += pops[i]->nslots;
     const SizeKernels* K = pops[bg.idx[0]]->K;
+    for (int i : bg.idx)
+      if (pops[i]->K != K) fail(SPR_E_INVALID_ARG, "populations of one size were created with different kernel variants");
     Workspace& w = ws_for(bg.n, total, K);
     std::vector<int> slots;
     std::vector<SlotDesc> descs;

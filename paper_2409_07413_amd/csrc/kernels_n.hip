@@ -596,8 +596,8 @@ const SizeKernels kTable = {N,          E,          T,          C,           RW,
 
 }  // namespace
 
-#define SPR_CAT2(a, b) a##b
-#define SPR_CAT(a, b) SPR_CAT2(a, b)
-const SizeKernels* SPR_CAT(size_kernels_, SPR_N)() { return &kTable; }
+#define SPR_CAT4_(a, b, c, d) a##b##c##d
+#define SPR_CAT4(a, b, c, d) SPR_CAT4_(a, b, c, d)
+const SizeKernels* SPR_CAT4(size_kernels_, SPR_N, _, SPR_VARIANT)() { return &kTable; }
 
 }  // namespace spr

@@ -19,22 +19,36 @@
 
 namespace spr {
 
-#define SPR_SIZES(X) \
-  X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
-#define SPR_DECL(n) const SizeKernels* size_kernels_##n();
-SPR_SIZES(SPR_DECL)
-#undef SPR_DECL
+// sizes with one compiled plan (V1) and with a tunable alternative (V2)
+#define SPR_SIZES(V1, V2)                                                                  \
+  V1(8) V1(12) V1(16) V1(24) V1(32) V1(48) V1(64) V1(96) V1(128) V1(192) V2(256) V2(384) \
+      V2(512) V2(768) V2(1024)
+#define SPR_DECL1(n) const SizeKernels* size_kernels_##n##_0();
+#define SPR_DECL2(n) SPR_DECL1(n) const SizeKernels* size_kernels_##n##_1();
+SPR_SIZES(SPR_DECL1, SPR_DECL2)
+#undef SPR_DECL1
+#undef SPR_DECL2
 
-const SizeKernels* size_kernels(int n) {
+const SizeKernels* size_kernels(int n, int v) {
   switch (n) {
-#define SPR_CASE(n) \
-  case n:           \
-    return size_kernels_##n();
-    SPR_SIZES(SPR_CASE)
-#undef SPR_CASE
+#define SPR_CASE1(n) \
+  case n:            \
+    return v == 0 ? size_kernels_##n##_0() : nullptr;
+#define SPR_CASE2(n) \
+  case n:            \
+    return v == 0 ? size_kernels_##n##_0() : (v == 1 ? size_kernels_##n##_1() : nullptr);
+    SPR_SIZES(SPR_CASE1, SPR_CASE2)
+#undef SPR_CASE1
+#undef SPR_CASE2
     default:
       return nullptr;
   }
+}
+
+int size_variants(int n) {
+  int v = 0;
+  while (size_kernels(n, v)) ++v;
+  return v;
 }
 
 }  // namespace spr
@@ -102,7 +116,7 @@ spr_status spr_shot_create(spr_ctx* ctx, int32_t n, const float* amp, const uint
   if (!live_has(ctx)) return SPR_E_INVALID_ARG;
   *out = nullptr;
   return guarded(ctx, [&] {
-    const SizeKernels* K = size_kernels(n);
+    const SizeKernels* K = ctx_kernels(ctx, n);
     if (!K) fail(SPR_E_UNSUPPORTED_SIZE, "unsupported detector size " + std::to_string(n));
     use_device(ctx);
     const size_t nn = (size_t)n * n;
@@ -663,7 +677,7 @@ spr_status spr_fft2(spr_ctx* ctx, int32_t n, int32_t batch, const float* in, flo
                     void* hip_stream) {
   if (!ctx || !in || !out || batch < 0) return SPR_E_INVALID_ARG;
   return guarded(ctx, [&] {
-    const SizeKernels* K = size_kernels(n);
+    const SizeKernels* K = ctx_kernels(ctx, n);
     if (!K) fail(SPR_E_UNSUPPORTED_SIZE, "unsupported size " + std::to_string(n));
     if (batch == 0) return;
     use_device(ctx);
@@ -676,6 +690,156 @@ spr_status spr_fft2(spr_ctx* ctx, int32_t n, int32_t batch, const float* in, flo
     ColFftArgs c{nullptr, nullptr, batch, reinterpret_cast<float2*>(out), reinterpret_cast<float2*>(out), dir,
                  1.f / (float)n, tw};
     launch_ok(K->col_fft(c, s), "col_fft");
+  });
+}
+
+int32_t spr_size_variants(int32_t n) { return size_variants(n); }
+
+spr_status spr_ctx_set_variant(spr_ctx* ctx, int32_t n, int32_t variant, int32_t chunk_members) {
+  if (!ctx || !live_has(ctx)) return SPR_E_INVALID_ARG;
+  return guarded(ctx, [&] {
+    if (!size_kernels(n)) fail(SPR_E_UNSUPPORTED_SIZE, "unsupported size " + std::to_string(n));
+    if (variant < 0 || variant >= size_variants(n))
+      fail(SPR_E_INVALID_ARG, "size " + std::to_string(n) + " has " + std::to_string(size_variants(n)) +
+                                  " kernel variants");
+    if (chunk_members < 0) fail(SPR_E_INVALID_ARG, "negative chunk");
+    ctx->variant[n] = variant;
+    ctx->chunk_members[n] = chunk_members;
+  });
+}
+
+spr_status spr_ctx_get_tuning(spr_ctx* ctx, int32_t n, int32_t* variant, int32_t* chunk_members) {
+  if (!ctx || !variant || !chunk_members || !live_has(ctx)) return SPR_E_INVALID_ARG;
+  auto v = ctx->variant.find(n);
+  auto c = ctx->chunk_members.find(n);
+  *variant = v == ctx->variant.end() ? 0 : v->second;
+  *chunk_members = c == ctx->chunk_members.end() ? 0 : c->second;
+  return SPR_OK;
+}
+
+spr_status spr_ctx_autotune(spr_ctx* ctx, int32_t n, int32_t members, spr_tune_result* out) {
+  if (!ctx || !out || members < 1 || !live_has(ctx)) return SPR_E_INVALID_ARG;
+  return guarded(ctx, [&] {
+    if (!size_kernels(n)) fail(SPR_E_UNSUPPORTED_SIZE, "unsupported size " + std::to_string(n));
+    use_device(ctx);
+    std::memset(out, 0, sizeof(*out));
+    const size_t nn = (size_t)n * n;
+    const int W = (int)((nn + 31) / 32);
+    hipStream_t s = ctx->stream;
+    // a synthetic shot (unit modulus, all measured) and a random-phase population
+    std::vector<float> one(nn, 1.0f);
+    std::vector<uint32_t> bits((size_t)W * members, 0xffffffffu);
+    std::vector<int> ident(members);
+    for (int m = 0; m < members; ++m) ident[m] = m;
+    float* amp = nullptr;
+    float2 *X = nullptr, *T = nullptr, *Y = nullptr;
+    uint32_t* S = nullptr;
+    double *E = nullptr, *errp = nullptr;
+    float *bmax = nullptr, *maxv = nullptr;
+    int *flags = nullptr, *slots = nullptr;
+    SlotDesc* desc = nullptr;
+    std::vector<hipEvent_t> ev;
+    auto cleanup = [&] {
+      (void)hipStreamSynchronize(s);
+      for (void* q : {(void*)amp, (void*)X, (void*)T, (void*)Y, (void*)S, (void*)E, (void*)errp, (void*)bmax,
+                      (void*)maxv, (void*)flags, (void*)slots, (void*)desc})
+        if (q) (void)hipFree(q);
+      for (auto e : ev) (void)hipEventDestroy(e);
+    };
+    try {
+      const SizeKernels* K0 = size_kernels(n, 0);
+      amp = dalloc<float>(nn);
+      X = dalloc<float2>(nn * members);
+      T = dalloc<float2>(nn * members);
+      Y = dalloc<float2>(nn * members);
+      S = dalloc<uint32_t>((size_t)W * members);
+      E = dalloc<double>(members);
+      errp = dalloc<double>((size_t)members * n);
+      bmax = dalloc<float>((size_t)members * smooth_blocks_per_member(n));
+      maxv = dalloc<float>(members);
+      flags = dalloc<int>(1);
+      slots = dalloc<int>(members);
+      desc = dalloc<SlotDesc>(members);
+      HIPCHK(hipMemcpy(amp, one.data(), nn * sizeof(float), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(S, bits.data(), bits.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(slots, ident.data(), sizeof(int) * members, hipMemcpyHostToDevice));
+      std::vector<SlotDesc> dh(members);
+      for (int m = 0; m < members; ++m) {
+        dh[m].X = X + (size_t)m * nn;
+        dh[m].T = T + (size_t)m * nn;
+        dh[m].S = S + (size_t)m * W;
+        dh[m].amp = amp;
+        dh[m].amp16 = nullptr;
+        dh[m].E = E + m;
+        dh[m].den = (double)nn;
+        dh[m].flags = flags;
+        dh[m].amp_scale = 1.f;
+        dh[m].pad = 0;
+      }
+      HIPCHK(hipMemcpy(desc, dh.data(), sizeof(SlotDesc) * members, hipMemcpyHostToDevice));
+      (void)twiddles(ctx, n);
+      random_phase_start(ctx, K0, n, members, amp, nullptr, 1.f, 12345, X, s);
+      for (int k = 0; k < 2; ++k) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        ev.push_back(e);
+      }
+      const std::vector<Iter> its(10, Iter{ALG_RAAR, 0.9f, 0.5});
+      std::vector<int> chunks = {members};
+      const int resident = (int)std::max<size_t>(1, ((size_t)256 << 20) / (2 * nn * sizeof(float2)));
+      for (int c : {resident, resident / 2})
+        if (c >= 1 && c < members && std::find(chunks.begin(), chunks.end(), c) == chunks.end()) chunks.push_back(c);
+      double best = -1;
+      int nc = 0;
+      for (int v = 0; v < size_variants(n); ++v) {
+        for (int c : chunks) {
+          Group g;
+          g.ctx = ctx;
+          g.K = size_kernels(n, v);
+          g.n = n;
+          g.W = W;
+          g.slots = slots;
+          g.nm = members;
+          g.desc = desc;
+          g.T = T;
+          g.Y = Y;
+          g.err_partial = errp;
+          g.block_max = bmax;
+          g.maxv = maxv;
+          g.flags = flags;
+          g.timing = nullptr;
+          g.chunk = c;
+          run_iterations(g, its, s);  // warm-up
+          HIPCHK(hipEventRecord(ev[0], s));
+          for (int rep = 0; rep < 3; ++rep) run_iterations(g, its, s);
+          HIPCHK(hipEventRecord(ev[1], s));
+          HIPCHK(hipEventSynchronize(ev[1]));
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+          const double rate = (double)members * its.size() * 3 / (ms * 1e-3);
+          if (nc < SPR_TUNE_MAX) {
+            out->cand_variant[nc] = v;
+            out->cand_chunk[nc] = c;
+            out->cand_rate[nc] = rate;
+            ++nc;
+          }
+          if (rate > best) {
+            best = rate;
+            out->variant = v;
+            out->chunk_members = c;
+          }
+        }
+      }
+      out->n = n;
+      out->candidates = nc;
+      out->member_iterations_per_s = best;
+      ctx->variant[n] = out->variant;
+      ctx->chunk_members[n] = out->chunk_members;
+    } catch (...) {
+      cleanup();
+      throw;
+    }
+    cleanup();
   });
 }
 

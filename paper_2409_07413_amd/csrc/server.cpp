@@ -234,7 +234,8 @@ class HipExec : public Exec {
     max_tiles_ = 1;
     max_blocks_ = 1;
     for (int n = 8; n <= 1024; ++n)
-      if (const SizeKernels* K = size_kernels(n)) {
+      if (const SizeKernels* K = ctx_kernels(ctx, n)) {
+        Ks_[n] = K;  // the context's kernel variant of each size, fixed for the server's life
         max_tiles_ = std::max(max_tiles_, n / K->C);
         max_blocks_ = std::max(max_blocks_, smooth_blocks_per_member(n));
       }
@@ -419,7 +420,7 @@ class HipExec : public Exec {
   Group group(int n, const int* slots, int nm) {
     Group g;
     g.ctx = ctx_;
-    g.K = size_kernels(n);
+    g.K = Ks_.at(n);
     g.n = n;
     g.W = (int)(((size_t)n * n + 31) / 32);
     g.slots = slots;
@@ -493,7 +494,7 @@ class HipExec : public Exec {
         launch(launch_pack(pa, s_), "pack");
       }
       if (init) {
-        random_phase_start(ctx_, size_kernels(n), n, P, fp16 ? nullptr : dev<float>(L.amp),
+        random_phase_start(ctx_, Ks_.at(n), n, P, fp16 ? nullptr : dev<float>(L.amp),
                            fp16 ? dev<__half>(L.amp) : nullptr, amp_scale, seed, dev<float2>(L.X), s_);
         launches += 3;
       } else {
@@ -518,7 +519,7 @@ class HipExec : public Exec {
     const int n = L.n;
     const size_t nn = (size_t)n * n;
     const int total = (int)slots.size();
-    const SizeKernels* K = size_kernels(n);
+    const SizeKernels* K = Ks_.at(n);
     const float2* tw = twiddles(ctx_, n);
     if (L.kind == STEP_SEQ) {
       const int chunk = (int)std::max<size_t>(1, ws_bytes_ / (8 * nn));
@@ -655,6 +656,7 @@ class HipExec : public Exec {
   size_t meta_used_ = 0;
   std::vector<std::function<void()>> ops_;
   std::vector<hipEvent_t> events_;
+  std::map<int, const SizeKernels*> Ks_;
   PinnedPool pool_;
 };
 
