@@ -502,6 +502,111 @@ def batch_study(ctx, B, shots=32, P_batch=32, G=50):
     return res
 
 
+# ---------------------------------------------------------------------------
+# The other single-shot configurations
+# ---------------------------------------------------------------------------
+def plain_128_study(ctx, B):
+    """128^2, five ellipses in a 40-px disk, 1e6 photons, 8x8 beamstop, P = 8
+    random-phase starts (seed 2001), centred 48 x 48 start support; 10 blocks
+    of HIO^j ER^(20-j) (j 16 -> 0, beta 0.9) with shrink-wrap (sigma 2 -> 1,
+    tau 0.10) and a final GetError.  FP32 device run against the FP64 oracle
+    run of the same schedule from the same start, beside the oracle's own
+    divergence under an FP32-rounding perturbation of the start."""
+    import torch
+    from oracle import mpr
+    from paper_2409_07413_amd import synth
+    n, P, seed = 128, 8, 2001
+    sh0 = synth.shot(n, "ellipses", 1001, 1e6, beamstop=8)
+    amp = sh0["amp"].astype(np.float32)
+    mask = sh0["mask"].astype(np.uint8)
+    S0 = synth.centred_square(n, 48)
+    sched = B.sched_plain(ctx, alg=B.ALG_HIO, G=10, j=16, j_er=4, j_end=0, beta=0.9, chi=0.5, sigma=2.0,
+                          sigma_end=1.0, tau=0.10, tau_end=0.10)
+    shot = ctx.shot(amp, mask)
+    pop = shot.population(None, S0.astype(np.uint8), seed=seed, P=P)
+    x0 = pop.read()[0].astype(np.complex128)
+    stream = torch.cuda.Stream()
+    reps = 20
+    pops = [shot.population(None, S0.astype(np.uint8), seed=seed, P=P) for _ in range(reps)]
+    pops[0].run(sched, stream)
+    pops[0].sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in pops[1:]:
+        q.run(sched, stream)
+    torch.cuda.synchronize()
+    gpu_s = (time.perf_counter() - t0) / (reps - 1)
+    rho, supp, err = pops[0].read()
+    for q in pops:
+        q.close()
+    pop.close()
+    shot.close()
+    sched.close()
+    M = mpr.to_fft_order(amp.astype(np.float64))
+    known = mpr.to_fft_order(sh0["mask"])
+    prm = dict(alg="HIO", beta=0.9, chi=0.5, G=10, j=16, j_er=4, j_end=0, sigma=2.0, sigma_end=1.0,
+               tau=0.10, tau_end=0.10)
+    t0 = time.perf_counter()
+    ref = mpr.run_plain(M, known, x0, S0, prm)
+    cpu_s = time.perf_counter() - t0
+    rng = np.random.default_rng(5)
+    eps = np.finfo(np.float32).eps * np.abs(x0).max()
+    pert = mpr.run_plain(M, known, x0 + eps * (rng.standard_normal(x0.shape) + 1j * rng.standard_normal(x0.shape)),
+                         S0, prm)
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    Eref = np.array(ref["E"])
+    return {"n": n, "P": P, "iterations": 200,
+            "gpu_ms_per_run": gpu_s * 1e3, "gpu_member_iterations_per_s": P * 200 / gpu_s,
+            "oracle_s_per_run": cpu_s, "oracle_cores": 1,
+            "best_gpu": int(np.argmin(err)), "best_oracle": int(np.argmin(Eref)),
+            "fitness_gpu": [float(e) for e in err], "fitness_oracle": [float(e) for e in Eref],
+            "density_rel_l2_gpu_vs_oracle": [rel(rho[p], ref["x"][p]) for p in range(P)],
+            "density_rel_l2_oracle_perturbed_vs_oracle": [rel(pert["x"][p], ref["x"][p]) for p in range(P)],
+            "support_mismatch_px_gpu_vs_oracle": [int((supp[p] != ref["S"][p]).sum()) for p in range(P)]}
+
+
+def mpr_1024_study(ctx, B, generations=20):
+    """1024^2, twelve clustered spheres (150-px extent), 1e8 photons, 24x24
+    beamstop and 4-px gap, P = 64 sphere starts (Sigma_init 180, seed 2002,
+    Philox 3002); the MPR schedule (RAAR beta 0.9, R = 3 x 20 + 40 ER, sigma
+    2 -> 0.5, tau 0.10 -> 2/3 tau, C_p 0.6, C_w 0.4, tiles 4..128) for all
+    generations: 2P x 100 x G member-iterations."""
+    import torch
+    from paper_2409_07413_amd import synth
+    n, P = 1024, 64
+    tune = ctx.autotune(n, 2 * P)
+    sh0 = synth.shot(n, "spheres", 1002, 1e8, beamstop=24, gap=4)
+    rho0 = synth.sphere_starts(sh0["amp"], sh0["mask"], P, 2002, sigma_init=180).astype(np.complex64)
+    supp0 = synth.centred_square(n, 180).astype(np.uint8)
+    shot = ctx.shot(sh0["amp"].astype(np.float32), sh0["mask"].astype(np.uint8))
+    pop = shot.population(rho0, supp0, memetic=True, seed=3002)
+    G = generations
+    prm = lambda g: dict(alg=2, G=G, R=R, j=J, j_er=J_ER, j_end=0, j_eval=J_EVAL, t_min=4, t_max=n // 8,  # noqa: E731
+                         gen_first=g, gen_count=1, init_error=1 if g == 1 else 0, beta=0.9, chi=0.5,
+                         sigma=2.0, sigma_end=0.5, tau=0.10, tau_end=0.10 * 2.0 / 3.0, c_p=0.6, c_w=0.4)
+    scheds = [B.sched_mpr(ctx, **prm(g)) for g in range(1, G + 1)]
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sc in scheds:
+        pop.run(sc, stream)
+    pop.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = pop.stats()
+    pop.close()
+    shot.close()
+    its = 2 * P * (R * (J + J_ER) + J_EVAL) * G
+    return {"n": n, "P": P, "members": 2 * P, "generations": G, "tuning": {"variant": tune["variant"],
+            "chunk_members": tune["chunk_members"]}, "seconds": dt, "member_iterations_per_s": its / dt,
+            "iteration_pixels_per_s": its * n * n / dt,
+            "pct_hbm_peak_iterations": its * n * n * 40.0 / dt / (HBM_PEAK_GBS * 1e9),
+            "best_fitness_last": stats[-1].err_best if stats else None}
+
+
 def copy_calibration():
     """A plain copy kernel of known size: 256 MiB read + 256 MiB written per
     launch (torch copy_, a hipMemcpy device-to-device kernel).  Its FETCH_SIZE /
@@ -550,11 +655,25 @@ def main():
                     help="time the iteration kernels at every served detector size and exit")
     ap.add_argument("--graph-study", action="store_true",
                     help="compare captured-graph replays with eager schedule runs and exit")
+    ap.add_argument("--plain-128", action="store_true",
+                    help="128^2 plain HIO+ER run, FP32 device vs FP64 oracle, and exit")
+    ap.add_argument("--mpr-1024", action="store_true", help="1024^2 MPR run (20 generations) and exit")
     ap.add_argument("--batch-study", action="store_true",
                     help="32 uneven shots: one at a time, one batch, one captured batch (after tuning) and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.plain_128 or args.mpr_1024:
+        import torch  # noqa: F401
+        from paper_2409_07413_amd import binding as B
+        ctx = B.Context(0)
+        ctx.set_cache_budget(CACHE_BUDGET)
+        if args.plain_128:
+            print(json.dumps({"plain_128": plain_128_study(ctx, B)}), flush=True)
+        else:
+            print(json.dumps({"mpr_1024": mpr_1024_study(ctx, B)}), flush=True)
+        ctx.close()
         return
     if args.batch_study:
         import torch  # noqa: F401
