@@ -75,10 +75,11 @@ def kernel_sources_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_id, chunk):
+def measured_traffic(kernel_key, chunk):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE measurement (copy-kernel calibrated), or None when
-    the kernels changed since it was taken."""
+    FETCH_SIZE / WRITE_SIZE measurement (copy-kernel calibrated, averaged over
+    the kernel's launches in the measured generation), or None when the
+    kernels changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic_512_pop64.json")
     if not os.path.exists(path):
         return None
@@ -88,7 +89,7 @@ def measured_traffic(kernel_id, chunk):
         return None
     if t.get("sources_digest") != kernel_sources_digest() or t.get("members_per_launch") != chunk:
         return None
-    return t.get("kernels", {}).get(str(kernel_id), {}).get("hbm_bytes_per_launch")
+    return t.get("kernels", {}).get(str(kernel_key), {}).get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(sh, rho0, supp0, seconds_target=15.0):
@@ -754,8 +755,9 @@ def main():
     torch.cuda.synchronize()
 
     # timed region: K generations; HIP events only around the dominant kernel's
-    # launches (k_col_proj, run in every iteration), on the launch stream
-    pop.timing(True, kernels=[B.KERNEL_COL_PROJ])
+    # launches (k_row_update, ER and HIO/RAAR forms, run in every iteration),
+    # on the launch stream
+    pop.timing(True, kernels=[B.KERNEL_ROW_UPDATE_ER, B.KERNEL_ROW_UPDATE_IA])
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -767,7 +769,9 @@ def main():
     wall = time.perf_counter() - t0
     pop.sync()
     gpu_ms = ev0.elapsed_time(ev1)
-    n_l, ms = pop.timing_read(B.KERNEL_COL_PROJ)
+    n_er, ms_er = pop.timing_read(B.KERNEL_ROW_UPDATE_ER)
+    n_ia, ms_ia = pop.timing_read(B.KERNEL_ROW_UPDATE_IA)
+    n_l, ms = n_er + n_ia, ms_er + ms_ia
 
     # one more generation with every iteration kernel timed (breakdown only)
     pop.timing(True)
@@ -782,9 +786,12 @@ def main():
     member_its = 2 * P * (R * (J + J_ER) + J_EVAL) * args.steps
     value = member_its / wall
     chunk = min(2 * P, max(1, CACHE_BUDGET // (2 * N * N * 8)))
-    bytes_per_launch = algorithmic_bytes_per_px(B.KERNEL_COL_PROJ, chunk) * N * N * chunk
+    bytes_total = (n_er * algorithmic_bytes_per_px(B.KERNEL_ROW_UPDATE_ER, chunk)
+                   + n_ia * algorithmic_bytes_per_px(B.KERNEL_ROW_UPDATE_IA, chunk)) * N * N * chunk
+    bytes_per_launch = bytes_total / n_l
     achieved = bytes_per_launch / (ms / n_l * 1e-3) / 1e9
-    traffic = measured_traffic(B.KERNEL_COL_PROJ, chunk)
+    t_er, t_ia = measured_traffic("row_update_er", chunk), measured_traffic("row_update_ia", chunk)
+    traffic = (n_er * t_er + n_ia * t_ia) / n_l if t_er is not None and t_ia is not None else None
     # whole-step algorithmic bytes: iterations only (ingest/shrink-wrap/fitness/crossover excluded)
     ia_its = er_its = 0
     for i in range(args.warmup, total):
@@ -795,7 +802,6 @@ def main():
                 er_its += o.count
     step_bytes = 2 * P * N * N * (ia_its * (40.125 + 4.0 / chunk) + er_its * (32.125 + 4.0 / chunk))
     pct_hbm = step_bytes / wall / (HBM_PEAK_GBS * 1e9)
-    dom = B.KERNEL_COL_PROJ
     out = {
         "metric": "member-iterations/s at 512^2 pop 64 (% HBM peak); p50/p99 shot latency",
         "value": value,
@@ -817,10 +823,11 @@ def main():
                                "R=3 x 20 + 40 ER = 100 iterations per member per generation",
                    "n": N, "P": P, "members": 2 * P, "generations_timed": args.steps,
                    "schedule_G": G},
-        "roofline": {"bound": "hbm", "kernel": B.KERNEL_NAMES[dom], "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_row_update", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "launches": n_l, "avg_launch_us": ms / n_l * 1e3,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "launch_mix": {"ER": n_er, "HIO/RAAR": n_ia}},
         "members_per_launch": chunk,
         "kernels": {B.KERNEL_NAMES[k]: {"launches": v[0], "avg_us": v[1] / v[0] * 1e3,
                                         "GBps": algorithmic_bytes_per_px(k, chunk) * N * N * chunk

@@ -19,8 +19,11 @@ namespace spr {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// The per-size kernels are built without automatic contraction, so that a
+// kernel's results do not depend on how the compiler treats its context; the
+// fused multiply-adds that matter are written out.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -__fmul_rn(a.y, b.y)), fmaf(a.x, b.y, __fmul_rn(a.y, b.x)));
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
@@ -100,7 +103,7 @@ template <int DIR> __device__ __forceinline__ void dft2(float2& a0, float2& a1) 
 template <int DIR> __device__ __forceinline__ void dft3(float2& a0, float2& a1, float2& a2) {
   const float h = 0.86602540378443864676f;  // sin(2 pi / 3)
   float2 s = cadd(a1, a2), d = csub(a1, a2);
-  float2 m = make_float2(a0.x - 0.5f * s.x, a0.y - 0.5f * s.y);
+  float2 m = make_float2(fmaf(-0.5f, s.x, a0.x), fmaf(-0.5f, s.y, a0.y));
   float2 r = mul_i<DIR>(cscale(d, h));
   a0 = cadd(a0, s);
   a1 = cadd(m, r);

@@ -65,20 +65,23 @@ __device__ __forceinline__ bool bit_at(const uint32_t* __restrict__ S, int idx) 
 }
 
 // Nearest point of {|arg z| <= chi pi} (positivity: Re z >= 0 exactly).
+// The real-space arithmetic below spells out every rounding (__fmul_rn,
+// fmaf), so that the run-time and the specialised forms of a kernel, which
+// the compiler would otherwise contract differently, give identical bits.
 __device__ __forceinline__ float2 proj_phase(float2 z, const Phase& ph) {
   if (ph.mode == PHASE_OFF) return z;
   if (ph.mode == PHASE_POS) return make_float2(fmaxf(z.x, 0.f), z.y);
   const float aim = fabsf(z.y);
-  if (aim * ph.c <= z.x * ph.s) return z;
-  const float p = fmaxf(z.x * ph.c + aim * ph.s, 0.f);
+  if (__fmul_rn(aim, ph.c) <= __fmul_rn(z.x, ph.s)) return z;
+  const float p = fmaxf(fmaf(z.x, ph.c, __fmul_rn(aim, ph.s)), 0.f);
   const float sg = z.y < 0.f ? -1.f : 1.f;
-  return make_float2(p * ph.c, sg * p * ph.s);
+  return make_float2(__fmul_rn(p, ph.c), __fmul_rn(sg * p, ph.s));
 }
 
 __device__ __forceinline__ bool inside_phase(float2 z, const Phase& ph) {
   if (ph.mode == PHASE_OFF) return true;
   if (ph.mode == PHASE_POS) return z.x >= 0.f;
-  return fabsf(z.y) * ph.c <= z.x * ph.s;
+  return __fmul_rn(fabsf(z.y), ph.c) <= __fmul_rn(z.x, ph.s);
 }
 
 // Column-tile placement.  Workgroups go to the 8 XCDs round-robin by linear
@@ -105,7 +108,7 @@ __device__ __forceinline__ TileId col_tile_id() {
 __device__ __forceinline__ float2 modulus_replace(float2 X, float stored, float scale) {
   if (signbit(stored)) return X;
   const float Mv = stored * scale;
-  const float m2 = X.x * X.x + X.y * X.y;
+  const float m2 = fmaf(X.x, X.x, __fmul_rn(X.y, X.y));
   if (m2 > 0.f) return cscale(X, Mv * rsqrtf(m2));
   return make_float2(Mv, 0.f);
 }
@@ -182,6 +185,10 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
 // Row update: row IFFTs -> ER/HIO/RAAR real-space step -> next row FFT (or the
 // final real-space density).
 // ---------------------------------------------------------------------------
+// SPEC 0 takes the algorithm at run time (per-member parameters); 1, 2, 3 are
+// ER, HIO and RAAR compiled alone, which frees the registers of the paths a
+// uniform launch never takes.
+template <int SPEC>
 __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
@@ -198,7 +205,7 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   int alg = a.alg, out_mode = a.out_mode;
   float beta = a.beta;
   Phase ph = a.ph, ph_next = a.ph_next;
-  if (a.ip) {
+  if (SPEC == 0 && a.ip) {
     // per-member parameters (rows of one member share them; a wavefront may
     // hold rows of several members when N is small, which is safe because the
     // row transforms only synchronise within their own wavefront)
@@ -209,6 +216,9 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
     ph = q.ph;
     ph_next = q.ph_next;
   }
+  if constexpr (SPEC == 1) alg = ALG_ER;
+  if constexpr (SPEC == 2) alg = ALG_HIO;
+  if constexpr (SPEC == 3) alg = ALG_RAAR;
 
   const bool ia = alg != ALG_ER;
   float2* Tw = a.t_by_slot ? d.T + off : a.T + toff;
@@ -232,17 +242,18 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
     const float inv = 1.0f / (float)N;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const float2 xv = cscale(x[m], inv);
+      const float2 xv = make_float2(__fmul_rn(x[m].x, inv), __fmul_rn(x[m].y, inv));
       const float2 yv = y[m];
       const bool s = bit_at(Sm, row * N + t + T * m);
       if (alg == ALG_HIO) {
         const bool feasible = s && inside_phase(yv, ph);
-        xn[m] = feasible ? yv : make_float2(xv.x - beta * yv.x, xv.y - beta * yv.y);
+        xn[m] = feasible ? yv : make_float2(fmaf(-beta, yv.x, xv.x), fmaf(-beta, yv.y, xv.y));
       } else {  // RAAR
-        const float2 z = make_float2(2.f * yv.x - xv.x, 2.f * yv.y - xv.y);
+        const float2 z = make_float2(fmaf(2.f, yv.x, -xv.x), fmaf(2.f, yv.y, -xv.y));
         const float2 pc = s ? proj_phase(z, ph) : make_float2(0.f, 0.f);
-        const float g = 1.f - 2.f * beta;
-        xn[m] = make_float2(beta * pc.x + beta * xv.x + g * yv.x, beta * pc.y + beta * xv.y + g * yv.y);
+        const float g = fmaf(-2.f, beta, 1.f);
+        xn[m] = make_float2(fmaf(beta, pc.x, fmaf(beta, xv.x, __fmul_rn(g, yv.x))),
+                            fmaf(beta, pc.y, fmaf(beta, xv.y, __fmul_rn(g, yv.y))));
       }
     }
   }
@@ -300,8 +311,8 @@ __global__ __launch_bounds__(C* T) void k_col_err(ColErrArgs a) {
     const float stored = mv[m];
     if (!signbit(stored)) {
       const float2 X = cscale(v[m], inv);
-      const double df = (double)sqrtf(X.x * X.x + X.y * X.y) - (double)(stored * d.amp_scale);
-      acc += df * df;
+      const double df = (double)sqrtf(fmaf(X.x, X.x, __fmul_rn(X.y, X.y))) - (double)(stored * d.amp_scale);
+      acc = fma(df, df, acc);
     }
   }
   acc = wave_sum(acc);
@@ -424,7 +435,7 @@ __global__ __launch_bounds__(RWI* T) void k_row_argmax(RowArgmaxArgs a) {
   b.re = b.im = 0.f;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    const float q = v[m].x * v[m].x + v[m].y * v[m].y;
+    const float q = fmaf(v[m].x, v[m].x, __fmul_rn(v[m].y, v[m].y));
     const int idx = row * N + t + T * m;
     if (better(q, idx, b.val, b.idx)) {
       b.val = q;
@@ -515,7 +526,7 @@ __global__ __launch_bounds__(C* T) void k_col_mix(ColMixArgs a) {
         const float2 w = a.tw[ridx];  // exp(-2 pi i ridx / N)
         xs[k] = cmul(make_float2(al[k].pr, al[k].pi), cmul(w, xq));
       }
-      out = make_float2(xs[0].x + a.c_w * (xs[1].x - xs[2].x), xs[0].y + a.c_w * (xs[1].y - xs[2].y));
+      out = make_float2(fmaf(a.c_w, xs[1].x - xs[2].x, xs[0].x), fmaf(a.c_w, xs[1].y - xs[2].y, xs[0].y));
     } else {
       out = Fp[i];
     }
@@ -553,7 +564,15 @@ hipError_t l_col_proj(const ColProjArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t l_row_update(const RowUpdateArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_row_update, dim3(row_blocks(a.nm)), dim3(RW * T), kRowLds, s, a);
+  const dim3 grid(row_blocks(a.nm)), block(RW * T);
+  // the HIO/RAAR-only kernels gain on power-of-two sizes and lose on the
+  // radix-3 ones, where the run-time form keeps fewer registers live
+  constexpr bool kSpecIA = (N & (N - 1)) == 0;
+  if (a.ip) hipLaunchKernelGGL(k_row_update<0>, grid, block, kRowLds, s, a);
+  else if (a.alg == ALG_ER) hipLaunchKernelGGL(k_row_update<1>, grid, block, kRowLds, s, a);
+  else if (!kSpecIA) hipLaunchKernelGGL(k_row_update<0>, grid, block, kRowLds, s, a);
+  else if (a.alg == ALG_HIO) hipLaunchKernelGGL(k_row_update<2>, grid, block, kRowLds, s, a);
+  else hipLaunchKernelGGL(k_row_update<3>, grid, block, kRowLds, s, a);
   return hipGetLastError();
 }
 hipError_t l_col_err(const ColErrArgs& a, hipStream_t s) {

@@ -558,7 +558,11 @@ class HipExec : public Exec {
               q.ph_next = phase_of(nx.chi);
             }
           }
-          const IterParam* dip = meta(ip.data(), cm);
+          // members sharing one set of parameters take the launch-wide form
+          // (and the algorithm's own kernel); the arithmetic is the same
+          bool uniform = true;
+          for (int k = 1; k < cm && uniform; ++k) uniform = std::memcmp(&ip[k], &ip[0], sizeof(IterParam)) == 0;
+          const IterParam* dip = uniform ? nullptr : meta(ip.data(), cm);
           ColProjArgs ca{dslots, cm, dev<SlotDesc>(o_table_), 1, nullptr, dev<float2>(o_wsB_), tw};
           RowUpdateArgs ra;
           std::memset(&ra, 0, sizeof(ra));
@@ -570,10 +574,11 @@ class HipExec : public Exec {
           ra.W = (int)((nn + 31) / 32);
           ra.t_by_slot = 1;
           ra.ip = dip;
-          ra.alg = ALG_ER;
-          ra.ph = phase_of(1.0);
-          ra.out_mode = OUT_REAL;
-          ra.ph_next = phase_of(1.0);
+          ra.alg = ip[0].alg;
+          ra.beta = ip[0].beta;
+          ra.ph = ip[0].ph;
+          ra.out_mode = ip[0].out_mode;
+          ra.ph_next = ip[0].ph_next;
           ra.tw = tw;
           ops_.push_back([=] {
             launch(K->col_proj(ca, s_), "col_proj");
