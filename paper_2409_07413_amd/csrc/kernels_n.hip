@@ -48,7 +48,11 @@ constexpr size_t NN = (size_t)N * N;
 constexpr bool kRowWave = SPR_ROW_WAVE != 0 && 64 % T == 0;
 static_assert(kRowWave || T % 64 == 0, "a row transform must fill whole wavefronts or fit in one");
 using RowL = Lds<1, SPR_ROW_PAD, kRowWave>;
-using ColL = Lds<C, 0, false>;
+#ifndef SPR_COL_PAD
+#define SPR_COL_PAD 0
+#endif
+// column tile: position p of column c at (p + p / PAD) * C + c
+using ColL = Lds<C, SPR_COL_PAD, false>;
 constexpr int NR = RowL::span(N);  // LDS elements per row
 static_assert(N % C == 0, "column tile must divide N");
 
@@ -541,7 +545,7 @@ __global__ __launch_bounds__(C* T) void k_col_mix(ColMixArgs a) {
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-constexpr size_t kColLds = (size_t)C * N * sizeof(float2);
+constexpr size_t kColLds = (size_t)C * ColL::span(N) * sizeof(float2);
 constexpr size_t kRowLds = (size_t)RW * NR * sizeof(float2);
 constexpr size_t kRowLdsI = (size_t)RWI * NR * sizeof(float2);
 
