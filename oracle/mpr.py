@@ -107,6 +107,60 @@ def modulus_fourier(X, M, known):
     return out
 
 
+def radial_bins(N):
+    """Ring index of every FFT-order pixel: the distance of its signed
+    frequency (u, v) from the zero frequency, rounded half up to an integer."""
+    f = np.fft.fftfreq(N) * N
+    q = np.sqrt(f[:, None] ** 2 + f[None, :] ** 2)
+    return np.floor(q + 0.5).astype(np.int64)
+
+
+def upper_bounds(M, known, eta=1.5, max_unknown=0.2):
+    """Amplitude upper bounds for unknown pixels (appendix on missing
+    intensities, Eq. avgint, Eq. stdint, Eq. upperbound).
+
+    Per ring q (integer distance from the centre): mu = mean of I = M^2 over
+    the ring's known pixels, sigma = sqrt(mean(I^2) - mu^2) over the same,
+    U(q) = mu + eta * sigma.  A ring gets a bound only when its unknown pixels
+    are at most `max_unknown` of the ring (and it has a known pixel).
+    Readings: Eq. pm_bounds compares |rho~| with U, an amplitude with an
+    intensity; the amplitude bound taken is sqrt(U).  No saturation mask is
+    given, so the saturation rules do not apply.  Returns the bound per pixel
+    (NaN where there is none; known pixels get NaN too).
+    """
+    M = np.asarray(M, dtype=np.float64)
+    N = M.shape[0]
+    bins = radial_bins(N)
+    out = np.full((N, N), np.nan)
+    for q in np.unique(bins):
+        ring = bins == q
+        kn = ring & known
+        unk = ring & ~known
+        if not kn.any() or unk.sum() > max_unknown * ring.sum():
+            continue
+        I = M[kn] ** 2
+        mu = I.mean()
+        var = max((I ** 2).mean() - mu ** 2, 0.0)
+        out[unk] = np.sqrt(mu + eta * np.sqrt(var))
+    return out
+
+
+def modulus_fourier_bounded(X, M, known, bound):
+    """Eq. pm_bounds: measured pixels as in Eq. pm_full; an unknown pixel with
+    a bound b and |X| > b is brought to modulus b with its phase; every other
+    pixel is kept.  This is the nearest point of the set {|z| <= b}."""
+    out = modulus_fourier(X, M, known)
+    A = np.abs(X)
+    clamp = ~known & np.isfinite(bound) & (A > np.where(np.isfinite(bound), bound, np.inf))
+    out = np.where(clamp, X * (np.where(clamp, bound, 0.0) / np.where(clamp, A, 1.0)), out)
+    return out
+
+
+def proj_modulus_bounded(x, M, known, bound):
+    """P_M with upper bounds on the unknown pixels, in real space."""
+    return ifft2(modulus_fourier_bounded(fft2(x), M, known, bound))
+
+
 def proj_modulus(x, M, known):
     """P_M of Eq. pm with the mask of Eq. pm_full: F^-1[modulus_fourier(F[x])]."""
     return ifft2(modulus_fourier(fft2(x), M, known))
@@ -152,29 +206,34 @@ def proj_constraint(x, S, chi):
 # ----------------------------------------------------------------------------
 
 
-def er(x, S, M, known, chi):
-    """Error Reduction, x' = P_M P_C x (optimisation-problem appendix)."""
-    return proj_modulus(proj_constraint(x, S, chi), M, known)
+def _pm(x, M, known, bound):
+    return proj_modulus(x, M, known) if bound is None else proj_modulus_bounded(x, M, known, bound)
 
 
-def hio(x, S, M, known, chi, beta):
+def er(x, S, M, known, chi, bound=None):
+    """Error Reduction, x' = P_M P_C x (optimisation-problem appendix).
+    With `bound`, P_M is the upper-bounded projector of Eq. pm_bounds."""
+    return _pm(proj_constraint(x, S, chi), M, known, bound)
+
+
+def hio(x, S, M, known, chi, beta, bound=None):
     """Hybrid Input-Output (cited, not written out, in the paper).
 
     Fienup's rule with y = P_M x: x' = y where y satisfies the real-space
     constraints (inside S and P_C y = y), otherwise x - beta*y.
     """
-    y = proj_modulus(x, M, known)
+    y = _pm(x, M, known, bound)
     feasible = S & (proj_phase(y, chi) == y)
     return np.where(feasible, y, x - beta * y)
 
 
-def raar(x, S, M, known, chi, beta):
+def raar(x, S, M, known, chi, beta, bound=None):
     """Relaxed Averaged Alternating Reflections (cited, not written out).
 
     Luke's form beta/2 (R_C R_M + I) x + (1 - beta) P_M x with R = 2P - I,
     i.e. x' = beta*P_C(2y - x) + beta*x + (1 - 2 beta)*y, y = P_M x.
     """
-    y = proj_modulus(x, M, known)
+    y = _pm(x, M, known, bound)
     return beta * proj_constraint(2.0 * y - x, S, chi) + beta * x + (1.0 - 2.0 * beta) * y
 
 
