@@ -495,12 +495,48 @@ def default_t_max(N, t_min=4):
     return max(t_min, N // 8)
 
 
-def crossover(xs, Ss, known, g, seed, c_p, c_w, t_min, t_max):
+def average(xs, Ss, E, known):
+    """The population average (Alg. mpr's final Average, Eq. avgrec), with the
+    members aligned first.
+
+    The densities of a population are defined up to translation, twin and a
+    global phase; the paper resolves these before any operation on several
+    densities (appendix on aligning the reconstructions).  Reading: every
+    member is aligned by Reshift to the member with the lowest error (ties to
+    the lower index), then rho_avg = mean of the aligned densities and S_avg
+    = union of the aligned supports (Eq. avgrec read as the union over
+    p = 1..P).  Also returns the two average moduli of the appendix on
+    unconstrained modes: Mdot = |F[rho_avg]| (Eq. avgint1) and Mddot = mean of
+    |F[rho_p]| (Eq. avgint2), and the alignment records.
+    """
+    b = int(np.argmin(E))
+    Xs = [fft2(x) for x in xs]
+    al = [reshift(X, S, Xs[b], known) for X, S in zip(Xs, Ss)]
+    Xavg = sum(a[0] for a in al) / len(xs)
+    S_avg = np.zeros_like(Ss[0], dtype=bool)
+    for a in al:
+        S_avg = S_avg | a[1]
+    Mddot = sum(np.abs(X) for X in Xs) / len(xs)
+    return {"rho": ifft2(Xavg), "S": S_avg, "Mdot": np.abs(Xavg), "Mddot": Mddot, "best": b,
+            "align": [a[2] for a in al]}
+
+
+def mix_average_modulus(Xa, Mdot, Mddot, c_a):
+    """Eq. crossavg: the parent a keeps its Fourier phases and takes the modulus
+    C_a (Mdot + Mddot)/2 + (1 - C_a)|Xa| (phase 0 where Xa = 0)."""
+    A = np.abs(Xa)
+    unit = np.where(A > 0, Xa / np.where(A > 0, A, 1.0), 1.0)
+    return (c_a * 0.5 * (Mdot + Mddot) + (1.0 - c_a) * A) * unit
+
+
+def crossover(xs, Ss, known, g, seed, c_p, c_w, t_min, t_max, c_a=0.0, avg=None):
     """Alg. crossover: one child per parent p from three aligned parents.
 
     Non-map Fourier pixels keep the child's own parent p ("Copy"); map pixels
     take X_a + C_w (X_b - X_c); the support is S_a OR (S_b AND S_c AND S_p);
-    the child density is the inverse transform of the mixed spectrum.
+    the child density is the inverse transform of the mixed spectrum.  With
+    C_a > 0 the aligned parent a first takes the modulus of Eq. crossavg from
+    the population average `avg` (see `average`).
     """
     P = len(xs)
     N = xs[0].shape[0]
@@ -511,6 +547,8 @@ def crossover(xs, Ss, known, g, seed, c_p, c_w, t_min, t_max):
         aligned = [reshift(Xs[q], Ss[q], Xs[p], known) for q in abc]
         cmap = crossover_map(N, seed, g, p, c_p, t_min, t_max)
         (Xa, Sa, ia), (Xb, Sb, ib), (Xc, Sc, ic) = aligned
+        if c_a > 0.0:
+            Xa = mix_average_modulus(Xa, avg["Mdot"], avg["Mddot"], c_a)
         Xn = np.where(cmap, Xa + c_w * (Xb - Xc), Xs[p])
         Sn = Sa | (Sb & Sc & Ss[p])
         kids_x.append(ifft2(Xn))
@@ -575,9 +613,11 @@ def improve_member(x, S, M, known, prm, g, stats):
 
 
 def run_mpr(M, known, x0, S0, prm, seed, gen_offset=0, generations=None):
-    """Alg. mpr without the final Average: crossover, improve both, select.
+    """Alg. mpr: crossover, improve both, select; the final Average is
+    returned under "average".
 
-    ``prm`` adds R, j_eval, c_p, c_w, t_min, t_max to the plain keys.  The
+    ``prm`` adds R, j_eval, c_p, c_w, t_min, t_max (and optionally c_a, the
+    weight of Eq. crossavg) to the plain keys.  The
     errors of the initial population are evaluated first (GetError), since the
     first generation's statistics need them.  Generations gen_offset+1 ..
     gen_offset+generations are run (all G by default).
@@ -590,8 +630,10 @@ def run_mpr(M, known, x0, S0, prm, seed, gen_offset=0, generations=None):
     n_gen = G - gen_offset if generations is None else generations
     history = []
     for g in range(gen_offset + 1, gen_offset + n_gen + 1):
+        c_a = prm.get("c_a", 0.0)
+        avg = average(xs, Ss, E, known) if c_a > 0.0 else None
         kx, kS, infos = crossover(xs, Ss, known, g, seed, prm["c_p"], prm["c_w"],
-                                  prm["t_min"], prm["t_max"])
+                                  prm["t_min"], prm["t_max"], c_a=c_a, avg=avg)
         stats = generation_stats(E, Ss, g, G)
         new_par = [improve_member(xs[p], Ss[p], M, known, prm, g, stats) for p in range(P)]
         new_kid = [improve_member(kx[p], kS[p], M, known, prm, g, stats) for p in range(P)]
@@ -602,4 +644,4 @@ def run_mpr(M, known, x0, S0, prm, seed, gen_offset=0, generations=None):
             xs.append(src[0]); Ss.append(src[1]); E.append(src[2])
         history.append({"g": g, "stats": stats, "replaced": repl, "crossover": infos,
                         "E_par": [e for _, _, e in new_par], "E_kid": [e for _, _, e in new_kid]})
-    return {"x": xs, "S": Ss, "E": E, "history": history}
+    return {"x": xs, "S": Ss, "E": E, "history": history, "average": average(xs, Ss, E, known)}
