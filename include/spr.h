@@ -124,6 +124,16 @@ spr_status spr_shot_create(spr_ctx* ctx, int32_t n, const float* amp, const uint
                            uint32_t flags, spr_shot** out);
 /* SPR_E_BUSY while populations created on the shot are alive. */
 spr_status spr_shot_destroy(spr_shot* shot);
+/* Upper bounds on the unknown amplitudes (appendix on missing intensities,   */
+/* Eq. avgint, Eq. stdint, Eq. upperbound, Eq. pm_bounds): per ring of pixels  */
+/* at the same rounded distance q from the zero frequency, mu and sigma of the */
+/* known intensities M^2 give U(q) = mu + eta sigma; the projector then brings */
+/* an unknown Fourier value whose modulus exceeds sqrt(U(q)) down to it (phase */
+/* kept).  Rings with more than max_unknown (e.g. 0.2) of their pixels unknown */
+/* get no bound.  eta <= 0 removes the bounds.  The bounds live in the sign-   */
+/* marked unknown pixels of the stored modulus (no extra memory).  Waits for   */
+/* the device; *rings (may be NULL) gets the number of bounded rings.          */
+spr_status spr_shot_set_bounds(spr_shot* shot, double eta, double max_unknown, int32_t* rings);
 
 /* ------------------------------------------------------------------------- */
 /* Population: P reconstructions (Alg. mpr / Alg. randomsearch, D1-D2 of the   */
@@ -160,6 +170,8 @@ spr_status spr_pop_write(spr_pop* pop, const float* rho, const uint8_t* supp, co
 #define SPR_OP_STATS 7        /* alpha_best, alpha_all, alpha_eval of Alg. improve, for gen/gens */
 #define SPR_OP_CROSSOVER 8    /* Alg. crossover into the children: c_p, c_w, t_min, t_max, gen */
 #define SPR_OP_SELECT 9       /* Alg. select, gen */
+#define SPR_OP_AVERAGE 10     /* Alg. mpr's Average of the parents (Eq. avgrec), members aligned */
+                              /* to the best one; also the average modulus used when c_a > 0    */
 
 #define SPR_ALG_HIO 1
 #define SPR_ALG_RAAR 2
@@ -188,6 +200,8 @@ typedef struct spr_op {
   double alpha;   /* SUPPORT_AREA with SPR_AREA_ABS: target area in pixels */
   double c_p;     /* CROSSOVER: tile election probability */
   double c_w;     /* CROSSOVER: differential weight */
+  double c_a;     /* CROSSOVER: weight of the average modulus on parent a (Eq. crossavg); */
+                  /* > 0 needs an earlier AVERAGE                                       */
 } spr_op;
 
 /* Parameters of Table tab:params and the linear schedules ("Changing values  */
@@ -212,6 +226,7 @@ typedef struct spr_mpr_params {
   double beta, chi;
   double sigma, sigma_end, tau, tau_end;
   double c_p, c_w;
+  double c_a;                /* Eq. crossavg weight (0: the plain crossover) */
 } spr_mpr_params;
 
 /* Schedule calls run on the host only; ctx (for error messages) may be NULL. */
@@ -219,8 +234,9 @@ spr_status spr_sched_create(spr_ctx* ctx, const spr_op* ops, int32_t nops, spr_s
 /* Alg. randomsearch with Alg. normalimprove: per block Sequence then           */
 /* UpdateSupport on every member, then GET_ERROR on every member.               */
 spr_status spr_sched_plain(spr_ctx* ctx, const spr_plain_params* prm, spr_sched** out);
-/* Alg. mpr (without the final Average): per generation CROSSOVER, STATS, the  */
-/* Alg. improve operations on every member, SELECT.                            */
+/* Alg. mpr: per generation (AVERAGE when c_a > 0), CROSSOVER, STATS, the      */
+/* Alg. improve operations on every member, SELECT; after generation G the     */
+/* final AVERAGE (read with spr_read_average).                                 */
 spr_status spr_sched_mpr(spr_ctx* ctx, const spr_mpr_params* prm, spr_sched** out);
 spr_status spr_sched_destroy(spr_sched* sched);
 /* Copy out the expanded op list (ops may be NULL to query the count). */
@@ -263,6 +279,9 @@ spr_status spr_read(spr_pop* pop, float* rho, uint8_t* supp, double* err, uint32
 /* One parent (or child with SPR_READ_CHILDREN) into caller buffers: rho N*N  */
 /* complex, supp N*N uint8; either may be NULL.  member in [0, P).            */
 spr_status spr_read_member(spr_pop* pop, int32_t member, float* rho, uint8_t* supp, uint32_t flags);
+/* The last AVERAGE: rho N*N complex, supp N*N uint8, err its Eq. error_calc  */
+/* fitness (each may be NULL).  SPR_E_INVALID_ARG before any AVERAGE.         */
+spr_status spr_read_average(spr_pop* pop, float* rho, uint8_t* supp, double* err, uint32_t flags);
 /* Generation records, oldest first; at most max_n; *n_out gets the count. */
 spr_status spr_read_stats(spr_pop* pop, spr_gen_stats* out, int32_t max_n, int32_t* n_out);
 
@@ -369,6 +388,8 @@ typedef struct spr_shot_desc {
   uint64_t seed;          /* keys the random-phase start */
   double arrival;         /* < 0: stamped at submit; else the arrival time on the server clock */
                           /* (the simulated executor admits no request before its arrival)  */
+  double bound_eta;       /* > 0: upper bounds on unknown amplitudes as spr_shot_set_bounds */
+  double bound_max_unknown;
 } spr_shot_desc;
 
 typedef struct spr_result {

@@ -30,7 +30,8 @@ READ_CHILDREN = 0x8
 INIT_RANDOM_PHASE = 0x10
 AMP_FP16 = 0x20
 
-OP_ER, OP_HIO, OP_RAAR, OP_SHRINKWRAP, OP_SUPPORT_AREA, OP_GET_ERROR, OP_STATS, OP_CROSSOVER, OP_SELECT = range(1, 10)
+OP_ER, OP_HIO, OP_RAAR, OP_SHRINKWRAP, OP_SUPPORT_AREA, OP_GET_ERROR, OP_STATS, OP_CROSSOVER, OP_SELECT, OP_AVERAGE = \
+    range(1, 11)
 ALG_HIO, ALG_RAAR = 1, 2
 AREA_BEST, AREA_EVAL, AREA_ABS = 0, 1, 2
 SCOPE_ALL, SCOPE_PARENTS, SCOPE_CHILDREN = 0, 1, 2
@@ -46,7 +47,7 @@ class Op(C.Structure):
     _fields_ = [("kind", C.c_int32), ("count", C.c_int32), ("scope", C.c_int32), ("which", C.c_int32),
                 ("gen", C.c_int32), ("gens", C.c_int32), ("t_min", C.c_int32), ("t_max", C.c_int32),
                 ("beta", C.c_double), ("chi", C.c_double), ("sigma", C.c_double), ("tau", C.c_double),
-                ("alpha", C.c_double), ("c_p", C.c_double), ("c_w", C.c_double)]
+                ("alpha", C.c_double), ("c_p", C.c_double), ("c_w", C.c_double), ("c_a", C.c_double)]
 
 
 class PlainParams(C.Structure):
@@ -61,7 +62,7 @@ class MprParams(C.Structure):
                 ("t_max", C.c_int32), ("gen_first", C.c_int32), ("gen_count", C.c_int32),
                 ("init_error", C.c_int32), ("beta", C.c_double), ("chi", C.c_double),
                 ("sigma", C.c_double), ("sigma_end", C.c_double), ("tau", C.c_double),
-                ("tau_end", C.c_double), ("c_p", C.c_double), ("c_w", C.c_double)]
+                ("tau_end", C.c_double), ("c_p", C.c_double), ("c_w", C.c_double), ("c_a", C.c_double)]
 
 
 class GenStats(C.Structure):
@@ -87,7 +88,8 @@ class ServerCfg(C.Structure):
 class ShotDesc(C.Structure):
     _fields_ = [("n", C.c_int32), ("amp", C.c_void_p), ("mask", C.c_void_p), ("supp0", C.c_void_p),
                 ("supp_per_member", C.c_int32), ("flags", C.c_uint32), ("rho0", C.c_void_p),
-                ("seed", C.c_uint64), ("arrival", C.c_double)]
+                ("seed", C.c_uint64), ("arrival", C.c_double), ("bound_eta", C.c_double),
+                ("bound_max_unknown", C.c_double)]
 
 
 class Result(C.Structure):
@@ -118,7 +120,7 @@ EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_suppo
            "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
            "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
            "spr_timing_enable", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch",
-           "spr_read_member", "spr_size_variants", "spr_ctx_autotune", "spr_ctx_set_variant",
+           "spr_read_member", "spr_read_average", "spr_shot_set_bounds", "spr_size_variants", "spr_ctx_autotune", "spr_ctx_set_variant",
            "spr_ctx_get_tuning", "spr_graph_create", "spr_graph_create_batch", "spr_graph_launch",
            "spr_graph_destroy", "spr_server_create", "spr_server_submit", "spr_server_poll", "spr_server_step", "spr_server_drain",
            "spr_server_stats_get", "spr_server_last_error", "spr_server_destroy"]
@@ -158,6 +160,8 @@ def _proto(lib):
         "spr_ctx_set_cache_budget": (i32, [vp, C.c_uint64]),
         "spr_run_batch": (i32, [vp, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), i32, vp]),
         "spr_read_member": (i32, [vp, i32, vp, vp, u32]),
+        "spr_read_average": (i32, [vp, vp, vp, vp, u32]),
+        "spr_shot_set_bounds": (i32, [vp, C.c_double, C.c_double, C.POINTER(i32)]),
         "spr_size_variants": (i32, [i32]),
         "spr_ctx_autotune": (i32, [vp, i32, i32, C.POINTER(TuneResult)]),
         "spr_ctx_set_variant": (i32, [vp, i32, i32, i32]),
@@ -417,6 +421,12 @@ class Shot:
         except Exception:
             pass
 
+    def set_bounds(self, eta=1.5, max_unknown=0.2):
+        """Upper bounds on the unknown amplitudes from the radial profile; returns the bounded rings."""
+        r = C.c_int32()
+        self.ctx._check(self.ctx.lib.spr_shot_set_bounds(self.h, float(eta), float(max_unknown), C.byref(r)))
+        return r.value
+
     def population(self, rho0, supp0, memetic=False, seed=0, gen_offset=0, P=None):
         """rho0 None: P members from the device-side random-phase start keyed by seed."""
         return Population(self, rho0, supp0, memetic, seed, gen_offset, P)
@@ -504,6 +514,16 @@ class Population:
         self.ctx._check(self.ctx.lib.spr_read(self.h, rho.ctypes.data, supp.ctypes.data,
                                               err.ctypes.data, flags))
         return rho, supp.astype(bool), err
+
+    def average(self):
+        """The last AVERAGE: rho (N,N) complex64, supp (N,N) bool, its fitness."""
+        n = self.n
+        rho = np.empty((n, n), dtype=np.complex64)
+        supp = np.empty((n, n), dtype=np.uint8)
+        err = np.empty(1, dtype=np.float64)
+        self.ctx._check(self.ctx.lib.spr_read_average(self.h, rho.ctypes.data, supp.ctypes.data,
+                                                      err.ctypes.data, 0))
+        return rho, supp.astype(bool), float(err[0])
 
     def graph(self, sched):
         """Capture sched on this population into a replayable graph."""
@@ -611,7 +631,8 @@ class Server:
             raw = self.lib.spr_server_last_error(self.h)
             raise SprError(st, raw.decode() if raw else "")
 
-    def submit(self, amp, mask, supp0, rho0=None, seed=0, fft_order=False, arrival=None, fp16=False):
+    def submit(self, amp, mask, supp0, rho0=None, seed=0, fft_order=False, arrival=None, fp16=False,
+               bound_eta=0.0, bound_max_unknown=0.2):
         """Queue one shot (host arrays); rho0 None = device random-phase start."""
         n = int(amp.shape[0])
         amp = np.ascontiguousarray(amp, dtype=np.float32)
@@ -625,7 +646,8 @@ class Server:
             rho0 = np.ascontiguousarray(rho0, dtype=np.complex64)
             rp = rho0.ctypes.data
         d = ShotDesc(n, amp.ctypes.data, mask.ctypes.data, supp0.ctypes.data, 1 if supp0.ndim == 3 else 0,
-                     flags, rp, int(seed) & 0xFFFFFFFFFFFFFFFF, -1.0 if arrival is None else float(arrival))
+                     flags, rp, int(seed) & 0xFFFFFFFFFFFFFFFF, -1.0 if arrival is None else float(arrival),
+                     float(bound_eta), float(bound_max_unknown))
         t = C.c_uint64()
         self._check(self.lib.spr_server_submit(self.h, C.byref(d), C.byref(t)))
         self._n[t.value] = n

@@ -133,8 +133,9 @@ struct ColFftArgs {
 
 // Reshift cross-correlations: pair (child p, parent q) for q in {a, b, c}.
 struct ColCorrArgs {
-  int npairs;            // 3 P
+  int npairs;            // 3 P (crossover) or P (average)
   const int* abc;        // [P][3] chosen parents (population indices)
+  const int* ref_idx;    // null: pair k aligns abc[k] to k / 3; else pair k aligns k to *ref_idx
   const float2* F;       // parent spectra, indexed by population index [P][N*N]
   const float* amp;      // mask = sign bit (FP32 or FP16 storage)
   const __half* amp16;
@@ -179,6 +180,8 @@ struct ColMixArgs {
   uint64_t cp_thr;       // Bernoulli threshold (may be 2^32)
   float inv_n;           // unitary inverse scaling folded into the column pass
   const float2* tw;
+  float c_a;             // weight of the population's average modulus on parent a (0: none)
+  const float* Mavg;     // (|F[rho_avg]| + mean |F[rho_p]|) / 2, FFT order (used when c_a > 0)
 };
 
 // Per-size kernel table.

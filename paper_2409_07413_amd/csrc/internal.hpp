@@ -94,6 +94,18 @@ struct spr_pop {
   AlignRec* align = nullptr;
   int* abc = nullptr;
   int* mapprm = nullptr;
+  // population average (allocated by the first AVERAGE): density, support
+  // words, fitness, the mean aligned spectrum, the average modulus for the
+  // crossover, the best parent's index and a one-slot descriptor table
+  float2* avgX = nullptr;
+  uint32_t* avgS = nullptr;
+  double* avgE = nullptr;
+  float2* avgF = nullptr;
+  float* Mavg = nullptr;
+  int* avg_ref = nullptr;
+  SlotDesc* avg_desc = nullptr;
+  int* avg_slot = nullptr;
+  bool avg_done = false;
   uint8_t* stage = nullptr;
   size_t stage_bytes = 0;
   hipStream_t last = nullptr;
@@ -254,6 +266,9 @@ double encode_shot(int n, const float* a, const uint8_t* mask, uint32_t flags, f
   return den;
 }
 
+// Smallest positive normal FP16 value (a zero bound in FP16 storage).
+constexpr float kHalfTiny = 6.103515625e-05f;
+
 // FP16 storage of the encoded modulus: M / s rounded to nearest even, with s
 // the power of two that puts the largest measured value in [2^13, 2^14], so
 // that no stored value overflows and small ones stay clear of the subnormal
@@ -268,13 +283,65 @@ float fp16_encode(const float* enc, size_t nn, std::vector<__half>& out, double&
   out.resize(nn);
   den = 0.0;
   for (size_t k = 0; k < nn; ++k) {
-    out[k] = __float2half(std::signbit(enc[k]) ? -0.0f : enc[k] / s);
+    // unknown pixels keep their (scaled) amplitude bound, or -0
+    out[k] = __float2half(std::signbit(enc[k]) ? -std::min(-enc[k] / s, 65504.0f) : enc[k] / s);
     if (!std::signbit(enc[k])) {
       const double v = (double)__half2float(out[k]) * (double)s;
       den += v * v;
     }
   }
   return s;
+}
+
+// Upper bounds of the unknown amplitudes from the radial profile of the known
+// intensities (Eq. avgint, Eq. stdint, Eq. upperbound): per ring q (distance
+// of the signed frequency from zero, rounded half up), mu and sigma of I = M^2
+// over the ring's known pixels and U = mu + eta sigma; a ring with more than
+// max_unknown of its pixels unknown gets none.  The amplitude bound sqrt(U)
+// goes into the unknown pixels of `enc` (stored values, FFT order) as -sqrt(U)
+// / scale, keeping the sign bit that marks them; -0 means no bound, and a zero
+// bound is kept as the smallest positive normal value.  eta <= 0 clears every
+// bound.  Returns the number of rings with a bound.
+int apply_upper_bounds(int n, float* enc, float scale, double eta, double max_unknown,
+                       float tiny = std::numeric_limits<float>::min()) {
+  const size_t nn = (size_t)n * n;
+  std::vector<int> bin(nn);
+  int nb = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const double u = i < (n + 1) / 2 ? i : i - n, v = j < (n + 1) / 2 ? j : j - n;
+      const int b = (int)std::floor(std::sqrt(u * u + v * v) + 0.5);
+      bin[(size_t)i * n + j] = b;
+      nb = std::max(nb, b + 1);
+    }
+  std::vector<double> s1(nb, 0.0), s2(nb, 0.0);
+  std::vector<int64_t> known(nb, 0), total(nb, 0);
+  for (size_t k = 0; k < nn; ++k) {
+    total[bin[k]]++;
+    if (!std::signbit(enc[k])) {
+      const double I = (double)enc[k] * scale * ((double)enc[k] * scale);
+      s1[bin[k]] += I;
+      s2[bin[k]] += I * I;
+      known[bin[k]]++;
+    }
+  }
+  std::vector<double> bound(nb, -1.0);
+  int rings = 0;
+  for (int b = 0; b < nb; ++b) {
+    if (!(eta > 0.0) || known[b] == 0) continue;
+    if ((double)(total[b] - known[b]) > max_unknown * (double)total[b]) continue;
+    const double mu = s1[b] / (double)known[b];
+    const double var = std::max(s2[b] / (double)known[b] - mu * mu, 0.0);
+    bound[b] = std::sqrt(mu + eta * std::sqrt(var));
+    ++rings;
+  }
+  for (size_t k = 0; k < nn; ++k) {
+    if (!std::signbit(enc[k])) continue;
+    const double b = bound[bin[k]];
+    if (b < 0.0) enc[k] = -0.0f;
+    else enc[k] = -std::max((float)(b / scale), tiny);
+  }
+  return rings;
 }
 
 uint8_t* stage(spr_pop* pop, size_t bytes) {
@@ -552,6 +619,95 @@ void need_memetic(spr_pop* pop, const char* what) {
   if (!pop->memetic) fail(SPR_E_INVALID_ARG, std::string(what) + " needs a population created with SPR_POP_MEMETIC");
 }
 
+// Parent spectra, correlation images and alignment records (first use).
+void correlation_buffers(spr_pop* pop) {
+  if (pop->F) return;
+  const int n = pop->n, P = pop->P;
+  const size_t nn = (size_t)n * n;
+  const int blocks = n / pop->K->RWI;
+  pop->F = dalloc<float2>((size_t)P * nn);
+  pop->Cc = dalloc<float2>((size_t)6 * P * nn);
+  pop->amax = dalloc<ArgmaxRec>((size_t)6 * P * blocks);
+  pop->align = dalloc<AlignRec>((size_t)3 * P);
+  pop->abc = dalloc<int>((size_t)3 * P);
+  pop->mapprm = dalloc<int>((size_t)5 * P);
+}
+
+void average_buffers(spr_pop* pop) {
+  if (pop->avgX) return;
+  const size_t nn = (size_t)pop->n * pop->n;
+  pop->avgX = dalloc<float2>(nn);
+  pop->avgS = dalloc<uint32_t>(pop->W);
+  pop->avgE = dalloc<double>(1);
+  pop->avgF = dalloc<float2>(nn);
+  pop->Mavg = dalloc<float>(nn);
+  pop->avg_ref = dalloc<int>(1);
+  pop->avg_slot = dalloc<int>(1);
+  pop->avg_desc = dalloc<SlotDesc>(1);
+  SlotDesc d{};
+  d.X = pop->avgX;
+  d.T = pop->T;
+  d.S = pop->avgS;
+  d.amp = pop->shot->amp;
+  d.amp16 = pop->shot->amp16;
+  d.E = pop->avgE;
+  d.den = pop->shot->den;
+  d.flags = pop->flags;
+  d.amp_scale = pop->shot->amp_scale;
+  const int zero = 0;
+  HIPCHK(hipMemcpy(pop->avg_desc, &d, sizeof(d), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(pop->avg_slot, &zero, sizeof(int), hipMemcpyHostToDevice));
+}
+
+// Population average of the parents (Alg. mpr's Average, Eq. avgrec): every
+// parent aligned to the best one (Reshift, Eq. crosscorr), the mean aligned
+// density and the union of the aligned supports, its fitness (Eq.
+// error_calc), and the average modulus (Eq. avgint1, Eq. avgint2) used by a
+// crossover with c_a > 0.
+void average(spr_pop* pop, hipStream_t s) {
+  const SizeKernels* K = pop->K;
+  const int n = pop->n, P = pop->P;
+  const float2* tw = twiddles(pop->ctx, n);
+  correlation_buffers(pop);
+  average_buffers(pop);
+  RowFftArgs r1{pop->table, pop->table, P, pop->X, pop->T, -1, 1.f, tw};
+  launch_ok(K->row_fft(r1, s), "row_fft");
+  ColFftArgs c1{pop->table, nullptr, P, pop->T, pop->F, -1, 1.f / (float)n, tw};
+  launch_ok(K->col_fft(c1, s), "col_fft");
+  AvgArgs aa{P, n, pop->W, pop->table, pop->E, pop->avg_ref, pop->F, pop->align, pop->avgF, pop->Mavg,
+             pop->S, pop->avgS, tw};
+  launch_ok(launch_avg_best(aa, s), "avg_best");
+  ColCorrArgs cc{P, nullptr, pop->avg_ref, pop->F, pop->shot->amp, pop->shot->amp16, pop->Cc, tw};
+  launch_ok(K->col_corr(cc, s), "col_corr");
+  RowArgmaxArgs am{2 * P, pop->Cc, pop->amax, tw};
+  launch_ok(K->row_argmax(am, s), "row_argmax");
+  AlignArgs al{P, n / K->RWI, n, pop->amax, pop->align};
+  launch_ok(launch_align(al, s), "align");
+  launch_ok(launch_avg_spectra(aa, s), "avg_spectra");
+  launch_ok(launch_avg_support(aa, s), "avg_support");
+  // rho_avg = unitary inverse transform of the mean aligned spectrum
+  ColFftArgs c2{nullptr, nullptr, 1, pop->avgF, pop->T, +1, 1.f, tw};
+  launch_ok(K->col_fft(c2, s), "col_fft");
+  RowFftArgs r2{nullptr, nullptr, 1, pop->T, pop->avgX, +1, 1.f / (float)n, tw};
+  launch_ok(K->row_fft(r2, s), "row_fft");
+  Group g;
+  g.ctx = pop->ctx;
+  g.K = K;
+  g.n = n;
+  g.W = pop->W;
+  g.slots = pop->avg_slot;
+  g.nm = 1;
+  g.desc = pop->avg_desc;
+  g.T = pop->T;
+  g.Y = pop->Y;
+  g.err_partial = pop->err_partial;
+  g.block_max = pop->block_max;
+  g.maxv = pop->maxv;
+  g.flags = pop->flags;
+  get_error(g, s);
+  pop->avg_done = true;
+}
+
 void crossover(spr_pop* pop, const spr_op& op, hipStream_t s) {
   need_memetic(pop, "CROSSOVER");
   if (pop->P < 4) fail(SPR_E_INVALID_ARG, "crossover needs P >= 4");
@@ -564,14 +720,9 @@ void crossover(spr_pop* pop, const spr_op& op, hipStream_t s) {
   if (t_max < t_min) fail(SPR_E_INVALID_ARG, "crossover t_max < t_min");
   if (!(op.c_p >= 0.0 && op.c_p <= 1.0)) fail(SPR_E_INVALID_ARG, "crossover probability outside [0, 1]");
   const int blocks = n / K->RWI;
-  if (!pop->F) {
-    pop->F = dalloc<float2>((size_t)P * nn);
-    pop->Cc = dalloc<float2>((size_t)6 * P * nn);
-    pop->amax = dalloc<ArgmaxRec>((size_t)6 * P * blocks);
-    pop->align = dalloc<AlignRec>((size_t)3 * P);
-    pop->abc = dalloc<int>((size_t)3 * P);
-    pop->mapprm = dalloc<int>((size_t)5 * P);
-  }
+  correlation_buffers(pop);
+  if (op.c_a > 0.0 && !pop->avg_done)
+    fail(SPR_E_INVALID_ARG, "a crossover with c_a > 0 needs an AVERAGE of the parents first");
   // parent spectra F[p] (unitary)
   RowFftArgs r1{pop->table, pop->table, P, pop->X, pop->T, -1, 1.f, tw};
   launch_ok(K->row_fft(r1, s), "row_fft");
@@ -579,7 +730,7 @@ void crossover(spr_pop* pop, const spr_op& op, hipStream_t s) {
   launch_ok(K->col_fft(c1, s), "col_fft");
   ChoiceArgs ch{P, op.gen, t_min, t_max, pop->seed, pop->abc, pop->mapprm};
   launch_ok(launch_choice(ch, s), "choice");
-  ColCorrArgs cc{3 * P, pop->abc, pop->F, pop->shot->amp, pop->shot->amp16, pop->Cc, tw};
+  ColCorrArgs cc{3 * P, pop->abc, nullptr, pop->F, pop->shot->amp, pop->shot->amp16, pop->Cc, tw};
   launch_ok(K->col_corr(cc, s), "col_corr");
   RowArgmaxArgs am{6 * P, pop->Cc, pop->amax, tw};
   launch_ok(K->row_argmax(am, s), "row_argmax");
@@ -588,7 +739,8 @@ void crossover(spr_pop* pop, const spr_op& op, hipStream_t s) {
   double thr = std::floor(op.c_p * 4294967296.0);
   thr = std::min(std::max(thr, 0.0), 4294967296.0);
   ColMixArgs mx{P, pop->abc, pop->mapprm, pop->align, pop->F, pop->table, pop->T, (float)op.c_w,
-                pop->seed, op.gen, (uint64_t)thr, 1.f / (float)n, tw};
+                pop->seed, op.gen, (uint64_t)thr, 1.f / (float)n, tw,
+                op.c_a > 0.0 ? (float)op.c_a : 0.f, op.c_a > 0.0 ? pop->Mavg : nullptr};
   launch_ok(K->col_mix(mx, s), "col_mix");
   RowFftArgs r2{pop->table + P, pop->table + P, P, pop->T, pop->X, +1, 1.f, tw};
   launch_ok(K->row_fft(r2, s), "row_fft");
@@ -626,6 +778,9 @@ void validate_op(const spr_op& o) {
     case SPR_OP_CROSSOVER:
       if (o.gen < 1) fail(SPR_E_INVALID_ARG, "CROSSOVER needs gen >= 1");
       if (!(o.c_w >= 0.0 && o.c_w <= 2.0)) fail(SPR_E_INVALID_ARG, "c_w outside [0, 2]");
+      if (!(o.c_a >= 0.0 && o.c_a <= 1.0)) fail(SPR_E_INVALID_ARG, "c_a outside [0, 1]");
+      break;
+    case SPR_OP_AVERAGE:
       break;
     case SPR_OP_SELECT:
       if (o.gen < 1) fail(SPR_E_INVALID_ARG, "SELECT needs gen >= 1");
@@ -683,6 +838,9 @@ void run_schedule(spr_pop* pop, const spr_sched* sch, hipStream_t s) {
       }
       case SPR_OP_CROSSOVER:
         crossover(pop, o, s);
+        break;
+      case SPR_OP_AVERAGE:
+        average(pop, s);
         break;
       case SPR_OP_SELECT: {
         need_memetic(pop, "SELECT");
@@ -759,6 +917,14 @@ void destroy_pop(spr_pop* p) {
   dfree(p->align);
   dfree(p->abc);
   dfree(p->mapprm);
+  dfree(p->avgX);
+  dfree(p->avgS);
+  dfree(p->avgE);
+  dfree(p->avgF);
+  dfree(p->Mavg);
+  dfree(p->avg_ref);
+  dfree(p->avg_desc);
+  dfree(p->avg_slot);
   dfree(p->stage);
 }
 
@@ -789,7 +955,8 @@ Workspace& workspace(spr_ctx* ctx, int n, size_t members, const SizeKernels* K) 
 bool same_op(const spr_op& a, const spr_op& b) {
   return a.kind == b.kind && a.count == b.count && a.scope == b.scope && a.which == b.which && a.gen == b.gen &&
          a.gens == b.gens && a.t_min == b.t_min && a.t_max == b.t_max && a.beta == b.beta && a.chi == b.chi &&
-         a.sigma == b.sigma && a.tau == b.tau && a.alpha == b.alpha && a.c_p == b.c_p && a.c_w == b.c_w;
+         a.sigma == b.sigma && a.tau == b.tau && a.alpha == b.alpha && a.c_p == b.c_p && a.c_w == b.c_w &&
+         a.c_a == b.c_a;
 }
 
 // Populations of one size advancing through one schedule together: every
@@ -832,18 +999,14 @@ void run_group_schedule(const Group& g, const spr_sched* sch, hipStream_t s) {
 // Crossover buffers allocated ahead of a capture (no allocation may happen
 // while a stream is being captured).
 void prepare_buffers(spr_pop* pop, const spr_sched* sch) {
-  for (const auto& o : sch->ops)
-    if (o.kind == SPR_OP_CROSSOVER && pop->memetic && pop->P >= 4 && !pop->F) {
-      const int n = pop->n, P = pop->P;
-      const size_t nn = (size_t)n * n;
-      const int blocks = n / pop->K->RWI;
-      pop->F = dalloc<float2>((size_t)P * nn);
-      pop->Cc = dalloc<float2>((size_t)6 * P * nn);
-      pop->amax = dalloc<ArgmaxRec>((size_t)6 * P * blocks);
-      pop->align = dalloc<AlignRec>((size_t)3 * P);
-      pop->abc = dalloc<int>((size_t)3 * P);
-      pop->mapprm = dalloc<int>((size_t)5 * P);
+  for (const auto& o : sch->ops) {
+    if ((o.kind == SPR_OP_CROSSOVER && pop->memetic && pop->P >= 4) || o.kind == SPR_OP_AVERAGE)
+      correlation_buffers(pop);
+    if (o.kind == SPR_OP_AVERAGE) {
+      average_buffers(pop);
+      pop->avg_done = true;  // the captured AVERAGE precedes any crossover that uses it
     }
+  }
 }
 
 // Populations of one size in a batch: their schedule and where their

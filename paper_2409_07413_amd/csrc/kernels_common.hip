@@ -577,6 +577,70 @@ __global__ void k_gather_best(GatherBestArgs a) {
   }
 }
 
+// Best parent: lowest E, ties to the lower index, a NaN never chosen over a number.
+__global__ void k_avg_best(AvgArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int b = 0;
+  double bv = a.E[a.table[0]];
+  for (int p = 1; p < a.P; ++p) {
+    const double e = a.E[a.table[p]];
+    if (e < bv || (bv != bv && e == e)) {
+      bv = e;
+      b = p;
+    }
+  }
+  *a.ref = b;
+}
+
+// Per Fourier pixel: the mean of the aligned parent spectra and the mean of
+// their moduli (Eq. avgint1, Eq. avgint2), folded into Mavg.
+__global__ void k_avg_spectra(AvgArgs a) {
+  const long nn = (long)a.n * a.n;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  const int e = (int)(i / a.n), col = (int)(i % a.n);
+  float sx = 0.f, sy = 0.f, ms = 0.f;
+  for (int q = 0; q < a.P; ++q) {
+    const AlignRec al = a.align[q];
+    float2 x = a.F[(size_t)q * nn + i];
+    ms += sqrtf(fmaf(x.x, x.x, __fmul_rn(x.y, x.y)));
+    if (al.twin) x = make_float2(x.x, -x.y);
+    const int ridx = (int)(((long long)e * al.dr + (long long)col * al.dc) % a.n);
+    const float2 w = a.tw[ridx];
+    const float2 wx = make_float2(fmaf(w.x, x.x, -__fmul_rn(w.y, x.y)), fmaf(w.x, x.y, __fmul_rn(w.y, x.x)));
+    sx += fmaf(al.pr, wx.x, -__fmul_rn(al.pi, wx.y));
+    sy += fmaf(al.pr, wx.y, __fmul_rn(al.pi, wx.x));
+  }
+  const float inv = 1.f / (float)a.P;
+  const float2 m = make_float2(sx * inv, sy * inv);
+  a.avgF[i] = m;
+  a.Mavg[i] = 0.5f * (sqrtf(fmaf(m.x, m.x, __fmul_rn(m.y, m.y))) + ms * inv);
+}
+
+// Union of the aligned supports: S'(y) = S(y - d), or S(d - y) for a twin.
+__global__ void k_avg_support(AvgArgs a) {
+  const long w = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= a.W) return;
+  const long nn = (long)a.n * a.n;
+  uint32_t bits = 0;
+  for (int b = 0; b < 32; ++b) {
+    const long idx = w * 32 + b;
+    if (idx >= nn) break;
+    const int yr = (int)(idx / a.n), yc = (int)(idx % a.n);
+    bool on = false;
+    for (int q = 0; q < a.P && !on; ++q) {
+      const AlignRec al = a.align[q];
+      int sr = al.twin ? al.dr - yr : yr - al.dr;
+      int sc = al.twin ? al.dc - yc : yc - al.dc;
+      sr = ((sr % a.n) + a.n) % a.n;
+      sc = ((sc % a.n) + a.n) % a.n;
+      on = bit_at(a.S + (size_t)a.table[q] * a.W, (long)sr * a.n + sc);
+    }
+    if (on) bits |= 1u << b;
+  }
+  a.avgS[w] = bits;
+}
+
 inline unsigned blocks_for(long n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
 
 }  // namespace
@@ -640,6 +704,19 @@ hipError_t launch_init_phase(const InitPhaseArgs& a, hipStream_t s) {
 hipError_t launch_gather_best(const GatherBestArgs& a, hipStream_t s) {
   const long work = std::max<long>((long)a.n * a.n, std::max(a.W, a.P));
   hipLaunchKernelGGL(k_gather_best, dim3(blocks_for(work, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_avg_best(const AvgArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_avg_best, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_avg_spectra(const AvgArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_avg_spectra, dim3(blocks_for((long)a.n * a.n, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_avg_support(const AvgArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_avg_support, dim3(blocks_for(a.W, 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

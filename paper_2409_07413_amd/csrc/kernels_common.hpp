@@ -140,6 +140,21 @@ struct GatherBestArgs {
   unsigned char* out;
 };
 
+// Population average (members aligned to the best parent).
+struct AvgArgs {
+  int P, n, W;
+  const int* table;        // slot table (parents first)
+  const double* E;         // fitness by slot
+  int* ref;                // out: index of the best parent (lowest E, ties to the lower index)
+  const float2* F;         // parent spectra [P][n*n], unitary, FFT order
+  const AlignRec* align;   // [P]: alignment of parent q to the best one
+  float2* avgF;            // out: mean aligned spectrum
+  float* Mavg;             // out: (|avgF| + mean |F|) / 2
+  const uint32_t* S;       // support words by slot
+  uint32_t* avgS;          // out: union of the aligned supports
+  const float2* tw;        // exp(-2 pi i e / n)
+};
+
 // Blocks per member of the column smoothing pass (size of the block-max array).
 int smooth_blocks_per_member(int n);
 
@@ -157,5 +172,8 @@ hipError_t launch_pack(const PackArgs& a, hipStream_t s);
 hipError_t launch_unpack(const PackArgs& a, hipStream_t s);
 hipError_t launch_init_phase(const InitPhaseArgs& a, hipStream_t s);
 hipError_t launch_gather_best(const GatherBestArgs& a, hipStream_t s);
+hipError_t launch_avg_best(const AvgArgs& a, hipStream_t s);
+hipError_t launch_avg_spectra(const AvgArgs& a, hipStream_t s);
+hipError_t launch_avg_support(const AvgArgs& a, hipStream_t s);
 
 }  // namespace spr

@@ -109,11 +109,17 @@ __device__ __forceinline__ TileId col_tile_id() {
 
 // Masked modulus replacement on one unitary Fourier value (Eq. pm_full):
 // measured pixels get modulus M with the current phase (phase 0 if X = 0).
+// An unknown pixel stores minus its amplitude bound (-0: none); a value
+// above the bound is brought down to it with its phase (Eq. pm_bounds).
 __device__ __forceinline__ float2 modulus_replace(float2 X, float stored, float scale) {
-  if (signbit(stored)) return X;
-  const float Mv = stored * scale;
   const float m2 = fmaf(X.x, X.x, __fmul_rn(X.y, X.y));
-  if (m2 > 0.f) return cscale(X, Mv * rsqrtf(m2));
+  if (signbit(stored)) {
+    const float b = __fmul_rn(-stored, scale);
+    if (b > 0.f && m2 > __fmul_rn(b, b)) return cscale(X, __fmul_rn(b, rsqrtf(m2)));
+    return X;
+  }
+  const float Mv = __fmul_rn(stored, scale);
+  if (m2 > 0.f) return cscale(X, __fmul_rn(Mv, rsqrtf(m2)));
   return make_float2(Mv, 0.f);
 }
 
@@ -388,8 +394,8 @@ __global__ __launch_bounds__(C* T) void k_col_corr(ColCorrArgs a) {
   const TileId id = col_tile_id();
   const int col = id.tile * C + c;
   const int pair = id.img;
-  const int p = pair / 3;
-  const int q = a.abc[pair];
+  const int p = a.ref_idx ? *a.ref_idx : pair / 3;
+  const int q = a.ref_idx ? pair : a.abc[pair];
   const float2* Xq = a.F + (size_t)q * NN;
   const float2* Xp = a.F + (size_t)p * NN;
   float2 v1[E], v2[E];
@@ -529,6 +535,12 @@ __global__ __launch_bounds__(C* T) void k_col_mix(ColMixArgs a) {
         const int ridx = (int)(((long long)e * al[k].dr + (long long)col * al[k].dc) % N);
         const float2 w = a.tw[ridx];  // exp(-2 pi i ridx / N)
         xs[k] = cmul(make_float2(al[k].pr, al[k].pi), cmul(w, xq));
+      }
+      if (a.c_a > 0.f) {
+        // Eq. crossavg: parent a keeps its phase, its modulus moves towards the average one
+        const float A = sqrtf(fmaf(xs[0].x, xs[0].x, __fmul_rn(xs[0].y, xs[0].y)));
+        const float target = fmaf(a.c_a, a.Mavg[i], __fmul_rn(1.f - a.c_a, A));
+        xs[0] = A > 0.f ? cscale(xs[0], target / A) : make_float2(target, 0.f);
       }
       out = make_float2(fmaf(a.c_w, xs[1].x - xs[2].x, xs[0].x), fmaf(a.c_w, xs[1].y - xs[2].y, xs[0].y));
     } else {

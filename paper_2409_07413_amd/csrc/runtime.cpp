@@ -379,11 +379,18 @@ spr_status spr_sched_mpr(spr_ctx* ctx, const spr_mpr_params* prm, spr_sched** ou
       e.scope = SPR_SCOPE_PARENTS;
       ops.push_back(e);
     }
+    if (!(prm->c_a >= 0.0 && prm->c_a <= 1.0)) fail(SPR_E_INVALID_ARG, "c_a outside [0, 1]");
     for (int g = g0; g <= g1; ++g) {
+      if (prm->c_a > 0.0) {
+        spr_op av = make_op(SPR_OP_AVERAGE);
+        av.scope = SPR_SCOPE_PARENTS;
+        ops.push_back(av);
+      }
       spr_op x = make_op(SPR_OP_CROSSOVER);
       x.gen = g;
       x.c_p = prm->c_p;
       x.c_w = prm->c_w;
+      x.c_a = prm->c_a;
       x.t_min = prm->t_min;
       x.t_max = prm->t_max;
       ops.push_back(x);
@@ -417,6 +424,11 @@ spr_status spr_sched_mpr(spr_ctx* ctx, const spr_mpr_params* prm, spr_sched** ou
       spr_op se = make_op(SPR_OP_SELECT);
       se.gen = g;
       ops.push_back(se);
+      if (g == prm->G) {
+        spr_op av = make_op(SPR_OP_AVERAGE);
+        av.scope = SPR_SCOPE_PARENTS;
+        ops.push_back(av);
+      }
     }
     for (auto& o : ops)
       if (o.kind == SPR_OP_ER || o.kind == SPR_OP_HIO || o.kind == SPR_OP_RAAR) o.chi = prm->chi;
@@ -568,6 +580,28 @@ spr_status spr_read_member(spr_pop* pop, int32_t member, float* rho, uint8_t* su
       HIPCHK(hipStreamSynchronize(ctx->stream));
       HIPCHK(hipMemcpy(supp, st, nn, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
     }
+  });
+}
+
+spr_status spr_read_average(spr_pop* pop, float* rho, uint8_t* supp, double* err, uint32_t flags) {
+  if (!pop || !live_has(pop)) return SPR_E_INVALID_ARG;
+  spr_ctx* ctx = pop->ctx;
+  return guarded(ctx, [&] {
+    if (!pop->avg_done) fail(SPR_E_INVALID_ARG, "no AVERAGE has run on this population");
+    use_device(ctx);
+    sync_pop(pop);
+    const bool dev = flags & SPR_DEVICE_PTRS;
+    const size_t nn = (size_t)pop->n * pop->n;
+    const auto kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (rho) HIPCHK(hipMemcpy(rho, pop->avgX, nn * sizeof(float2), kind));
+    if (supp) {
+      uint8_t* st = stage(pop, nn);
+      PackArgs pa{pop->avg_slot, 1, pop->n, pop->W, 0, st, pop->avgS};
+      launch_ok(launch_unpack(pa, ctx->stream), "unpack");
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      HIPCHK(hipMemcpy(supp, st, nn, kind));
+    }
+    if (err) HIPCHK(hipMemcpy(err, pop->avgE, sizeof(double), kind));
   });
 }
 
@@ -840,6 +874,34 @@ spr_status spr_ctx_autotune(spr_ctx* ctx, int32_t n, int32_t members, spr_tune_r
       throw;
     }
     cleanup();
+  });
+}
+
+spr_status spr_shot_set_bounds(spr_shot* shot, double eta, double max_unknown, int32_t* rings) {
+  if (!shot || !live_has(shot)) return SPR_E_INVALID_ARG;
+  spr_ctx* ctx = shot->ctx;
+  return guarded(ctx, [&] {
+    if (!(max_unknown >= 0.0 && max_unknown <= 1.0)) fail(SPR_E_INVALID_ARG, "max_unknown must lie in [0, 1]");
+    use_device(ctx);
+    HIPCHK(hipDeviceSynchronize());  // populations may be reading the modulus
+    const int n = shot->n;
+    const size_t nn = (size_t)n * n;
+    std::vector<float> enc(nn);
+    int r = 0;
+    if (shot->amp16) {
+      std::vector<__half> h(nn);
+      HIPCHK(hipMemcpy(h.data(), shot->amp16, nn * sizeof(__half), hipMemcpyDeviceToHost));
+      for (size_t k = 0; k < nn; ++k) enc[k] = __half2float(h[k]);
+      r = apply_upper_bounds(n, enc.data(), shot->amp_scale, eta, max_unknown, kHalfTiny);
+      for (size_t k = 0; k < nn; ++k)
+        h[k] = __float2half(std::signbit(enc[k]) ? -std::min(-enc[k], 65504.0f) : enc[k]);
+      HIPCHK(hipMemcpy(shot->amp16, h.data(), nn * sizeof(__half), hipMemcpyHostToDevice));
+    } else {
+      HIPCHK(hipMemcpy(enc.data(), shot->amp, nn * sizeof(float), hipMemcpyDeviceToHost));
+      r = apply_upper_bounds(n, enc.data(), 1.0f, eta, max_unknown);
+      HIPCHK(hipMemcpy(shot->amp, enc.data(), nn * sizeof(float), hipMemcpyHostToDevice));
+    }
+    if (rings) *rings = r;
   });
 }
 

@@ -833,6 +833,11 @@ spr_status spr_server_submit(spr_server* sv, const spr_shot_desc* sd, uint64_t* 
       d = std::make_shared<ShotData>();
       d->enc.resize(nn);
       d->den = encode_shot(n, sd->amp, sd->mask, sd->flags, d->enc.data());
+      if (sd->bound_eta > 0.0) {
+        if (!(sd->bound_max_unknown >= 0.0 && sd->bound_max_unknown <= 1.0))
+          fail(SPR_E_INVALID_ARG, "bound_max_unknown must lie in [0, 1]");
+        apply_upper_bounds(n, d->enc.data(), 1.0f, sd->bound_eta, sd->bound_max_unknown);
+      }
       if (sd->flags & SPR_AMP_FP16) {
         d->amp_scale = fp16_encode(d->enc.data(), nn, d->enc16, d->den);
         if (!(d->den > 0.0)) fail(SPR_E_INVALID_ARG, "sum of measured M^2 must be positive");

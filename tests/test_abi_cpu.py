@@ -142,3 +142,18 @@ def test_op_validation():
             binding.sched_ops([o])
     s = binding.sched_ops([binding.op(binding.OP_ER, count=2), binding.op(binding.OP_GET_ERROR)])
     assert [o.kind for o in s.ops()] == [binding.OP_ER, binding.OP_GET_ERROR]
+
+
+def test_mpr_schedule_average_ops():
+    binding, _ = _lib()
+    K = binding
+    ops = binding.sched_mpr(**dict(MPR, G=3)).ops()
+    assert [o.kind for o in ops].count(K.OP_AVERAGE) == 1 and ops[-1].kind == K.OP_AVERAGE
+    ops = binding.sched_mpr(**dict(MPR, G=3, c_a=0.3)).ops()
+    kinds = [o.kind for o in ops]
+    assert kinds.count(K.OP_AVERAGE) == 4 and kinds[-1] == K.OP_AVERAGE
+    for i, o in enumerate(ops):
+        if o.kind == K.OP_CROSSOVER:
+            assert ops[i - 1].kind == K.OP_AVERAGE and o.c_a == 0.3
+    with pytest.raises(binding.SprError):
+        binding.sched_mpr(**dict(MPR, c_a=1.5))
