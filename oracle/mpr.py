@@ -47,6 +47,49 @@ def to_fft_order(img):
     return np.fft.ifftshift(np.asarray(img))
 
 
+def sphere_start(M, known, P, seed, sigma_init, n_init=5, diam=(0.2, 0.9), phase=(0.0, 0.0), gamma=1.0):
+    """The paper's Initialize (initialisation appendix): every member fills a
+    centred sigma_init-wide square with n_init projected spheres (optical depth
+    2 sqrt(R^2 - r^2)) of diameters in [diam[0], diam[1]] * sigma_init, each
+    with a global phase in [phase[0], phase[1]]; the modulus of the sum is
+    raised to gamma (phase kept) and the density is scaled by sqrt(nu), nu the
+    ratio of Eq. norm (known intensities over the known part of |F[rho]|^2).
+
+    Readings: sphere centres are uniform over the positions that keep the
+    sphere inside the square (the centre of the square when it is narrower
+    than the sphere), measured from the array centre (n/2, n/2); the random
+    numbers are the shared generator's draws 4k..4k+3 of (seed, purpose 5,
+    generation 0, member) for sphere k, mapped to [0, 1) as u / 2^32.
+    """
+    M = np.asarray(M, dtype=np.float64)
+    n = M.shape[0]
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    y -= n / 2.0
+    x -= n / 2.0
+    half = sigma_init / 2.0
+    den = float(np.sum(M[known] ** 2))
+    out = np.empty((P, n, n), dtype=np.complex128)
+    for p in range(P):
+        u = philox.draws_array(seed, philox.PURPOSE_SPHERES, 0, p, 4 * n_init).astype(np.float64) / 4294967296.0
+        rho = np.zeros((n, n), dtype=np.complex128)
+        for k in range(n_init):
+            D = (diam[0] + (diam[1] - diam[0]) * u[4 * k]) * sigma_init
+            R = D / 2.0
+            cy = cx = 0.0
+            if half > R:
+                cy = -half + R + 2.0 * (half - R) * u[4 * k + 1]
+                cx = -half + R + 2.0 * (half - R) * u[4 * k + 2]
+            ph = phase[0] + (phase[1] - phase[0]) * u[4 * k + 3]
+            r2 = (y - cy) ** 2 + (x - cx) ** 2
+            rho = rho + 2.0 * np.sqrt(np.clip(R * R - r2, 0.0, None)) * np.exp(1j * ph)
+        A = np.abs(rho)
+        unit = np.where(A > 0, rho / np.where(A > 0, A, 1.0), 0.0)
+        rho = A ** gamma * unit
+        power = float(np.sum(np.abs(fft2(rho))[known] ** 2))
+        out[p] = rho * np.sqrt(den / power) if power > 0 else rho
+    return out
+
+
 def fp16_modulus(M, known):
     """The measured modulus as the FP16 storage represents it.
 

@@ -33,6 +33,7 @@ PURPOSE_CHOICE = 1    # RandomChoice: draws 0..2
 PURPOSE_MAPPARAM = 2  # CrossoverMap tile size, grid shift, rotation: draws 0..4
 PURPOSE_TILE = 3      # CrossoverMap tile election: block = tile key, word 0
 PURPOSE_INIT = 4      # random-phase start: draw = FFT-order pixel index, generation 0
+PURPOSE_SPHERES = 5   # sphere start: draws 4k..4k+3 = diameter, row and column centre, phase of sphere k
 
 
 def _round(c, k):

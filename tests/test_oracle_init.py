@@ -109,3 +109,50 @@ def test_fp16_modulus_rounds_ties_to_even():
     Mq, s = mpr.fp16_modulus(M, np.ones((2, 2), bool))
     assert s == 1.0
     assert Mq[0, 1] == 2048.0 and Mq[1, 0] == 2052.0 and Mq[1, 1] == 1.0
+
+
+def test_sphere_start_single_centred_sphere_closed_form():
+    n = 32
+    M = np.abs(np.random.default_rng(1).standard_normal((n, n))) + 0.5
+    known = np.ones((n, n), bool)
+    known[:2, :2] = False
+    # one sphere whose diameter equals the square: centred, radius 6
+    x0 = mpr.sphere_start(M, known, 1, seed=3, sigma_init=12, n_init=1, diam=(1.0, 1.0))[0]
+    y, x = np.mgrid[0:n, 0:n] - n / 2.0
+    prof = 2 * np.sqrt(np.clip(36.0 - y ** 2 - x ** 2, 0, None))
+    c = x0.real.max() / prof.max()
+    np.testing.assert_allclose(x0, c * prof, atol=1e-12 * prof.max() * c)
+    # Eq. norm: the known part of the Fourier power equals the known intensities
+    assert abs(np.sum(np.abs(mpr.fft2(x0))[known] ** 2) - np.sum(M[known] ** 2)) < 1e-9 * np.sum(M[known] ** 2)
+
+
+def test_sphere_start_square_phase_gamma():
+    n = 48
+    M = np.ones((n, n))
+    known = np.ones((n, n), bool)
+    xs = mpr.sphere_start(M, known, 3, seed=9, sigma_init=20, phase=(0.7, 0.7))
+    y, x = np.mgrid[0:n, 0:n] - n / 2.0
+    inside = (np.abs(y) <= 10) & (np.abs(x) <= 10)
+    for x0 in xs:
+        assert np.all(x0[~inside] == 0)                          # inside the sigma_init square
+        nz = np.abs(x0) > 0
+        np.testing.assert_allclose(np.angle(x0[nz]), 0.7)          # constant phase
+    g1 = mpr.sphere_start(M, known, 1, seed=9, sigma_init=20, gamma=1.0)[0]
+    g5 = mpr.sphere_start(M, known, 1, seed=9, sigma_init=20, gamma=0.5)[0]
+    nz = np.abs(g1) > 0
+    ratio = np.abs(g5[nz]) / np.sqrt(np.abs(g1[nz]))               # |rho|^0.5 up to one scale
+    np.testing.assert_allclose(ratio, ratio[0], rtol=1e-10)
+    assert not np.allclose(xs[0], xs[1])                           # members differ
+
+
+def test_sphere_start_draw_mapping():
+    n = 64
+    M = np.ones((n, n))
+    known = np.ones((n, n), bool)
+    # one sphere of random diameter in [0.2, 0.9] x 30: its support width follows draw 0
+    x0 = mpr.sphere_start(M, known, 1, seed=2024, sigma_init=30, n_init=1)[0]
+    from oracle import philox
+    u0 = philox.draw(2024, philox.PURPOSE_SPHERES, 0, 0, 0) / 2 ** 32
+    D = (0.2 + 0.7 * u0) * 30
+    rows = np.nonzero(np.abs(x0).sum(axis=1))[0]
+    assert abs((rows[-1] - rows[0] + 1) - D) <= 2.0
