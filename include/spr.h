@@ -153,6 +153,25 @@ spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const ui
                           int32_t supp_per_member, uint32_t flags, uint64_t seed,
                           int32_t gen_offset, spr_pop** out);
 spr_status spr_pop_destroy(spr_pop* pop);
+/* The paper's Initialize (initialisation appendix) on the device, for the     */
+/* parents: each fills a centred sigma_init-wide square with n_init projected  */
+/* spheres (optical depth 2 sqrt(R^2 - r^2)), diameters uniform in             */
+/* [diam_min, diam_max] * sigma_init, centres uniform over the positions that  */
+/* keep the sphere in the square, each sphere with a phase uniform in          */
+/* [phase_min, phase_max]; the modulus of the sum is raised to gamma (phase    */
+/* kept) and the density scaled by sqrt(nu) of Eq. norm.  The draws are those  */
+/* of the population's seed (purpose 5: words 4k..4k+3 for sphere k).  With    */
+/* set_support the parents' supports become the square |row - N/2| <= s/2,     */
+/* |col - N/2| <= s/2 (s = sigma_init).  Waits for the device.                 */
+typedef struct spr_sphere_params {
+  double sigma_init;          /* side of the centred square, pixels (> 0) */
+  int32_t n_init;             /* spheres per member (>= 1) */
+  int32_t set_support;
+  double diam_min, diam_max;  /* fractions of sigma_init, e.g. 0.2 and 0.9 */
+  double phase_min, phase_max;
+  double gamma;               /* > 0 */
+} spr_sphere_params;
+spr_status spr_pop_init_spheres(spr_pop* pop, const spr_sphere_params* prm);
 /* Overwrite the state of the parents (or children with SPR_READ_CHILDREN):    */
 /* any of rho (P*N*N complex), supp (P*N*N uint8), err (P doubles) may be NULL. */
 spr_status spr_pop_write(spr_pop* pop, const float* rho, const uint8_t* supp, const double* err,

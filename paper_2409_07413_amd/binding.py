@@ -79,6 +79,12 @@ class XoverInfo(C.Structure):
                 ("phase", (C.c_float * 2) * 3), ("peak", (C.c_float * 2) * 3)]
 
 
+class SphereParams(C.Structure):
+    _fields_ = [("sigma_init", C.c_double), ("n_init", C.c_int32), ("set_support", C.c_int32),
+                ("diam_min", C.c_double), ("diam_max", C.c_double), ("phase_min", C.c_double),
+                ("phase_max", C.c_double), ("gamma", C.c_double)]
+
+
 class ServerCfg(C.Structure):
     _fields_ = [("hbm_budget", C.c_uint64), ("max_shots", C.c_int32), ("P", C.c_int32),
                 ("sched", C.c_void_p), ("flags", C.c_uint32), ("max_inflight", C.c_int32),
@@ -120,7 +126,7 @@ EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_suppo
            "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
            "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
            "spr_timing_enable", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch",
-           "spr_read_member", "spr_read_average", "spr_shot_set_bounds", "spr_size_variants", "spr_ctx_autotune", "spr_ctx_set_variant",
+           "spr_read_member", "spr_read_average", "spr_pop_init_spheres", "spr_shot_set_bounds", "spr_size_variants", "spr_ctx_autotune", "spr_ctx_set_variant",
            "spr_ctx_get_tuning", "spr_graph_create", "spr_graph_create_batch", "spr_graph_launch",
            "spr_graph_destroy", "spr_server_create", "spr_server_submit", "spr_server_poll", "spr_server_step", "spr_server_drain",
            "spr_server_stats_get", "spr_server_last_error", "spr_server_destroy"]
@@ -161,6 +167,7 @@ def _proto(lib):
         "spr_run_batch": (i32, [vp, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), i32, vp]),
         "spr_read_member": (i32, [vp, i32, vp, vp, u32]),
         "spr_read_average": (i32, [vp, vp, vp, vp, u32]),
+        "spr_pop_init_spheres": (i32, [vp, C.POINTER(SphereParams)]),
         "spr_shot_set_bounds": (i32, [vp, C.c_double, C.c_double, C.POINTER(i32)]),
         "spr_size_variants": (i32, [i32]),
         "spr_ctx_autotune": (i32, [vp, i32, i32, C.POINTER(TuneResult)]),
@@ -514,6 +521,13 @@ class Population:
         self.ctx._check(self.ctx.lib.spr_read(self.h, rho.ctypes.data, supp.ctypes.data,
                                               err.ctypes.data, flags))
         return rho, supp.astype(bool), err
+
+    def init_spheres(self, sigma_init, n_init=5, diam=(0.2, 0.9), phase=(0.0, 0.0), gamma=1.0,
+                     set_support=True):
+        """The paper's sphere start for the parents, on the device (keyed by the population seed)."""
+        prm = SphereParams(float(sigma_init), int(n_init), 1 if set_support else 0, float(diam[0]), float(diam[1]),
+                           float(phase[0]), float(phase[1]), float(gamma))
+        self.ctx._check(self.ctx.lib.spr_pop_init_spheres(self.h, C.byref(prm)))
 
     def average(self):
         """The last AVERAGE: rho (N,N) complex64, supp (N,N) bool, its fitness."""

@@ -210,7 +210,13 @@ int size_variants(int n);
 // Weyl key increments 0x9E3779B9, 0xBB67AE85.  counter = (block, member,
 // generation, purpose); key = (seed low, seed high).
 // ---------------------------------------------------------------------------
-enum Purpose : uint32_t { PURPOSE_CHOICE = 1, PURPOSE_MAPPARAM = 2, PURPOSE_TILE = 3, PURPOSE_INIT = 4 };
+enum Purpose : uint32_t {
+  PURPOSE_CHOICE = 1,
+  PURPOSE_MAPPARAM = 2,
+  PURPOSE_TILE = 3,
+  PURPOSE_INIT = 4,
+  PURPOSE_SPHERES = 5
+};
 
 struct U4 {
   uint32_t v[4];

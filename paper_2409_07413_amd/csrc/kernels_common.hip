@@ -641,6 +641,85 @@ __global__ void k_avg_support(AvgArgs a) {
   a.avgS[w] = bits;
 }
 
+// One pixel of one member: the sum of the projected spheres (FP64), its
+// modulus raised to gamma with the phase kept.
+__global__ void k_init_spheres(SphereArgs a) {
+  const long nn = (long)a.n * a.n;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = blockIdx.y;
+  if (i >= nn || m >= a.nm) return;
+  const double y = (double)(i / a.n) - 0.5 * a.n, x = (double)(i % a.n) - 0.5 * a.n;
+  const double half = 0.5 * a.sigma_init, inv32 = 2.3283064365386962890625e-10;
+  double re = 0.0, im = 0.0;
+  for (int k = 0; k < a.n_init; ++k) {
+    const U4 u = philox4x32_10((uint32_t)k, (uint32_t)m, 0u, PURPOSE_SPHERES, (uint32_t)a.seed,
+                               (uint32_t)(a.seed >> 32));
+    const double R = 0.5 * (a.dmin + (a.dmax - a.dmin) * (u.v[0] * inv32)) * a.sigma_init;
+    double cy = 0.0, cx = 0.0;
+    if (half > R) {
+      cy = -half + R + 2.0 * (half - R) * (u.v[1] * inv32);
+      cx = -half + R + 2.0 * (half - R) * (u.v[2] * inv32);
+    }
+    const double ph = a.phmin + (a.phmax - a.phmin) * (u.v[3] * inv32);
+    const double r2 = (y - cy) * (y - cy) + (x - cx) * (x - cx);
+    const double d = R * R - r2;
+    if (d > 0.0) {
+      const double t = 2.0 * sqrt(d);
+      double sn, cs;
+      sincos(ph, &sn, &cs);
+      re += t * cs;
+      im += t * sn;
+    }
+  }
+  const double A = sqrt(re * re + im * im);
+  float2 v = make_float2(0.f, 0.f);
+  if (A > 0.0) {
+    const double g = pow(A, a.gamma) / A;
+    v = make_float2((float)(re * g), (float)(im * g));
+  }
+  a.X[(size_t)a.slots[m] * nn + i] = v;
+}
+
+// Known-pixel power of each member's spectrum: fixed-order block partial sums.
+__global__ void k_norm_partial(NormArgs a) {
+  __shared__ double red[256];
+  const long nn = (long)a.n * a.n;
+  const int m = blockIdx.y;
+  const long chunk = (nn + a.blocks - 1) / a.blocks;
+  const long beg = blockIdx.x * chunk, end = beg + chunk < nn ? beg + chunk : nn;
+  double s = 0.0;
+  for (long i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    if (signbit(amp_load(a.amp, a.amp16, i))) continue;
+    const float2 f = a.F[(size_t)m * nn + i];
+    s += (double)f.x * f.x + (double)f.y * f.y;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.partial[(size_t)m * a.blocks + blockIdx.x] = red[0];
+}
+
+__global__ void k_norm_factor(NormArgs a) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= a.nm) return;
+  double p = 0.0;
+  for (int b = 0; b < a.blocks; ++b) p += a.partial[(size_t)m * a.blocks + b];
+  a.fac[m] = p > 0.0 ? (float)sqrt(a.den / p) : 1.f;
+}
+
+__global__ void k_norm_scale(NormArgs a) {
+  const long nn = (long)a.n * a.n;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = blockIdx.y;
+  if (i >= nn) return;
+  float2* X = a.X + (size_t)a.slots[m] * nn;
+  const float f = a.fac[m];
+  X[i] = make_float2(X[i].x * f, X[i].y * f);
+}
+
 inline unsigned blocks_for(long n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
 
 }  // namespace
@@ -717,6 +796,18 @@ hipError_t launch_avg_spectra(const AvgArgs& a, hipStream_t s) {
 }
 hipError_t launch_avg_support(const AvgArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_avg_support, dim3(blocks_for(a.W, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_spheres(const SphereArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_spheres, dim3(blocks_for((long)a.n * a.n, 256), a.nm), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm(const NormArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_partial, dim3(a.blocks, a.nm), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_norm_factor, dim3(blocks_for(a.nm, 64)), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_norm_scale, dim3(blocks_for((long)a.n * a.n, 256), a.nm), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

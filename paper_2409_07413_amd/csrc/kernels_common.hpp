@@ -155,6 +155,30 @@ struct AvgArgs {
   const float2* tw;        // exp(-2 pi i e / n)
 };
 
+// Sphere start (the paper's Initialize): densities of nm members at slots.
+struct SphereArgs {
+  int nm, n, n_init;
+  uint64_t seed;
+  double sigma_init, dmin, dmax;  // diameters in [dmin, dmax] * sigma_init
+  double phmin, phmax, gamma;
+  const int* slots;
+  float2* X;                      // [slot][n*n]
+};
+
+// Eq. norm scaling: members' unitary spectra F [m][n*n] (contiguous), the
+// known-pixel power per member, and the factor sqrt(sum Xi M^2 / power).
+struct NormArgs {
+  int nm, n, blocks;              // blocks per member of the partial sums
+  const float2* F;
+  const float* amp;
+  const __half* amp16;
+  double den;
+  double* partial;                // [m][blocks]
+  float* fac;                     // [m]
+  const int* slots;
+  float2* X;
+};
+
 // Blocks per member of the column smoothing pass (size of the block-max array).
 int smooth_blocks_per_member(int n);
 
@@ -173,6 +197,8 @@ hipError_t launch_unpack(const PackArgs& a, hipStream_t s);
 hipError_t launch_init_phase(const InitPhaseArgs& a, hipStream_t s);
 hipError_t launch_gather_best(const GatherBestArgs& a, hipStream_t s);
 hipError_t launch_avg_best(const AvgArgs& a, hipStream_t s);
+hipError_t launch_init_spheres(const SphereArgs& a, hipStream_t s);
+hipError_t launch_norm(const NormArgs& a, hipStream_t s);
 hipError_t launch_avg_spectra(const AvgArgs& a, hipStream_t s);
 hipError_t launch_avg_support(const AvgArgs& a, hipStream_t s);
 

@@ -281,6 +281,53 @@ spr_status spr_pop_destroy(spr_pop* pop) {
   return SPR_OK;
 }
 
+spr_status spr_pop_init_spheres(spr_pop* pop, const spr_sphere_params* prm) {
+  if (!pop || !prm || !live_has(pop)) return SPR_E_INVALID_ARG;
+  spr_ctx* ctx = pop->ctx;
+  return guarded(ctx, [&] {
+    if (!(prm->sigma_init > 0.0) || prm->n_init < 1 || prm->n_init > 4096 || !(prm->gamma > 0.0) ||
+        !(prm->diam_min > 0.0) || prm->diam_max < prm->diam_min || prm->phase_max < prm->phase_min)
+      fail(SPR_E_INVALID_ARG, "bad sphere parameters");
+    use_device(ctx);
+    sync_pop(pop);
+    hipStream_t s = ctx->stream;
+    const int n = pop->n, P = pop->P;
+    const size_t nn = (size_t)n * n;
+    const SizeKernels* K = pop->K;
+    const float2* tw = twiddles(ctx, n);
+    SphereArgs sa{P, n, prm->n_init, pop->seed, prm->sigma_init, prm->diam_min, prm->diam_max,
+                  prm->phase_min, prm->phase_max, prm->gamma, pop->table, pop->X};
+    launch_ok(launch_init_spheres(sa, s), "init_spheres");
+    // unitary spectra of the parents into the row-transform buffers
+    RowFftArgs r1{pop->table, nullptr, P, pop->X, pop->T, -1, 1.f, tw};
+    launch_ok(K->row_fft(r1, s), "row_fft");
+    ColFftArgs c1{nullptr, nullptr, P, pop->T, pop->T, -1, 1.f / (float)n, tw};
+    launch_ok(K->col_fft(c1, s), "col_fft");
+    const int blocks = (int)std::min<size_t>(64, (nn + 4095) / 4096);
+    double* partial = dalloc<double>((size_t)P * blocks);
+    float* fac = dalloc<float>(P);
+    NormArgs na{P, n, blocks, pop->T, pop->shot->amp, pop->shot->amp16, pop->shot->den, partial, fac, pop->table,
+                pop->X};
+    hipError_t e = launch_norm(na, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dfree(partial);
+    dfree(fac);
+    launch_ok(e, "norm");
+    if (prm->set_support) {
+      std::vector<uint8_t> sq(nn, 0);
+      const double half = 0.5 * prm->sigma_init;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+          if (std::fabs(i - 0.5 * n) <= half && std::fabs(j - 0.5 * n) <= half) sq[(size_t)i * n + j] = 1;
+      uint8_t* st = stage(pop, nn);
+      HIPCHK(hipMemcpy(st, sq.data(), nn, hipMemcpyHostToDevice));
+      PackArgs pa{pop->table, P, n, pop->W, 1, st, pop->S};
+      launch_ok(launch_pack(pa, s), "pack");
+      HIPCHK(hipStreamSynchronize(s));
+    }
+  });
+}
+
 spr_status spr_pop_write(spr_pop* pop, const float* rho, const uint8_t* supp, const double* err,
                          uint32_t flags) {
   if (!pop) return SPR_E_INVALID_ARG;
