@@ -564,6 +564,34 @@ def average(xs, Ss, E, known):
             "align": [a[2] for a in al]}
 
 
+def complexity(x):
+    """Eq. complexity: Gamma = 1 - |sum rho| / sum |rho| (0 for a constant phase)."""
+    x = np.asarray(x, dtype=np.complex128)
+    a = float(np.sum(np.abs(x)))
+    return 1.0 - abs(complex(np.sum(x))) / a if a > 0 else 0.0
+
+
+def monitors(xs, E, avg=None, avg_err=None):
+    """Per-generation indicators of the monitoring section and the appendix on
+    unconstrained modes: best, lower-median, worst and mean error; mean
+    complexity Gamma over the members; mean density sum |sum rho| and its
+    standard deviation relative to the mean (population standard deviation);
+    for the average reconstruction, its Gamma and error.  Readings: the median
+    of an even count is the lower of the two middle values (an actual member's
+    error)."""
+    E = np.asarray(E, dtype=np.float64)
+    sums = np.array([abs(complex(np.sum(np.asarray(x, dtype=np.complex128)))) for x in xs])
+    Es = np.sort(E)
+    out = {"err_best": float(Es[0]), "err_median": float(Es[(len(Es) - 1) // 2]), "err_worst": float(Es[-1]),
+           "err_mean": float(E.mean()), "gamma_mean": float(np.mean([complexity(x) for x in xs])),
+           "sum_mean": float(sums.mean()),
+           "sum_rel_std": float(sums.std() / sums.mean()) if sums.mean() > 0 else 0.0}
+    if avg is not None:
+        out["gamma_avg"] = complexity(avg)
+        out["err_avg"] = float(avg_err) if avg_err is not None else float("nan")
+    return out
+
+
 def mix_average_modulus(Xa, Mdot, Mddot, c_a):
     """Eq. crossavg: the parent a keeps its Fourier phases and takes the modulus
     C_a (Mdot + Mddot)/2 + (1 - C_a)|Xa| (phase 0 where Xa = 0)."""

@@ -83,3 +83,27 @@ def test_crossover_with_ca_zero_is_the_plain_crossover_and_ca_one_sets_the_modul
     c = mpr.crossover(xs, Ss, known, 2, 7, 1.0, 0.0, 4, 4, c_a=1.0, avg=avg)
     for x in c[0]:
         np.testing.assert_allclose(np.abs(mpr.fft2(x)), 0.5 * (avg["Mdot"] + avg["Mddot"]), atol=1e-10)
+
+
+def test_complexity_closed_forms():
+    x = np.zeros((4, 4), complex)
+    x[1, 1], x[2, 2] = 3.0, 1.0
+    assert mpr.complexity(x) == 0.0                       # constant phase
+    x[2, 2] = 1j * 3.0
+    assert abs(mpr.complexity(x) - (1 - np.sqrt(18) / 6)) < 1e-15
+    x[2, 2] = -3.0
+    assert mpr.complexity(x) == 1.0                       # opposite phases cancel
+    assert mpr.complexity(np.exp(0.4j) * np.abs(x)) < 1e-15  # global phase does not count
+
+
+def test_monitor_statistics_by_hand():
+    xs = [np.full((2, 2), 1.0 + 0j), np.full((2, 2), 3.0 + 0j), np.array([[1, -1], [1j, -1j]], complex)]
+    m = mpr.monitors(xs, [0.3, 0.1, 0.2])
+    assert m["err_best"] == 0.1 and m["err_median"] == 0.2 and m["err_worst"] == 0.3
+    assert abs(m["err_mean"] - 0.2) < 1e-15
+    sums = np.array([4.0, 12.0, 0.0])
+    assert abs(m["sum_mean"] - sums.mean()) < 1e-12
+    assert abs(m["sum_rel_std"] - sums.std() / sums.mean()) < 1e-12
+    assert abs(m["gamma_mean"] - (0 + 0 + 1) / 3) < 1e-15
+    m4 = mpr.monitors(xs + [xs[0]], [0.4, 0.1, 0.2, 0.3])
+    assert m4["err_median"] == 0.2                          # lower of the two middle values
