@@ -191,6 +191,7 @@ spr_status spr_pop_write(spr_pop* pop, const float* rho, const uint8_t* supp, co
 #define SPR_OP_SELECT 9       /* Alg. select, gen */
 #define SPR_OP_AVERAGE 10     /* Alg. mpr's Average of the parents (Eq. avgrec), members aligned */
                               /* to the best one; also the average modulus used when c_a > 0    */
+#define SPR_OP_MONITOR 11     /* indicators of the parents for generation gen (spr_read_monitor) */
 
 #define SPR_ALG_HIO 1
 #define SPR_ALG_RAAR 2
@@ -246,6 +247,8 @@ typedef struct spr_mpr_params {
   double sigma, sigma_end, tau, tau_end;
   double c_p, c_w;
   double c_a;                /* Eq. crossavg weight (0: the plain crossover) */
+  int32_t monitor;           /* 1: AVERAGE and MONITOR after every generation */
+  int32_t pad;
 } spr_mpr_params;
 
 /* Schedule calls run on the host only; ctx (for error messages) may be NULL. */
@@ -301,6 +304,20 @@ spr_status spr_read_member(spr_pop* pop, int32_t member, float* rho, uint8_t* su
 /* The last AVERAGE: rho N*N complex, supp N*N uint8, err its Eq. error_calc  */
 /* fitness (each may be NULL).  SPR_E_INVALID_ARG before any AVERAGE.         */
 spr_status spr_read_average(spr_pop* pop, float* rho, uint8_t* supp, double* err, uint32_t flags);
+/* Indicators of the monitoring section and the appendix on unconstrained    */
+/* modes, per MONITOR op: errors of the parents (best, lower median, worst,   */
+/* mean), mean complexity Gamma = 1 - |sum rho| / sum |rho| (Eq. complexity),  */
+/* mean density sum |sum rho| and its population standard deviation relative  */
+/* to the mean, and Gamma and error of the last AVERAGE (has_avg).             */
+typedef struct spr_monitor {
+  int32_t gen, P;
+  double err_best, err_median, err_worst, err_mean;
+  double gamma_mean, sum_mean, sum_rel_std;
+  double gamma_avg, err_avg;
+  int32_t has_avg, pad;
+} spr_monitor;
+/* Monitor records, oldest first; at most max_n; *n_out gets the count. */
+spr_status spr_read_monitor(spr_pop* pop, spr_monitor* out, int32_t max_n, int32_t* n_out);
 /* Generation records, oldest first; at most max_n; *n_out gets the count. */
 spr_status spr_read_stats(spr_pop* pop, spr_gen_stats* out, int32_t max_n, int32_t* n_out);
 

@@ -30,8 +30,8 @@ READ_CHILDREN = 0x8
 INIT_RANDOM_PHASE = 0x10
 AMP_FP16 = 0x20
 
-OP_ER, OP_HIO, OP_RAAR, OP_SHRINKWRAP, OP_SUPPORT_AREA, OP_GET_ERROR, OP_STATS, OP_CROSSOVER, OP_SELECT, OP_AVERAGE = \
-    range(1, 11)
+OP_ER, OP_HIO, OP_RAAR, OP_SHRINKWRAP, OP_SUPPORT_AREA, OP_GET_ERROR, OP_STATS, OP_CROSSOVER, OP_SELECT, OP_AVERAGE, \
+    OP_MONITOR = range(1, 12)
 ALG_HIO, ALG_RAAR = 1, 2
 AREA_BEST, AREA_EVAL, AREA_ABS = 0, 1, 2
 SCOPE_ALL, SCOPE_PARENTS, SCOPE_CHILDREN = 0, 1, 2
@@ -62,7 +62,8 @@ class MprParams(C.Structure):
                 ("t_max", C.c_int32), ("gen_first", C.c_int32), ("gen_count", C.c_int32),
                 ("init_error", C.c_int32), ("beta", C.c_double), ("chi", C.c_double),
                 ("sigma", C.c_double), ("sigma_end", C.c_double), ("tau", C.c_double),
-                ("tau_end", C.c_double), ("c_p", C.c_double), ("c_w", C.c_double), ("c_a", C.c_double)]
+                ("tau_end", C.c_double), ("c_p", C.c_double), ("c_w", C.c_double), ("c_a", C.c_double),
+                ("monitor", C.c_int32), ("pad", C.c_int32)]
 
 
 class GenStats(C.Structure):
@@ -77,6 +78,13 @@ class XoverInfo(C.Structure):
                 ("ty", C.c_int32), ("sx", C.c_int32), ("sy", C.c_int32), ("rot", C.c_int32),
                 ("dr", C.c_int32 * 3), ("dc", C.c_int32 * 3), ("twin", C.c_int32 * 3),
                 ("phase", (C.c_float * 2) * 3), ("peak", (C.c_float * 2) * 3)]
+
+
+class Monitor(C.Structure):
+    _fields_ = [("gen", C.c_int32), ("P", C.c_int32), ("err_best", C.c_double), ("err_median", C.c_double),
+                ("err_worst", C.c_double), ("err_mean", C.c_double), ("gamma_mean", C.c_double),
+                ("sum_mean", C.c_double), ("sum_rel_std", C.c_double), ("gamma_avg", C.c_double),
+                ("err_avg", C.c_double), ("has_avg", C.c_int32), ("pad", C.c_int32)]
 
 
 class SphereParams(C.Structure):
@@ -126,7 +134,7 @@ EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_suppo
            "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
            "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
            "spr_timing_enable", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch",
-           "spr_read_member", "spr_read_average", "spr_pop_init_spheres", "spr_shot_set_bounds", "spr_size_variants", "spr_ctx_autotune", "spr_ctx_set_variant",
+           "spr_read_member", "spr_read_average", "spr_read_monitor", "spr_pop_init_spheres", "spr_shot_set_bounds", "spr_size_variants", "spr_ctx_autotune", "spr_ctx_set_variant",
            "spr_ctx_get_tuning", "spr_graph_create", "spr_graph_create_batch", "spr_graph_launch",
            "spr_graph_destroy", "spr_server_create", "spr_server_submit", "spr_server_poll", "spr_server_step", "spr_server_drain",
            "spr_server_stats_get", "spr_server_last_error", "spr_server_destroy"]
@@ -167,6 +175,7 @@ def _proto(lib):
         "spr_run_batch": (i32, [vp, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), i32, vp]),
         "spr_read_member": (i32, [vp, i32, vp, vp, u32]),
         "spr_read_average": (i32, [vp, vp, vp, vp, u32]),
+        "spr_read_monitor": (i32, [vp, C.POINTER(Monitor), i32, C.POINTER(i32)]),
         "spr_pop_init_spheres": (i32, [vp, C.POINTER(SphereParams)]),
         "spr_shot_set_bounds": (i32, [vp, C.c_double, C.c_double, C.POINTER(i32)]),
         "spr_size_variants": (i32, [i32]),
@@ -521,6 +530,13 @@ class Population:
         self.ctx._check(self.ctx.lib.spr_read(self.h, rho.ctypes.data, supp.ctypes.data,
                                               err.ctypes.data, flags))
         return rho, supp.astype(bool), err
+
+    def monitors(self, max_n=4096):
+        """Monitor records, oldest first, as dicts."""
+        arr = (Monitor * max_n)()
+        n = C.c_int32()
+        self.ctx._check(self.ctx.lib.spr_read_monitor(self.h, arr, max_n, C.byref(n)))
+        return [{k: getattr(arr[i], k) for k, _ in Monitor._fields_ if k != "pad"} for i in range(n.value)]
 
     def init_spheres(self, sigma_init, n_init=5, diam=(0.2, 0.9), phase=(0.0, 0.0), gamma=1.0,
                      set_support=True):

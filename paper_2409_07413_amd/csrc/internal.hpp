@@ -106,6 +106,10 @@ struct spr_pop {
   SlotDesc* avg_desc = nullptr;
   int* avg_slot = nullptr;
   bool avg_done = false;
+  // per-generation monitor records (allocated by the first MONITOR)
+  MonitorDev* mon = nullptr;
+  double* mon_sums = nullptr;
+  int mon_cap = 4096;
   uint8_t* stage = nullptr;
   size_t stage_bytes = 0;
   hipStream_t last = nullptr;
@@ -633,6 +637,13 @@ void correlation_buffers(spr_pop* pop) {
   pop->mapprm = dalloc<int>((size_t)5 * P);
 }
 
+void monitor_buffers(spr_pop* pop) {
+  if (pop->mon) return;
+  pop->mon = dalloc<MonitorDev>(pop->mon_cap);
+  pop->mon_sums = dalloc<double>((size_t)(pop->P + 1) * 3);
+  HIPCHK(hipMemset(pop->mon, 0, sizeof(MonitorDev) * pop->mon_cap));
+}
+
 void average_buffers(spr_pop* pop) {
   if (pop->avgX) return;
   const size_t nn = (size_t)pop->n * pop->n;
@@ -782,6 +793,9 @@ void validate_op(const spr_op& o) {
       break;
     case SPR_OP_AVERAGE:
       break;
+    case SPR_OP_MONITOR:
+      if (o.gen < 1) fail(SPR_E_INVALID_ARG, "MONITOR needs gen >= 1");
+      break;
     case SPR_OP_SELECT:
       if (o.gen < 1) fail(SPR_E_INVALID_ARG, "SELECT needs gen >= 1");
       break;
@@ -842,6 +856,14 @@ void run_schedule(spr_pop* pop, const spr_sched* sch, hipStream_t s) {
       case SPR_OP_AVERAGE:
         average(pop, s);
         break;
+      case SPR_OP_MONITOR: {
+        monitor_buffers(pop);
+        const int g = o.gen > 0 ? o.gen - 1 : 0;
+        MonitorArgs ma{pop->P, pop->n, pop->table, pop->X, pop->avg_done ? pop->avgX : nullptr, pop->E,
+                       pop->avg_done ? pop->avgE : nullptr, pop->mon_sums, pop->mon + (g % pop->mon_cap), o.gen};
+        launch_ok(launch_monitor(ma, s), "monitor");
+        break;
+      }
       case SPR_OP_SELECT: {
         need_memetic(pop, "SELECT");
         SelectArgs se{pop->P, o.gen, pop->table, pop->E, record(pop, o.gen)};
@@ -925,6 +947,8 @@ void destroy_pop(spr_pop* p) {
   dfree(p->avg_ref);
   dfree(p->avg_desc);
   dfree(p->avg_slot);
+  dfree(p->mon);
+  dfree(p->mon_sums);
   dfree(p->stage);
 }
 
@@ -1006,6 +1030,7 @@ void prepare_buffers(spr_pop* pop, const spr_sched* sch) {
       average_buffers(pop);
       pop->avg_done = true;  // the captured AVERAGE precedes any crossover that uses it
     }
+    if (o.kind == SPR_OP_MONITOR) monitor_buffers(pop);
   }
 }
 

@@ -720,6 +720,90 @@ __global__ void k_norm_scale(NormArgs a) {
   X[i] = make_float2(X[i].x * f, X[i].y * f);
 }
 
+// Sum of rho and of |rho| of one member (or of the average, member P), in
+// FP64 with a fixed-order tree.
+__global__ void k_member_sums(MonitorArgs a) {
+  __shared__ double red[3][256];
+  const int m = blockIdx.x;
+  const long nn = (long)a.n * a.n;
+  const float2* X = m < a.P ? a.X + (size_t)a.table[m] * nn : a.avgX;
+  double re = 0.0, im = 0.0, ab = 0.0;
+  for (long i = threadIdx.x; i < nn; i += blockDim.x) {
+    const float2 v = X[i];
+    re += v.x;
+    im += v.y;
+    ab += sqrt((double)v.x * v.x + (double)v.y * v.y);
+  }
+  red[0][threadIdx.x] = re;
+  red[1][threadIdx.x] = im;
+  red[2][threadIdx.x] = ab;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) a.sums[(size_t)m * 3 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Ranks of the parents' errors (ties to the lower index, a NaN ranked last)
+// give the best, lower-median and worst values; the sums give the mean
+// complexity and the mean and relative spread of |sum rho|.
+__global__ void k_monitor_final(MonitorArgs a) {
+  __shared__ double med[3];
+  const int P = a.P;
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    double ei = a.E[a.table[i]];
+    if (ei != ei) ei = __builtin_huge_val();
+    int rank = 0;
+    for (int j = 0; j < P; ++j) {
+      double ej = a.E[a.table[j]];
+      if (ej != ej) ej = __builtin_huge_val();
+      if (ej < ei || (ej == ei && j < i)) ++rank;
+    }
+    if (rank == 0) med[0] = ei;
+    if (rank == (P - 1) / 2) med[1] = ei;
+    if (rank == P - 1) med[2] = ei;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double esum = 0.0, gsum = 0.0, ssum = 0.0, s2 = 0.0;
+  for (int p = 0; p < P; ++p) {
+    esum += a.E[a.table[p]];
+    const double* q = a.sums + (size_t)p * 3;
+    const double sa = sqrt(q[0] * q[0] + q[1] * q[1]);
+    gsum += q[2] > 0.0 ? 1.0 - sa / q[2] : 0.0;
+    ssum += sa;
+  }
+  const double smean = ssum / P;
+  for (int p = 0; p < P; ++p) {  // second pass: no cancellation in the spread
+    const double* q = a.sums + (size_t)p * 3;
+    const double d = sqrt(q[0] * q[0] + q[1] * q[1]) - smean;
+    s2 += d * d;
+  }
+  MonitorDev r;
+  r.gen = a.gen;
+  r.P = P;
+  r.err_best = med[0];
+  r.err_median = med[1];
+  r.err_worst = med[2];
+  r.err_mean = esum / P;
+  r.gamma_mean = gsum / P;
+  r.sum_mean = smean;
+  r.sum_rel_std = smean > 0.0 ? sqrt(s2 / P) / smean : 0.0;
+  r.has_avg = a.avgX != nullptr;
+  r.gamma_avg = 0.0;
+  r.err_avg = 0.0;
+  if (a.avgX) {
+    const double* q = a.sums + (size_t)P * 3;
+    const double sa = sqrt(q[0] * q[0] + q[1] * q[1]);
+    r.gamma_avg = q[2] > 0.0 ? 1.0 - sa / q[2] : 0.0;
+    r.err_avg = a.avgE ? *a.avgE : 0.0;
+  }
+  r.pad = 0;
+  *a.rec = r;
+}
+
 inline unsigned blocks_for(long n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
 
 }  // namespace
@@ -808,6 +892,12 @@ hipError_t launch_norm(const NormArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_norm_partial, dim3(a.blocks, a.nm), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_norm_factor, dim3(blocks_for(a.nm, 64)), dim3(64), 0, s, a);
   hipLaunchKernelGGL(k_norm_scale, dim3(blocks_for((long)a.n * a.n, 256), a.nm), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_monitor(const MonitorArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_member_sums, dim3(a.P + (a.avgX ? 1 : 0)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_monitor_final, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -179,6 +179,27 @@ struct NormArgs {
   float2* X;
 };
 
+// Per-generation monitor record (mirrors spr_monitor).
+struct MonitorDev {
+  int gen, P;
+  double err_best, err_median, err_worst, err_mean;
+  double gamma_mean, sum_mean, sum_rel_std;
+  double gamma_avg, err_avg;
+  int has_avg, pad;
+};
+
+struct MonitorArgs {
+  int P, n;
+  const int* table;     // parents: slots table[0..P)
+  const float2* X;      // densities by slot
+  const float2* avgX;   // the average density, or null
+  const double* E;      // fitness by slot
+  const double* avgE;   // fitness of the average, or null
+  double* sums;         // [P + 1][3]: Re sum, Im sum, sum of moduli (FP64)
+  MonitorDev* rec;
+  int gen;
+};
+
 // Blocks per member of the column smoothing pass (size of the block-max array).
 int smooth_blocks_per_member(int n);
 
@@ -199,6 +220,7 @@ hipError_t launch_gather_best(const GatherBestArgs& a, hipStream_t s);
 hipError_t launch_avg_best(const AvgArgs& a, hipStream_t s);
 hipError_t launch_init_spheres(const SphereArgs& a, hipStream_t s);
 hipError_t launch_norm(const NormArgs& a, hipStream_t s);
+hipError_t launch_monitor(const MonitorArgs& a, hipStream_t s);
 hipError_t launch_avg_spectra(const AvgArgs& a, hipStream_t s);
 hipError_t launch_avg_support(const AvgArgs& a, hipStream_t s);
 

@@ -471,10 +471,15 @@ spr_status spr_sched_mpr(spr_ctx* ctx, const spr_mpr_params* prm, spr_sched** ou
       spr_op se = make_op(SPR_OP_SELECT);
       se.gen = g;
       ops.push_back(se);
-      if (g == prm->G) {
+      if (g == prm->G || prm->monitor) {
         spr_op av = make_op(SPR_OP_AVERAGE);
         av.scope = SPR_SCOPE_PARENTS;
         ops.push_back(av);
+      }
+      if (prm->monitor) {
+        spr_op mo = make_op(SPR_OP_MONITOR);
+        mo.gen = g;
+        ops.push_back(mo);
       }
     }
     for (auto& o : ops)
@@ -649,6 +654,43 @@ spr_status spr_read_average(spr_pop* pop, float* rho, uint8_t* supp, double* err
       HIPCHK(hipMemcpy(supp, st, nn, kind));
     }
     if (err) HIPCHK(hipMemcpy(err, pop->avgE, sizeof(double), kind));
+  });
+}
+
+spr_status spr_read_monitor(spr_pop* pop, spr_monitor* out, int32_t max_n, int32_t* n_out) {
+  if (!pop || !n_out || (max_n > 0 && !out) || !live_has(pop)) return SPR_E_INVALID_ARG;
+  spr_ctx* ctx = pop->ctx;
+  return guarded(ctx, [&] {
+    use_device(ctx);
+    sync_pop(pop);
+    *n_out = 0;
+    if (!pop->mon) return;
+    std::vector<MonitorDev> h(pop->mon_cap);
+    HIPCHK(hipMemcpy(h.data(), pop->mon, sizeof(MonitorDev) * pop->mon_cap, hipMemcpyDeviceToHost));
+    std::vector<MonitorDev> used;
+    for (auto& r : h)
+      if (r.gen > 0) used.push_back(r);
+    std::sort(used.begin(), used.end(), [](const MonitorDev& a, const MonitorDev& b) { return a.gen < b.gen; });
+    int32_t k = 0;
+    for (auto& r : used) {
+      if (k >= max_n) break;
+      spr_monitor o;
+      o.gen = r.gen;
+      o.P = r.P;
+      o.err_best = r.err_best;
+      o.err_median = r.err_median;
+      o.err_worst = r.err_worst;
+      o.err_mean = r.err_mean;
+      o.gamma_mean = r.gamma_mean;
+      o.sum_mean = r.sum_mean;
+      o.sum_rel_std = r.sum_rel_std;
+      o.gamma_avg = r.gamma_avg;
+      o.err_avg = r.err_avg;
+      o.has_avg = r.has_avg;
+      o.pad = 0;
+      out[k++] = o;
+    }
+    *n_out = k;
   });
 }
 

@@ -157,3 +157,18 @@ def test_mpr_schedule_average_ops():
             assert ops[i - 1].kind == K.OP_AVERAGE and o.c_a == 0.3
     with pytest.raises(binding.SprError):
         binding.sched_mpr(**dict(MPR, c_a=1.5))
+
+
+def test_mpr_schedule_monitor_ops():
+    binding, _ = _lib()
+    K = binding
+    ops = binding.sched_mpr(**dict(MPR, G=3, monitor=1)).ops()
+    kinds = [o.kind for o in ops]
+    mons = [o for o in ops if o.kind == K.OP_MONITOR]
+    assert [o.gen for o in mons] == [1, 2, 3]
+    for i, o in enumerate(ops):
+        if o.kind == K.OP_MONITOR:
+            assert ops[i - 1].kind == K.OP_AVERAGE and ops[i - 2].kind == K.OP_SELECT
+    assert kinds.count(K.OP_AVERAGE) == 3
+    with pytest.raises(binding.SprError):
+        binding.sched_ops([binding.op(K.OP_MONITOR, gen=0)])

@@ -1,0 +1,79 @@
+"""Per-generation monitors (complexity, density-sum spread, error order
+statistics, the average's Gamma and error) against the oracle's indicators of
+the population state the device holds."""
+
+import numpy as np
+import pytest
+
+from oracle import mpr
+
+from gpu_cases import Case
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("err_best", "err_median", "err_worst", "err_mean", "gamma_mean", "sum_mean", "sum_rel_std")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2409_07413_amd import binding
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2409_07413_amd import binding
+    return binding
+
+
+def check(rec, ref, with_avg):
+    for k in KEYS:
+        assert rec[k] == pytest.approx(ref[k], rel=1e-9, abs=1e-300), k
+    assert rec["has_avg"] == int(with_avg)
+    if with_avg:
+        assert rec["gamma_avg"] == pytest.approx(ref["gamma_avg"], rel=1e-9)
+        assert rec["err_avg"] == ref["err_avg"]
+
+
+@pytest.mark.parametrize("n,P,with_avg", [(64, 5, True), (64, 6, False), (128, 8, True)])
+def test_monitor_matches_oracle(ctx, B, n, P, with_avg):
+    c = Case(n, P, seed=n + P)
+    sh, pop = c.population(ctx)
+    ops = [B.op(B.OP_RAAR, count=3, beta=0.9, chi=0.5), B.op(B.OP_GET_ERROR, scope=B.SCOPE_PARENTS)]
+    if with_avg:
+        ops.append(B.op(B.OP_AVERAGE, scope=B.SCOPE_PARENTS))
+    ops.append(B.op(B.OP_MONITOR, gen=1))
+    pop.run(B.sched_ops(ops, ctx))
+    rho, _, err = pop.read()
+    recs = pop.monitors()
+    assert len(recs) == 1 and recs[0]["gen"] == 1 and recs[0]["P"] == P
+    if with_avg:
+        avg, _, e_avg = pop.average()
+        ref = mpr.monitors(list(rho.astype(np.complex128)), err, avg.astype(np.complex128), e_avg)
+    else:
+        ref = mpr.monitors(list(rho.astype(np.complex128)), err)
+    check(recs[0], ref, with_avg)
+    pop.close()
+    sh.close()
+
+
+def test_mpr_monitor_history(ctx, B):
+    n, P, G = 32, 4, 3
+    c = Case(n, P, seed=77)
+    sh, pop = c.population(ctx, memetic=True, seed=5)
+    base = dict(alg=B.ALG_RAAR, G=G, R=2, j=4, j_er=2, j_end=0, j_eval=4, t_min=4, t_max=4, init_error=1,
+                beta=0.9, chi=0.5, sigma=2.0, sigma_end=0.5, tau=0.1, tau_end=0.1 * 2 / 3, c_p=0.6, c_w=0.4,
+                monitor=1)
+    for g in range(1, G + 1):
+        pop.run(B.sched_mpr(ctx, gen_first=g, gen_count=1, **dict(base, init_error=int(g == 1))))
+        rho, _, err = pop.read()
+        avg, _, e_avg = pop.average()
+        recs = pop.monitors()
+        assert [r["gen"] for r in recs] == list(range(1, g + 1))
+        check(recs[-1], mpr.monitors(list(rho.astype(np.complex128)), err, avg.astype(np.complex128), e_avg),
+              True)
+        assert recs[-1]["err_best"] == err.min()
+    pop.close()
+    sh.close()
