@@ -13,6 +13,8 @@
 // The iterate is kept as its row transform T = rowFFT(x): a column pass turns
 // T into rowFFT(P_M x) and the next row pass turns that back into the next
 // iterate's row transform, so each iteration is one read-write sweep per pass.
+#include <type_traits>
+
 #include "common.hpp"
 #include "fft.hpp"
 
@@ -63,6 +65,30 @@ constexpr int rows_within_image() {
   return r;
 }
 constexpr int RWI = rows_within_image();
+// When RW divides N the row grid covers the rows exactly, so no row of a
+// launch is out of range and the per-element guards compile away.
+constexpr bool kRowsExact = N % RW == 0;
+// A launch processes whole members of N rows.  When every wavefront's rows lie
+// in one member, the member index is wave-uniform, and the member's slot and
+// descriptor are read with scalar loads, apart from the vector loads of the
+// row data (whose completion is counted in order).
+constexpr bool kWaveOneMember = kRowsExact && (T >= 64 || N % (64 / T) == 0);
+__device__ __forceinline__ int row_member(int grow) {
+  const int m = grow / N;
+  if constexpr (kWaveOneMember) return __builtin_amdgcn_readfirstlane(m);
+  return m;
+}
+
+// Pointers read from a descriptor in device memory are not known to the
+// compiler to be global; these views make the loads global (vector memory
+// only) instead of flat.
+template <class V> using GPtr = const __attribute__((address_space(1))) V*;
+template <class V> __device__ __forceinline__ GPtr<V> gview(const V* p) { return (GPtr<V>)p; }
+typedef float F2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 gload(const float2* p, size_t i) {
+  const F2v v = gview(reinterpret_cast<const F2v*>(p))[i];
+  return make_float2(v.x, v.y);
+}
 
 __device__ __forceinline__ bool bit_at(const uint32_t* __restrict__ S, int idx) {
   return (S[idx >> 5] >> (idx & 31)) & 1u;
@@ -72,21 +98,72 @@ __device__ __forceinline__ bool bit_at(const uint32_t* __restrict__ S, int idx) 
 // The real-space arithmetic below spells out every rounding (__fmul_rn,
 // fmaf), so that the run-time and the specialised forms of a kernel, which
 // the compiler would otherwise contract differently, give identical bits.
+// The constraint form is a template argument: launches resolve it once (it is
+// uniform), and the element loops are then straight-line code with selects.
+template <int MODE>
 __device__ __forceinline__ float2 proj_phase(float2 z, const Phase& ph) {
-  if (ph.mode == PHASE_OFF) return z;
-  if (ph.mode == PHASE_POS) return make_float2(fmaxf(z.x, 0.f), z.y);
-  const float aim = fabsf(z.y);
-  if (__fmul_rn(aim, ph.c) <= __fmul_rn(z.x, ph.s)) return z;
-  const float p = fmaxf(fmaf(z.x, ph.c, __fmul_rn(aim, ph.s)), 0.f);
-  const float sg = z.y < 0.f ? -1.f : 1.f;
-  return make_float2(__fmul_rn(p, ph.c), __fmul_rn(sg * p, ph.s));
+  if constexpr (MODE == PHASE_OFF) {
+    return z;
+  } else if constexpr (MODE == PHASE_POS) {
+    return make_float2(fmaxf(z.x, 0.f), z.y);
+  } else {
+    const float aim = fabsf(z.y);
+    const bool inside = __fmul_rn(aim, ph.c) <= __fmul_rn(z.x, ph.s);
+    const float p = fmaxf(fmaf(z.x, ph.c, __fmul_rn(aim, ph.s)), 0.f);
+    const float ps = __fmul_rn(p, ph.s);
+    const float2 r = make_float2(__fmul_rn(p, ph.c), z.y < 0.f ? -ps : ps);
+    return inside ? z : r;
+  }
 }
 
+template <int MODE>
 __device__ __forceinline__ bool inside_phase(float2 z, const Phase& ph) {
-  if (ph.mode == PHASE_OFF) return true;
-  if (ph.mode == PHASE_POS) return z.x >= 0.f;
-  return __fmul_rn(fabsf(z.y), ph.c) <= __fmul_rn(z.x, ph.s);
+  if constexpr (MODE == PHASE_OFF) return true;
+  else if constexpr (MODE == PHASE_POS) return z.x >= 0.f;
+  else return __fmul_rn(fabsf(z.y), ph.c) <= __fmul_rn(z.x, ph.s);
 }
+
+__device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
+
+
+// The modulus values of a column tile's elements t + T*m of column col; the
+// storage form (FP32 or FP16) is uniform, so it is resolved once.
+__device__ __forceinline__ void load_col_amp(float (&mv)[E], const SlotDesc& d, int t, int col) {
+  if (d.amp16) {
+    GPtr<unsigned short> p = gview(reinterpret_cast<const unsigned short*>(d.amp16));
+#pragma unroll
+    for (int m = 0; m < E; ++m) mv[m] = __half2float(__ushort_as_half(p[(size_t)(t + T * m) * N + col]));
+  } else {
+    GPtr<float> p = gview(d.amp);
+#pragma unroll
+    for (int m = 0; m < E; ++m) mv[m] = p[(size_t)(t + T * m) * N + col];
+  }
+}
+
+template <int M> using ModeC = std::integral_constant<int, M>;
+// Calls f(ModeC<mode>{}) for a phase-constraint mode known only at run time.
+template <class F>
+__device__ __forceinline__ void with_phase_mode(int mode, F&& f) {
+  if (mode == PHASE_OFF) f(ModeC<PHASE_OFF>{});
+  else if (mode == PHASE_POS) f(ModeC<PHASE_POS>{});
+  else f(ModeC<PHASE_CONE>{});
+}
+
+// Support bits of a lane's row elements t + T*m, packed into one mask (bit m)
+// as soon as the words arrive, so that one register holds them.
+__device__ __forceinline__ uint32_t load_row_mask(const uint32_t* __restrict__ S, int row, int t) {
+  static_assert(E <= 32, "one mask bit per element");
+  uint32_t w[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) w[m] = gview(S)[(row * N + t + T * m) >> 5];
+  uint32_t mask = 0;
+#pragma unroll
+  for (int m = 0; m < E; ++m) mask |= ((w[m] >> ((row * N + t + T * m) & 31)) & 1u) << m;
+  return mask;
+}
+__device__ __forceinline__ bool mask_bit(uint32_t mask, int m) { return (mask >> m) & 1u; }
+// Makes v materialise here (no instruction of its own).
+__device__ __forceinline__ void materialise(uint32_t v) { asm volatile("" ::"v"(v)); }
 
 // Column-tile placement.  Workgroups go to the 8 XCDs round-robin by linear
 // id, and each XCD has its own L2.  A tile of C columns reads 8C bytes of every
@@ -107,20 +184,25 @@ __device__ __forceinline__ TileId col_tile_id() {
   return {ltile % ntiles, ltile / ntiles};
 }
 
-// Masked modulus replacement on one unitary Fourier value (Eq. pm_full):
-// measured pixels get modulus M with the current phase (phase 0 if X = 0).
-// An unknown pixel stores minus its amplitude bound (-0: none); a value
-// above the bound is brought down to it with its phase (Eq. pm_bounds).
-__device__ __forceinline__ float2 modulus_replace(float2 X, float stored, float scale) {
+// Masked modulus replacement (Eq. pm_full) on the unnormalised column
+// spectrum X = N * (unitary value), returning the projected unitary value
+// divided by N, the input of the unnormalised inverse column transform; both
+// normalisations are folded into one factor per element.  Measured pixels get
+// modulus M with the current phase (phase 0 if X = 0).  An unknown pixel
+// stores minus its amplitude bound (-0: none); a unitary value above the
+// bound b is brought down to it with its phase (Eq. pm_bounds).  The branches
+// follow the mask, which is coherent over neighbouring pixels.
+__device__ __forceinline__ float2 modulus_replace(float2 X, float stored, float scale, float inv) {
   const float m2 = fmaf(X.x, X.x, __fmul_rn(X.y, X.y));
   if (signbit(stored)) {
     const float b = __fmul_rn(-stored, scale);
-    if (b > 0.f && m2 > __fmul_rn(b, b)) return cscale(X, __fmul_rn(b, rsqrtf(m2)));
-    return X;
+    const float bn = __fmul_rn(b, (float)N);  // the bound on |X|
+    if (b > 0.f && m2 > __fmul_rn(bn, bn)) return cscale(X, __fmul_rn(__fmul_rn(b, inv), rsqrtf(m2)));
+    return cscale(X, __fmul_rn(inv, inv));
   }
-  const float Mv = __fmul_rn(stored, scale);
-  if (m2 > 0.f) return cscale(X, __fmul_rn(Mv, rsqrtf(m2)));
-  return make_float2(Mv, 0.f);
+  const float Mn = __fmul_rn(__fmul_rn(stored, scale), inv);
+  if (m2 > 0.f) return cscale(X, __fmul_rn(Mn, rsqrtf(m2)));
+  return make_float2(Mn, 0.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -131,24 +213,23 @@ __global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
   const int tid = threadIdx.x;
   const int r = tid / T, t = tid % T;
   const int grow = blockIdx.x * RW + r;
-  const bool valid = grow < a.nm * N;
-  const int member = valid ? grow / N : 0;
+  const bool valid = kRowsExact || grow < a.nm * N;
+  const int member = valid ? row_member(grow) : 0;
   const int row = valid ? grow % N : 0;
   const SlotDesc d = a.desc[a.slots[member]];
   const size_t off = (size_t)row * N;                         // within the member's density
   const size_t toff = (size_t)member * NN + (size_t)row * N;  // work buffer: by launch position
-  const uint32_t* Sm = d.S;
   float2 v[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int e = t + T * m;
-    float2 z = valid ? d.X[off + e] : make_float2(0.f, 0.f);
-    if (a.mode != INGEST_PLAIN) {
-      const bool s = bit_at(Sm, row * N + e);
-      if (a.mode == INGEST_PC) z = s ? proj_phase(z, a.ph) : make_float2(0.f, 0.f);
-      else z = s ? z : make_float2(0.f, 0.f);
-    }
-    v[m] = z;
+  for (int m = 0; m < E; ++m) v[m] = valid ? gload(d.X, off + t + T * m) : make_float2(0.f, 0.f);
+  if (a.mode != INGEST_PLAIN) {
+    const uint32_t smask = load_row_mask(d.S, row, t);
+    const int mode = a.mode == INGEST_PC ? a.ph.mode : PHASE_OFF;
+    with_phase_mode(mode, [&](auto MC) {
+#pragma unroll
+      for (int m = 0; m < E; ++m)
+        v[m] = mask_bit(smask, m) ? proj_phase<MC.value>(v[m], a.ph) : make_float2(0.f, 0.f);
+    });
   }
   fft<N, -1, RowL>(v, lds + r * NR, t, a.tw);
   float2* Tw = a.t_by_slot ? d.T + off : a.T + toff;
@@ -161,31 +242,38 @@ __global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
 // ---------------------------------------------------------------------------
 // Column projection: column FFT -> masked P_M -> column IFFT.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
+#ifdef SPR_ROW_WPE
+#define SPR_ROW_OCC __attribute__((amdgpu_waves_per_eu(SPR_ROW_WPE)))
+#else
+#define SPR_ROW_OCC
+#endif
+#ifdef SPR_COL_WPE
+#define SPR_COL_OCC __attribute__((amdgpu_waves_per_eu(SPR_COL_WPE)))
+#else
+#define SPR_COL_OCC
+#endif
+__global__ __launch_bounds__(C* T) SPR_COL_OCC void k_col_proj(ColProjArgs a) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const int c = tid % C, t = tid / C;
   const TileId id = col_tile_id();
   const int col = id.tile * C + c;
   float2* dst = a.Y + (size_t)id.img * NN;
-  const SlotDesc& d = a.desc[a.slots[id.img]];
+  const SlotDesc d = a.desc[a.slots[id.img]];
   const float2* src = a.t_by_slot ? d.T : a.T + (size_t)id.img * NN;
   const float amp_scale = d.amp_scale;
   float2 v[E];
   float mv[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = src[(size_t)(t + T * m) * N + col];
-#pragma unroll
-  for (int m = 0; m < E; ++m) mv[m] = amp_load(d.amp, d.amp16, (size_t)(t + T * m) * N + col);
+  for (int m = 0; m < E; ++m) v[m] = gload(src, (size_t)(t + T * m) * N + col);
+  load_col_amp(mv, d, t, col);
+  issue_fence();
   TwSet<N> ws;
   load_twiddle_set<N>(ws, t, a.tw);
   fft<N, -1, ColL>(v, lds + c, t, a.tw, ws);
   const float inv = 1.0f / (float)N;
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const float2 X = cscale(v[m], inv);  // unitary spectrum
-    v[m] = cscale(modulus_replace(X, mv[m], amp_scale), inv);
-  }
+  for (int m = 0; m < E; ++m) v[m] = modulus_replace(v[m], mv[m], amp_scale, inv);
   fft<N, +1, ColL>(v, lds + c, t, a.tw, ws);
 #pragma unroll
   for (int m = 0; m < E; ++m) dst[(size_t)(t + T * m) * N + col] = v[m];
@@ -199,18 +287,17 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
 // ER, HIO and RAAR compiled alone, which frees the registers of the paths a
 // uniform launch never takes.
 template <int SPEC>
-__global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
+__global__ __launch_bounds__(RW* T) SPR_ROW_OCC void k_row_update(RowUpdateArgs a) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const int r = tid / T, t = tid % T;
   const int grow = blockIdx.x * RW + r;
-  const bool valid = grow < a.nm * N;
-  const int member = valid ? grow / N : 0;
+  const bool valid = kRowsExact || grow < a.nm * N;
+  const int member = valid ? row_member(grow) : 0;
   const int row = valid ? grow % N : 0;
   const SlotDesc d = a.desc[a.slots[member]];
   const size_t off = (size_t)row * N;                         // within the member's density
   const size_t toff = (size_t)member * NN + (size_t)row * N;  // work buffers: by launch position
-  const uint32_t* Sm = d.S;
   float2* l = lds + r * NR;
   int alg = a.alg, out_mode = a.out_mode;
   float beta = a.beta;
@@ -232,6 +319,11 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
 
   const bool ia = alg != ALG_ER;
   float2* Tw = a.t_by_slot ? d.T + off : a.T + toff;
+  TwSet<N> ws;
+  load_twiddle_set<N>(ws, t, a.tw);  // first: the table is cache-resident
+  // the support words first: their mask is formed while the row data are
+  // still in flight (loads complete in issue order)
+  const uint32_t smask = (ia || out_mode == OUT_T_PC) ? load_row_mask(d.S, row, t) : 0u;
   float2 y[E], x[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) y[m] = valid ? a.Y[toff + t + T * m] : make_float2(0.f, 0.f);
@@ -239,8 +331,10 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
 #pragma unroll
     for (int m = 0; m < E; ++m) x[m] = valid ? Tw[t + T * m] : make_float2(0.f, 0.f);
   }
-  TwSet<N> ws;
-  load_twiddle_set<N>(ws, t, a.tw);
+  // keep every load of the row ahead of the first transform (compiler fence
+  // only: no instruction), so that all of them are in flight together
+  issue_fence();
+  materialise(smask);
   fft<N, +1, RowL>(y, l, t, a.tw, ws);  // y = P_M x (real space)
 
   float2 xn[E];
@@ -250,22 +344,25 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   } else {
     fft<N, +1, RowL>(x, l, t, a.tw, ws);
     const float inv = 1.0f / (float)N;
+    with_phase_mode(ph.mode, [&](auto MC) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const float2 xv = make_float2(__fmul_rn(x[m].x, inv), __fmul_rn(x[m].y, inv));
-      const float2 yv = y[m];
-      const bool s = bit_at(Sm, row * N + t + T * m);
-      if (alg == ALG_HIO) {
-        const bool feasible = s && inside_phase(yv, ph);
-        xn[m] = feasible ? yv : make_float2(fmaf(-beta, yv.x, xv.x), fmaf(-beta, yv.y, xv.y));
-      } else {  // RAAR
-        const float2 z = make_float2(fmaf(2.f, yv.x, -xv.x), fmaf(2.f, yv.y, -xv.y));
-        const float2 pc = s ? proj_phase(z, ph) : make_float2(0.f, 0.f);
-        const float g = fmaf(-2.f, beta, 1.f);
-        xn[m] = make_float2(fmaf(beta, pc.x, fmaf(beta, xv.x, __fmul_rn(g, yv.x))),
-                            fmaf(beta, pc.y, fmaf(beta, xv.y, __fmul_rn(g, yv.y))));
+      for (int m = 0; m < E; ++m) {
+        const float2 xv = make_float2(__fmul_rn(x[m].x, inv), __fmul_rn(x[m].y, inv));
+        const float2 yv = y[m];
+        const bool s = mask_bit(smask, m);
+        if (alg == ALG_HIO) {
+          const bool feasible = s & inside_phase<MC.value>(yv, ph);
+          xn[m] = feasible ? yv : make_float2(fmaf(-beta, yv.x, xv.x), fmaf(-beta, yv.y, xv.y));
+        } else {  // RAAR
+          const float2 z = make_float2(fmaf(2.f, yv.x, -xv.x), fmaf(2.f, yv.y, -xv.y));
+          const float2 pz = proj_phase<MC.value>(z, ph);
+          const float2 pc = s ? pz : make_float2(0.f, 0.f);
+          const float g = fmaf(-2.f, beta, 1.f);
+          xn[m] = make_float2(fmaf(beta, pc.x, fmaf(beta, xv.x, __fmul_rn(g, yv.x))),
+                              fmaf(beta, pc.y, fmaf(beta, xv.y, __fmul_rn(g, yv.y))));
+        }
       }
-    }
+    });
   }
 
   if (out_mode == OUT_REAL) {
@@ -276,11 +373,13 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
     return;
   }
   if (out_mode == OUT_T_PC) {
+    with_phase_mode(ph_next.mode, [&](auto MC) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const bool s = bit_at(Sm, row * N + t + T * m);
-      xn[m] = s ? proj_phase(xn[m], ph_next) : make_float2(0.f, 0.f);
-    }
+      for (int m = 0; m < E; ++m) {
+        const float2 pz = proj_phase<MC.value>(xn[m], ph_next);
+        xn[m] = mask_bit(smask, m) ? pz : make_float2(0.f, 0.f);
+      }
+    });
   }
   fft<N, -1, RowL>(xn, l, t, a.tw, ws);
   if (valid) {
@@ -305,14 +404,13 @@ __global__ __launch_bounds__(C* T) void k_col_err(ColErrArgs a) {
   const int c = tid % C, t = tid / C;
   const TileId id = col_tile_id();
   const int col = id.tile * C + c;
-  const SlotDesc& d = a.desc[a.slots[id.img]];
+  const SlotDesc d = a.desc[a.slots[id.img]];
   const float2* src = a.t_by_slot ? d.T : a.T + (size_t)id.img * NN;
   float2 v[E];
   float mv[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = src[(size_t)(t + T * m) * N + col];
-#pragma unroll
-  for (int m = 0; m < E; ++m) mv[m] = amp_load(d.amp, d.amp16, (size_t)(t + T * m) * N + col);
+  for (int m = 0; m < E; ++m) v[m] = gload(src, (size_t)(t + T * m) * N + col);
+  load_col_amp(mv, d, t, col);
   fft<N, -1, ColL>(v, lds + c, t, a.tw);
   const float inv = 1.0f / (float)N;
   double acc = 0.0;
@@ -345,8 +443,8 @@ __global__ __launch_bounds__(RW* T) void k_row_fft(RowFftArgs a) {
   const int tid = threadIdx.x;
   const int r = tid / T, t = tid % T;
   const int grow = blockIdx.x * RW + r;
-  const bool valid = grow < a.nm * N;
-  const int member = valid ? grow / N : 0;
+  const bool valid = kRowsExact || grow < a.nm * N;
+  const int member = valid ? row_member(grow) : 0;
   const int row = valid ? grow % N : 0;
   const int si = a.slots_in ? a.slots_in[member] : member;
   const int so = a.slots_out ? a.slots_out[member] : member;
@@ -376,7 +474,7 @@ __global__ __launch_bounds__(C* T) void k_col_fft(ColFftArgs a) {
   float2* dst = a.out + (size_t)so * NN;
   float2 v[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = src[(size_t)(t + T * m) * N + col];
+  for (int m = 0; m < E; ++m) v[m] = gload(src, (size_t)(t + T * m) * N + col);
   if (a.dir < 0) fft<N, -1, ColL>(v, lds + c, t, a.tw);
   else fft<N, +1, ColL>(v, lds + c, t, a.tw);
 #pragma unroll
