@@ -754,10 +754,10 @@ def main():
     pop.sync()
     torch.cuda.synchronize()
 
-    # timed region: K generations; HIP events only around the dominant kernel's
-    # launches (k_row_update, ER and HIO/RAAR forms, run in every iteration),
-    # on the launch stream
-    pop.timing(True, kernels=[B.KERNEL_ROW_UPDATE_ER, B.KERNEL_ROW_UPDATE_IA])
+    # timed region: K generations; HIP events around the launches of the two
+    # projection-loop kernels (k_col_proj; k_row_update, ER and HIO/RAAR forms),
+    # which run in every iteration, on the launch stream
+    pop.timing(True, kernels=[B.KERNEL_COL_PROJ, B.KERNEL_ROW_UPDATE_ER, B.KERNEL_ROW_UPDATE_IA])
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -771,6 +771,7 @@ def main():
     gpu_ms = ev0.elapsed_time(ev1)
     n_er, ms_er = pop.timing_read(B.KERNEL_ROW_UPDATE_ER)
     n_ia, ms_ia = pop.timing_read(B.KERNEL_ROW_UPDATE_IA)
+    n_cp, ms_cp = pop.timing_read(B.KERNEL_COL_PROJ)
     n_l, ms = n_er + n_ia, ms_er + ms_ia
 
     # one more generation with every iteration kernel timed (breakdown only)
@@ -792,6 +793,19 @@ def main():
     achieved = bytes_per_launch / (ms / n_l * 1e-3) / 1e9
     t_er, t_ia = measured_traffic("row_update_er", chunk), measured_traffic("row_update_ia", chunk)
     traffic = (n_er * t_er + n_ia * t_ia) / n_l if t_er is not None and t_ia is not None else None
+    roof_row = {"bound": "hbm", "kernel": "k_row_update", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic, "launches": n_l, "avg_launch_us": ms / n_l * 1e3,
+                "total_ms": ms, "algorithmic_bytes_per_launch": bytes_per_launch,
+                "launch_mix": {"ER": n_er, "HIO/RAAR": n_ia}}
+    cp_bytes = algorithmic_bytes_per_px(B.KERNEL_COL_PROJ, chunk) * N * N * chunk
+    cp_achieved = cp_bytes / (ms_cp / n_cp * 1e-3) / 1e9
+    roof_col = {"bound": "hbm", "kernel": "k_col_proj", "achieved": cp_achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": cp_achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(B.KERNEL_COL_PROJ, chunk), "launches": n_cp,
+                "avg_launch_us": ms_cp / n_cp * 1e3, "total_ms": ms_cp, "algorithmic_bytes_per_launch": cp_bytes}
+    # the dominant kernel: the larger share of event-timed time in the timed region
+    roofline = roof_row if ms >= ms_cp else roof_col
     # whole-step algorithmic bytes: iterations only (ingest/shrink-wrap/fitness/crossover excluded)
     ia_its = er_its = 0
     for i in range(args.warmup, total):
@@ -823,11 +837,8 @@ def main():
                                "R=3 x 20 + 40 ER = 100 iterations per member per generation",
                    "n": N, "P": P, "members": 2 * P, "generations_timed": args.steps,
                    "schedule_G": G},
-        "roofline": {"bound": "hbm", "kernel": "k_row_update", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "launches": n_l, "avg_launch_us": ms / n_l * 1e3,
-                     "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "launch_mix": {"ER": n_er, "HIO/RAAR": n_ia}},
+        "roofline": roofline,
+        "rooflines": {"k_row_update": roof_row, "k_col_proj": roof_col},
         "members_per_launch": chunk,
         "kernels": {B.KERNEL_NAMES[k]: {"launches": v[0], "avg_us": v[1] / v[0] * 1e3,
                                         "GBps": algorithmic_bytes_per_px(k, chunk) * N * N * chunk
