@@ -141,6 +141,208 @@ __global__ __launch_bounds__(SMOOTH_THREADS) void k_smooth_cols(SmoothColArgs a)
   }
 }
 
+// Fused 2D smoothing: a workgroup smooths a tile of up to 64 x 64 outputs of
+// one member.  |x| of the tile and a periodic halo of RC on every side is
+// staged in LDS, the row taps go to a second LDS array for the tile's columns
+// (halo rows included), and the column taps produce the outputs and the tile
+// maximum.  Each thread slides a window of 8 outputs along its row or column,
+// so every staged value is read once per window.  The 2 RC + 1 taps are the
+// 2r + 1 Gaussian weights centred in zeros (RC >= r, chosen per launch): the
+// products of the zero taps add nothing, so each output accumulates exactly
+// the Gaussian taps, in k order, with fused multiply-adds, as the separate
+// row and column passes do (a non-finite |x| within RC - r pixels beyond an
+// output's window also reaches that output; such a density already has a
+// non-finite fitness).
+struct Smooth2dArgs {
+  const int* slots;
+  const SlotDesc* desc;
+  int nm, n;
+  float* out;        // [member][n*n]
+  float* block_max;  // [member][tiles]
+  float w[MAX_TAPS];  // centred: w[RC - r + k] = Gaussian tap k, zero elsewhere
+};
+constexpr int SM_TILE = 64;
+constexpr int SM_SEG = 8;
+constexpr int SM_THREADS = 512;
+constexpr int SM_BATCH = 4;
+
+__host__ __device__ inline int round8(int v) { return (v + 7) & ~7; }
+
+template <int RC, bool FULL>
+__global__ __launch_bounds__(SM_THREADS) void k_smooth2d(Smooth2dArgs a) {
+  extern __shared__ float sm[];
+  __shared__ float wmax[SM_THREADS / 64];
+  const int n = a.n;
+  // FULL: n >= SM_TILE, so the tile geometry (and every LDS offset) is known
+  // at compile time
+  const int tw = FULL ? SM_TILE : (n < SM_TILE ? n : SM_TILE), th = tw;
+  const int twr = round8(tw), thr = round8(th);
+  // odd pitches: a wavefront reading one element of 64 consecutive rows hits
+  // 64 different LDS banks
+  const int apitch = twr + 2 * RC + 1;  // A: (thr + 2 RC) rows x apitch
+  const int bpitch = twr + 1;           // B: (thr + 2 RC) rows x bpitch
+  const int arows = thr + 2 * RC;
+  float* A = sm;
+  float* Bt = sm;  // B (row-smoothed), written over A once A is consumed
+  const int c0 = blockIdx.x * tw, i0 = blockIdx.y * th, m = blockIdx.z;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = SM_THREADS / 64;
+  typedef float F2v __attribute__((ext_vector_type(2)));
+  const __attribute__((address_space(1))) F2v* X = (const __attribute__((address_space(1))) F2v*)a.desc[a.slots[m]].X;
+  // stage A: |x| with the periodic halo; the wrapped columns of a lane are
+  // the same on every row
+  constexpr int MAXC = (SM_TILE + 2 * RC + 63) / 64;
+  int gcol[MAXC];
+#pragma unroll
+  for (int q = 0; q < MAXC; ++q) {
+    int gj = (c0 - RC + lane + 64 * q) % n;
+    gcol[q] = gj < 0 ? gj + n : gj;
+  }
+  // rows in batches of SM_BATCH per wavefront: all loads of a batch are in
+  // flight before the first is used
+  for (int row0 = wave; row0 < arows; row0 += NW * SM_BATCH) {
+    F2v z[SM_BATCH][MAXC];
+#pragma unroll
+    for (int b = 0; b < SM_BATCH; ++b) {
+      const int row = row0 + NW * b;
+      // the row is the same for the whole wavefront: its base address is scalar
+      int gi = i0 - RC + row;
+      if (gi < 0 || gi >= n) {
+        gi %= n;
+        gi = gi < 0 ? gi + n : gi;
+      }
+      gi = __builtin_amdgcn_readfirstlane(gi);
+      const __attribute__((address_space(1))) F2v* xr = X + (size_t)gi * n;
+#pragma unroll
+      for (int q = 0; q < MAXC; ++q) {
+        const int col = lane + 64 * q;
+        if (row < arows && col < apitch) z[b][q] = xr[gcol[q]];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < SM_BATCH; ++b) {
+      const int row = row0 + NW * b;
+#pragma unroll
+      for (int q = 0; q < MAXC; ++q) {
+        const int col = lane + 64 * q;
+        if (row < arows && col < apitch) A[row * apitch + col] = sqrtf(z[b][q].x * z[b][q].x + z[b][q].y * z[b][q].y);
+      }
+    }
+  }
+  __syncthreads();
+  // stage B: row taps, windows of 8 outputs along the rows, held in registers
+  // until every thread has read A
+  const int nseg_b = twr / SM_SEG;
+  constexpr int MAXI = ((SM_TILE + 2 * RC) * (SM_TILE / SM_SEG) + SM_THREADS - 1) / SM_THREADS;
+  float accb[MAXI][SM_SEG];
+#pragma unroll
+  for (int it = 0; it < MAXI; ++it) {
+    const int item = threadIdx.x + it * SM_THREADS;
+    if (item < arows * nseg_b) {
+      int seg = 0, row = item;
+      while (row >= arows) {  // at most SM_TILE / SM_SEG steps, no division
+        row -= arows;
+        ++seg;
+      }
+      const float* src = A + row * apitch + seg * SM_SEG;
+#pragma unroll
+      for (int j = 0; j < SM_SEG; ++j) accb[it][j] = 0.f;
+#pragma unroll
+      for (int t = 0; t < SM_SEG + 2 * RC; ++t) {
+        const float v = src[t];
+#pragma unroll
+        for (int j = 0; j < SM_SEG; ++j) {
+          const int k = t - j;
+          if (k >= 0 && k <= 2 * RC) accb[it][j] += a.w[k] * v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < MAXI; ++it) {
+    const int item = threadIdx.x + it * SM_THREADS;
+    if (item < arows * nseg_b) {
+      int seg = 0, row = item;
+      while (row >= arows) {
+        row -= arows;
+        ++seg;
+      }
+#pragma unroll
+      for (int j = 0; j < SM_SEG; ++j) Bt[row * bpitch + seg * SM_SEG + j] = accb[it][j];
+    }
+  }
+  __syncthreads();
+  // stage C: column taps, windows of 8 outputs down the columns
+  float mx = 0.f;
+  float* out = a.out + (size_t)m * n * n;
+  const int nseg_c = thr / SM_SEG;
+  for (int item = threadIdx.x; item < twr * nseg_c; item += SM_THREADS) {
+    int seg = 0, col = item;
+    while (col >= twr) {
+      col -= twr;
+      ++seg;
+    }
+    const float* src = Bt + seg * SM_SEG * bpitch + col;
+    float acc[SM_SEG];
+#pragma unroll
+    for (int j = 0; j < SM_SEG; ++j) acc[j] = 0.f;
+#pragma unroll
+    for (int t = 0; t < SM_SEG + 2 * RC; ++t) {
+      const float v = src[t * bpitch];
+#pragma unroll
+      for (int j = 0; j < SM_SEG; ++j) {
+        const int k = t - j;
+        if (k >= 0 && k <= 2 * RC) acc[j] += a.w[k] * v;
+      }
+    }
+    if (col < tw && c0 + col < n) {
+#pragma unroll
+      for (int j = 0; j < SM_SEG; ++j) {
+        const int oi = seg * SM_SEG + j;
+        if (oi < th && i0 + oi < n) {
+          out[(size_t)(i0 + oi) * n + c0 + col] = acc[j];
+          mx = fmaxf(mx, acc[j]);
+        }
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  if (lane == 0) wmax[wave] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float v = wmax[0];
+    for (int w = 1; w < NW; ++w) v = fmaxf(v, wmax[w]);
+    a.block_max[(size_t)m * (gridDim.x * gridDim.y) + blockIdx.y * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+size_t smooth2d_lds(int n, int rc) {
+  const int t = n < SM_TILE ? n : SM_TILE;
+  const int tr = round8(t);
+  return (size_t)(tr + 2 * rc) * (tr + 2 * rc + 1) * sizeof(float);
+}
+
+template <int RC, bool FULL>
+hipError_t launch_smooth2d_tile(const Smooth2dArgs& a, dim3 grid, hipStream_t s) {
+  const size_t lds = smooth2d_lds(a.n, RC);
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_smooth2d<RC, FULL>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_smooth2d<RC, FULL>), grid, dim3(SM_THREADS), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int RC>
+hipError_t launch_smooth2d_rc(Smooth2dArgs a, const float* w, int r, dim3 grid, hipStream_t s) {
+  for (int k = 0; k < MAX_TAPS; ++k) a.w[k] = 0.f;
+  for (int k = 0; k <= 2 * r; ++k) a.w[RC - r + k] = w[k];
+  if (a.n >= SM_TILE) return launch_smooth2d_tile<RC, true>(a, grid, s);
+  return launch_smooth2d_tile<RC, false>(a, grid, s);
+}
+
 __global__ __launch_bounds__(256) void k_member_max(MemberMaxArgs a) {
   __shared__ float wmax[4];
   const int m = blockIdx.x;
@@ -822,11 +1024,30 @@ hipError_t launch_smooth(const SmoothArgs& rows, const SmoothColArgs& cols, cons
                          hipStream_t s) {
   const int n = rows.n;
   if (n > 1024 || rows.r > (MAX_TAPS - 1) / 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_smooth_rows, dim3(n, rows.nm), dim3(SMOOTH_THREADS), 0, s, rows);
   const int cw = n < COLS_PER_TILE ? n : COLS_PER_TILE;
   const int rh = n < ROWS_PER_TILE ? n : ROWS_PER_TILE;
-  hipLaunchKernelGGL(k_smooth_cols, dim3((n + cw - 1) / cw, (n + rh - 1) / rh, cols.nm), dim3(SMOOTH_THREADS), 0,
-                     s, cols);
+  const dim3 grid((n + cw - 1) / cw, (n + rh - 1) / rh, rows.nm);
+  if (SM_TILE == COLS_PER_TILE && SM_TILE == ROWS_PER_TILE) {
+    Smooth2dArgs a{};
+    a.slots = rows.slots;
+    a.desc = rows.desc;
+    a.nm = rows.nm;
+    a.n = n;
+    a.out = cols.out;
+    a.block_max = cols.block_max;
+    const int r = rows.r;
+    hipError_t e;
+    if (r == 0) e = launch_smooth2d_rc<0>(a, rows.w, r, grid, s);
+    else if (r <= 2) e = launch_smooth2d_rc<2>(a, rows.w, r, grid, s);
+    else if (r <= 4) e = launch_smooth2d_rc<4>(a, rows.w, r, grid, s);
+    else if (r <= 8) e = launch_smooth2d_rc<8>(a, rows.w, r, grid, s);
+    else if (r <= 16) e = launch_smooth2d_rc<16>(a, rows.w, r, grid, s);
+    else e = launch_smooth2d_rc<32>(a, rows.w, r, grid, s);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_smooth_rows, dim3(n, rows.nm), dim3(SMOOTH_THREADS), 0, s, rows);
+    hipLaunchKernelGGL(k_smooth_cols, grid, dim3(SMOOTH_THREADS), 0, s, cols);
+  }
   hipLaunchKernelGGL(k_member_max, dim3(mx.nm), dim3(256), 0, s, mx);
   return hipGetLastError();
 }
