@@ -522,8 +522,7 @@ void run_iterations(const Group& g, const std::vector<Iter>& its, hipStream_t s)
 }
 
 void smooth(const Group& g, double sigma, hipStream_t s) {
-  SmoothArgs ra{};
-  SmoothColArgs ca{};
+  SmoothArgs sa{};
   int r = 0;
   std::vector<double> w(1, 1.0);
   if (sigma > 0) {
@@ -537,21 +536,16 @@ void smooth(const Group& g, double sigma, hipStream_t s) {
     }
     for (auto& v : w) v /= sum;
   }
-  ra.slots = g.slots;
-  ra.nm = g.nm;
-  ra.n = g.n;
-  ra.r = r;
-  ra.desc = g.desc;
-  ra.out = reinterpret_cast<float*>(g.T);
-  ca.nm = g.nm;
-  ca.n = g.n;
-  ca.r = r;
-  ca.in = ra.out;
-  ca.out = reinterpret_cast<float*>(g.Y);
-  ca.block_max = g.block_max;
-  for (int k = 0; k <= 2 * r; ++k) ra.w[k] = ca.w[k] = (float)w[k];
+  sa.slots = g.slots;
+  sa.nm = g.nm;
+  sa.n = g.n;
+  sa.r = r;
+  sa.desc = g.desc;
+  sa.out = reinterpret_cast<float*>(g.Y);
+  sa.block_max = g.block_max;
+  for (int k = 0; k <= 2 * r; ++k) sa.w[k] = (float)w[k];
   MemberMaxArgs ma{g.nm, smooth_blocks_per_member(g.n), g.block_max, g.maxv};
-  launch_ok(launch_smooth(ra, ca, ma, s), "smooth");
+  launch_ok(launch_smooth(sa, ma, s), "smooth");
 }
 
 void shrinkwrap(const Group& g, double sigma, double tau, hipStream_t s) {
@@ -575,6 +569,9 @@ void support_area(const Group& g, double sigma, const double* alpha_src, int alp
   ta.alpha_index = alpha_index;
   ta.alpha_abs = alpha_abs;
   ta.desc = g.desc;
+  // the row-transform buffer is free between sequences: it holds the
+  // selection's histograms (at least nm * n * n floats)
+  ta.scratch = reinterpret_cast<uint32_t*>(g.T);
   launch_ok(launch_topk(ta, s), "topk");
 }
 

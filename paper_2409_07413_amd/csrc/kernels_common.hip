@@ -75,71 +75,6 @@ __global__ void k_err_final(ErrFinalArgs a) {
 // ---------------------------------------------------------------------------
 // Shrink-wrap: |x| smoothed by a circular separable Gaussian (rows, columns).
 // ---------------------------------------------------------------------------
-constexpr int SMOOTH_THREADS = 256;
-constexpr int COLS_PER_TILE = 64;
-constexpr int ROWS_PER_TILE = 64;
-
-// One workgroup per row: |x| with its periodic halo in LDS, then the taps.
-__global__ __launch_bounds__(SMOOTH_THREADS) void k_smooth_rows(SmoothArgs a) {
-  __shared__ float ext[1024 + MAX_TAPS];
-  const int n = a.n, r = a.r;
-  const int i = blockIdx.x, m = blockIdx.y;
-  const float2* xr = a.desc[a.slots[m]].X + (size_t)i * n;
-  for (int q = threadIdx.x; q < n + 2 * r; q += blockDim.x) {
-    int j = (q - r) % n;
-    j = j < 0 ? j + n : j;
-    const float2 z = xr[j];
-    ext[q] = sqrtf(z.x * z.x + z.y * z.y);
-  }
-  __syncthreads();
-  float* out = a.out + (size_t)m * n * n + (size_t)i * n;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    float acc = 0.f;
-    for (int k = 0; k <= 2 * r; ++k) acc += a.w[k] * ext[j + k];
-    out[j] = acc;
-  }
-}
-
-// Column smoothing on a tile of 64 columns x 64 rows staged (with its periodic
-// halo rows) in LDS; also the tile maximum.
-__global__ __launch_bounds__(SMOOTH_THREADS) void k_smooth_cols(SmoothColArgs a) {
-  __shared__ float tile[(ROWS_PER_TILE + MAX_TAPS) * COLS_PER_TILE];
-  __shared__ float wmax[SMOOTH_THREADS / 64];
-  const int n = a.n, r = a.r;
-  const int cw = n < COLS_PER_TILE ? n : COLS_PER_TILE;
-  const int rh = n < ROWS_PER_TILE ? n : ROWS_PER_TILE;
-  const int c0 = blockIdx.x * cw, i0 = blockIdx.y * rh, m = blockIdx.z;
-  const float* src = a.in + (size_t)m * n * n;
-  const int rows_ext = rh + 2 * r;
-  for (int q = threadIdx.x; q < rows_ext * COLS_PER_TILE; q += blockDim.x) {
-    const int rr = q / COLS_PER_TILE, cc = q % COLS_PER_TILE;
-    if (cc < cw && c0 + cc < n) {
-      int ii = (i0 + rr - r) % n;
-      ii = ii < 0 ? ii + n : ii;
-      tile[q] = src[(size_t)ii * n + c0 + cc];
-    }
-  }
-  __syncthreads();
-  float mx = 0.f;
-  float* out = a.out + (size_t)m * n * n;
-  for (int q = threadIdx.x; q < rh * COLS_PER_TILE; q += blockDim.x) {
-    const int rr = q / COLS_PER_TILE, cc = q % COLS_PER_TILE;
-    if (cc < cw && c0 + cc < n && i0 + rr < n) {
-      float acc = 0.f;
-      for (int k = 0; k <= 2 * r; ++k) acc += a.w[k] * tile[(rr + k) * COLS_PER_TILE + cc];
-      out[(size_t)(i0 + rr) * n + c0 + cc] = acc;
-      mx = fmaxf(mx, acc);
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float v = wmax[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmaxf(v, wmax[w]);
-    a.block_max[(size_t)m * (gridDim.x * gridDim.y) + blockIdx.y * gridDim.x + blockIdx.x] = v;
-  }
-}
 
 // Fused 2D smoothing: a workgroup smooths a tile of up to 64 x 64 outputs of
 // one member.  |x| of the tile and a periodic halo of RC on every side is
@@ -498,6 +433,179 @@ __global__ __launch_bounds__(TOPK_THREADS) void k_topk(TopkArgs a) {
       if (kk[j] > prefix) {
         byte |= 1u << j;
       } else if (kk[j] == prefix) {
+        if (rank < rem) byte |= 1u << j;
+        ++rank;
+      }
+    }
+    if (i < nn) Sb[i >> 3] = (uint8_t)byte;
+    taken += (uint32_t)total;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// UpdateSupportSize on large images: the same selection spread over many
+// workgroups per member.  Three digit passes (bits 31..20, 19..8, 7..0 of the
+// float keys) each build the member's histogram of the keys that match the
+// digits found so far (per-workgroup LDS histograms added into a global one),
+// and a one-workgroup step per member picks the digit holding the k-th
+// largest key.  Then every workgroup counts its keys equal to the k-th
+// largest, and writes its support bytes, taking the equal keys in index order
+// after those of the earlier workgroups.
+// ---------------------------------------------------------------------------
+constexpr int TKM_THREADS = 256;
+constexpr int TKM_KEYS = TKM_THREADS * 32;  // keys per workgroup
+constexpr int TKM_BINS = 4096;
+
+struct TopkPass {
+  int shift, bits;
+};
+__host__ __device__ constexpr TopkPass topk_pass(int pass) {
+  return pass == 0 ? TopkPass{20, 12} : pass == 1 ? TopkPass{8, 12} : TopkPass{0, 8};
+}
+
+struct TopkMArgs {
+  TopkArgs a;
+  int bpm;          // workgroups per member
+  uint32_t* hist;   // [nm][TKM_BINS]
+  uint32_t* state;  // [nm][4]: digits found (prefix), their mask, keys still to take (rem)
+  uint32_t* ties;   // [nm][bpm]
+};
+
+__global__ __launch_bounds__(TKM_THREADS) void k_topkm_zero(TopkMArgs t) {
+  uint32_t* h = t.hist + (size_t)blockIdx.x * TKM_BINS;
+  for (int b = threadIdx.x; b < TKM_BINS; b += TKM_THREADS) h[b] = 0u;
+}
+
+template <int PASS>
+__global__ __launch_bounds__(TKM_THREADS) void k_topkm_hist(TopkMArgs t) {
+  constexpr TopkPass tp = topk_pass(PASS);
+  constexpr uint32_t dmask = (1u << tp.bits) - 1u;
+  __shared__ uint32_t lh[1 << tp.bits];
+  const int m = blockIdx.y, lane = threadIdx.x & 63;
+  const long nn = (long)t.a.n * t.a.n;
+  const uint32_t* keys = reinterpret_cast<const uint32_t*>(t.a.in + (size_t)m * nn);
+  const uint32_t prefix = PASS ? t.state[m * 4 + 0] : 0u, pmask = PASS ? t.state[m * 4 + 1] : 0u;
+  for (int b = threadIdx.x; b < (1 << tp.bits); b += TKM_THREADS) lh[b] = 0u;
+  __syncthreads();
+  const long base = (long)blockIdx.x * TKM_KEYS;
+#pragma unroll
+  for (int c = 0; c < TKM_KEYS / (TKM_THREADS * 8); ++c) {
+    const long i = base + (long)c * TKM_THREADS * 8 + (long)threadIdx.x * 8;
+    uint32_t kk[8];
+    load8(keys, i, nn, kk);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int bin = (i + j < nn && (kk[j] & pmask) == prefix) ? (int)((kk[j] >> tp.shift) & dmask) : -1;
+      wave_histogram_add(lh, bin, lane);
+    }
+  }
+  __syncthreads();
+  uint32_t* h = t.hist + (size_t)m * TKM_BINS;
+  for (int b = threadIdx.x; b < (1 << tp.bits); b += TKM_THREADS)
+    if (lh[b]) atomicAdd(&h[b], lh[b]);
+}
+
+template <int PASS>
+__global__ __launch_bounds__(TKM_THREADS) void k_topkm_select(TopkMArgs t) {
+  constexpr TopkPass tp = topk_pass(PASS);
+  constexpr int NB = 1 << tp.bits, PER = NB / TKM_THREADS;
+  __shared__ int scan_sh[TKM_THREADS / 64];
+  const int m = blockIdx.x;
+  uint32_t* h = t.hist + (size_t)m * TKM_BINS;
+  uint32_t* st = t.state + m * 4;
+  uint32_t rem;
+  if (PASS == 0) {
+    const long nn = (long)t.a.n * t.a.n;
+    const double alpha = t.a.alpha_src ? t.a.alpha_src[t.a.alpha_index] : t.a.alpha_abs;
+    double kd = floor(alpha + 0.5);
+    if (!(kd >= 1.0)) kd = 1.0;
+    if (kd > (double)nn) kd = (double)nn;
+    rem = (uint32_t)kd;
+  } else {
+    rem = st[2];
+  }
+  // thread u owns bins (TKM_THREADS - 1 - u) * PER ... + PER - 1, so that an
+  // exclusive scan over u counts the keys in higher bins
+  const int u = threadIdx.x;
+  const int lo = (TKM_THREADS - 1 - u) * PER;
+  uint32_t cnt[PER];
+  int part = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    cnt[q] = h[lo + q];
+    part += (int)cnt[q];
+  }
+  int total;
+  const int above = block_exclusive_scan(part, scan_sh, &total);
+  if ((uint32_t)above < rem && rem <= (uint32_t)(above + part)) {
+    uint32_t cum = (uint32_t)above;
+    int digit = lo;
+#pragma unroll
+    for (int q = PER - 1; q >= 0; --q) {
+      if (cum + cnt[q] >= rem) {
+        digit = lo + q;
+        break;
+      }
+      cum += cnt[q];
+    }
+    const uint32_t prefix = PASS ? st[0] : 0u, pmask = PASS ? st[1] : 0u;
+    st[0] = prefix | ((uint32_t)digit << tp.shift);
+    st[1] = pmask | (((1u << tp.bits) - 1u) << tp.shift);
+    st[2] = rem - cum;
+  }
+  // leave the histogram cleared for the next pass
+#pragma unroll
+  for (int q = 0; q < PER; ++q) h[lo + q] = 0u;
+}
+
+__global__ __launch_bounds__(TKM_THREADS) void k_topkm_ties(TopkMArgs t) {
+  __shared__ int scan_sh[TKM_THREADS / 64];
+  const int m = blockIdx.y;
+  const long nn = (long)t.a.n * t.a.n;
+  const uint32_t* keys = reinterpret_cast<const uint32_t*>(t.a.in + (size_t)m * nn);
+  const uint32_t kth = t.state[m * 4 + 0];
+  const long base = (long)blockIdx.x * TKM_KEYS;
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < TKM_KEYS / (TKM_THREADS * 8); ++r) {
+    const long i = base + (long)r * TKM_THREADS * 8 + (long)threadIdx.x * 8;
+    uint32_t kk[8];
+    load8(keys, i, nn, kk);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) c += (i + j < nn && kk[j] == kth) ? 1 : 0;
+  }
+  int total;
+  block_exclusive_scan(c, scan_sh, &total);
+  if (threadIdx.x == 0) t.ties[(size_t)m * t.bpm + blockIdx.x] = (uint32_t)total;
+}
+
+__global__ __launch_bounds__(TKM_THREADS) void k_topkm_write(TopkMArgs t) {
+  __shared__ int scan_sh[TKM_THREADS / 64];
+  const int m = blockIdx.y;
+  const long nn = (long)t.a.n * t.a.n;
+  const uint32_t* keys = reinterpret_cast<const uint32_t*>(t.a.in + (size_t)m * nn);
+  uint8_t* Sb = reinterpret_cast<uint8_t*>(t.a.desc[t.a.slots[m]].S);
+  const uint32_t kth = t.state[m * 4 + 0], rem = t.state[m * 4 + 2];
+  uint32_t taken = 0;  // equal keys in earlier workgroups
+  for (int b = 0; b < (int)blockIdx.x; ++b) taken += t.ties[(size_t)m * t.bpm + b];
+  const long base = (long)blockIdx.x * TKM_KEYS;
+  for (int r = 0; r < TKM_KEYS / (TKM_THREADS * 8); ++r) {
+    const long i = base + (long)r * TKM_THREADS * 8 + (long)threadIdx.x * 8;
+    uint32_t kk[8];
+    load8(keys, i, nn, kk);
+    int ties = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ties += (i + j < nn && kk[j] == kth) ? 1 : 0;
+    int total;
+    const int before = block_exclusive_scan(ties, scan_sh, &total);
+    uint32_t rank = taken + (uint32_t)before;
+    uint32_t byte = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (i + j >= nn) continue;
+      if (kk[j] > kth) {
+        byte |= 1u << j;
+      } else if (kk[j] == kth) {
         if (rank < rem) byte |= 1u << j;
         ++rank;
       }
@@ -1015,39 +1123,30 @@ hipError_t launch_err_final(const ErrFinalArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 int smooth_blocks_per_member(int n) {
-  const int cw = n < COLS_PER_TILE ? n : COLS_PER_TILE;
-  const int rh = n < ROWS_PER_TILE ? n : ROWS_PER_TILE;
-  return ((n + cw - 1) / cw) * ((n + rh - 1) / rh);
+  const int t = n < SM_TILE ? n : SM_TILE;
+  return ((n + t - 1) / t) * ((n + t - 1) / t);
 }
 
-hipError_t launch_smooth(const SmoothArgs& rows, const SmoothColArgs& cols, const MemberMaxArgs& mx,
-                         hipStream_t s) {
-  const int n = rows.n;
-  if (n > 1024 || rows.r > (MAX_TAPS - 1) / 2) return hipErrorInvalidValue;
-  const int cw = n < COLS_PER_TILE ? n : COLS_PER_TILE;
-  const int rh = n < ROWS_PER_TILE ? n : ROWS_PER_TILE;
-  const dim3 grid((n + cw - 1) / cw, (n + rh - 1) / rh, rows.nm);
-  if (SM_TILE == COLS_PER_TILE && SM_TILE == ROWS_PER_TILE) {
-    Smooth2dArgs a{};
-    a.slots = rows.slots;
-    a.desc = rows.desc;
-    a.nm = rows.nm;
-    a.n = n;
-    a.out = cols.out;
-    a.block_max = cols.block_max;
-    const int r = rows.r;
-    hipError_t e;
-    if (r == 0) e = launch_smooth2d_rc<0>(a, rows.w, r, grid, s);
-    else if (r <= 2) e = launch_smooth2d_rc<2>(a, rows.w, r, grid, s);
-    else if (r <= 4) e = launch_smooth2d_rc<4>(a, rows.w, r, grid, s);
-    else if (r <= 8) e = launch_smooth2d_rc<8>(a, rows.w, r, grid, s);
-    else if (r <= 16) e = launch_smooth2d_rc<16>(a, rows.w, r, grid, s);
-    else e = launch_smooth2d_rc<32>(a, rows.w, r, grid, s);
-    if (e != hipSuccess) return e;
-  } else {
-    hipLaunchKernelGGL(k_smooth_rows, dim3(n, rows.nm), dim3(SMOOTH_THREADS), 0, s, rows);
-    hipLaunchKernelGGL(k_smooth_cols, grid, dim3(SMOOTH_THREADS), 0, s, cols);
-  }
+hipError_t launch_smooth(const SmoothArgs& sa, const MemberMaxArgs& mx, hipStream_t s) {
+  const int n = sa.n, r = sa.r;
+  if (n > 1024 || r > (MAX_TAPS - 1) / 2) return hipErrorInvalidValue;
+  const int t = n < SM_TILE ? n : SM_TILE;
+  const dim3 grid((n + t - 1) / t, (n + t - 1) / t, sa.nm);
+  Smooth2dArgs a{};
+  a.slots = sa.slots;
+  a.desc = sa.desc;
+  a.nm = sa.nm;
+  a.n = n;
+  a.out = sa.out;
+  a.block_max = sa.block_max;
+  hipError_t e;
+  if (r == 0) e = launch_smooth2d_rc<0>(a, sa.w, r, grid, s);
+  else if (r <= 2) e = launch_smooth2d_rc<2>(a, sa.w, r, grid, s);
+  else if (r <= 4) e = launch_smooth2d_rc<4>(a, sa.w, r, grid, s);
+  else if (r <= 8) e = launch_smooth2d_rc<8>(a, sa.w, r, grid, s);
+  else if (r <= 16) e = launch_smooth2d_rc<16>(a, sa.w, r, grid, s);
+  else e = launch_smooth2d_rc<32>(a, sa.w, r, grid, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_member_max, dim3(mx.nm), dim3(256), 0, s, mx);
   return hipGetLastError();
 }
@@ -1055,8 +1154,35 @@ hipError_t launch_threshold(const ThresholdArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_threshold, dim3(blocks_for((long)a.n * a.n, 256), a.nm), dim3(256), 0, s, a);
   return hipGetLastError();
 }
+// Sizes from 96 up spread the selection over workgroups (their work area fits
+// the member's row-transform buffer); smaller ones use one workgroup per member.
+size_t topk_scratch_words(int n) {
+  if (n < 96) return 0;
+  const size_t bpm = ((size_t)n * n + TKM_KEYS - 1) / TKM_KEYS;
+  return TKM_BINS + 4 + bpm;
+}
+
 hipError_t launch_topk(const TopkArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_topk, dim3(a.nm), dim3(TOPK_THREADS), 0, s, a);
+  if (topk_scratch_words(a.n) == 0 || !a.scratch) {
+    hipLaunchKernelGGL(k_topk, dim3(a.nm), dim3(TOPK_THREADS), 0, s, a);
+    return hipGetLastError();
+  }
+  TopkMArgs t{};
+  t.a = a;
+  t.bpm = (int)(((long)a.n * a.n + TKM_KEYS - 1) / TKM_KEYS);
+  t.hist = a.scratch;
+  t.state = a.scratch + (size_t)a.nm * TKM_BINS;
+  t.ties = t.state + (size_t)a.nm * 4;
+  const dim3 grid(t.bpm, a.nm), block(TKM_THREADS);
+  hipLaunchKernelGGL(k_topkm_zero, dim3(a.nm), block, 0, s, t);
+  hipLaunchKernelGGL(k_topkm_hist<0>, grid, block, 0, s, t);
+  hipLaunchKernelGGL(k_topkm_select<0>, dim3(a.nm), block, 0, s, t);
+  hipLaunchKernelGGL(k_topkm_hist<1>, grid, block, 0, s, t);
+  hipLaunchKernelGGL(k_topkm_select<1>, dim3(a.nm), block, 0, s, t);
+  hipLaunchKernelGGL(k_topkm_hist<2>, grid, block, 0, s, t);
+  hipLaunchKernelGGL(k_topkm_select<2>, dim3(a.nm), block, 0, s, t);
+  hipLaunchKernelGGL(k_topkm_ties, grid, block, 0, s, t);
+  hipLaunchKernelGGL(k_topkm_write, grid, block, 0, s, t);
   return hipGetLastError();
 }
 hipError_t launch_stats(const StatsArgs& a, hipStream_t s) {

@@ -32,20 +32,15 @@ struct ErrFinalArgs {
   const SlotDesc* desc;  // fitness slot, sum of Xi M^2 and status word per member
 };
 
+// Shrink-wrap smoothing of |x| (Gaussian of radius r, periodic, rows then
+// columns) for nm members; also the maximum per tile (block_max).
 struct SmoothArgs {
   const int* slots;
   int nm, n, r;
   const SlotDesc* desc;
-  float* out;     // [member][n*n]
-  float w[MAX_TAPS];
-};
-
-struct SmoothColArgs {
-  int nm, n, r;
-  const float* in;
-  float* out;
-  float* block_max;  // [member][blocks per member]
-  float w[MAX_TAPS];
+  float* out;        // [member][n*n]
+  float* block_max;  // [member][tiles per member]
+  float w[MAX_TAPS]; // taps k = 0..2r
 };
 
 struct MemberMaxArgs {
@@ -71,7 +66,12 @@ struct TopkArgs {
   int alpha_index;
   double alpha_abs;
   const SlotDesc* desc;
+  // work area of at least nm * topk_scratch_words(n) words (sizes that use
+  // the multi-workgroup selection), or null
+  uint32_t* scratch;
 };
+// Words of top-k work area per member (0: the size uses one workgroup per member).
+size_t topk_scratch_words(int n);
 
 struct StatsArgs {
   int P, W, gen, gens;
@@ -204,7 +204,7 @@ struct MonitorArgs {
 int smooth_blocks_per_member(int n);
 
 hipError_t launch_err_final(const ErrFinalArgs& a, hipStream_t s);
-hipError_t launch_smooth(const SmoothArgs& rows, const SmoothColArgs& cols, const MemberMaxArgs& mx,
+hipError_t launch_smooth(const SmoothArgs& a, const MemberMaxArgs& mx,
                          hipStream_t s);
 hipError_t launch_threshold(const ThresholdArgs& a, hipStream_t s);
 hipError_t launch_topk(const TopkArgs& a, hipStream_t s);

@@ -146,18 +146,20 @@ def test_support_area(ctx, B, n, alpha):
     sh.close()
 
 
-def test_support_area_exact_ties(ctx, B):
-    # integer-valued densities: many exact ties, resolved by the lower index
-    n = 32
+@pytest.mark.parametrize("n,alpha", [(32, 200.0), (128, 200.0), (128, 9000.0), (384, 70000.0)])
+def test_support_area_exact_ties(ctx, B, n, alpha):
+    # integer-valued densities: many exact ties, resolved by the lower index;
+    # from 96 up the selection runs over many workgroups per member, and the
+    # tie group of the k-th value spans several of them
     c = Case(n, 2, seed=5)
     rng = np.random.default_rng(3)
     vals = rng.integers(0, 4, size=(2, n, n)).astype(np.complex64)
     sh, pop = c.population(ctx)
     pop.write(rho=vals)
-    run_ops(pop, B, [B.op(B.OP_SUPPORT_AREA, sigma=0.0, which=B.AREA_ABS, alpha=200.0)])
+    run_ops(pop, B, [B.op(B.OP_SUPPORT_AREA, sigma=0.0, which=B.AREA_ABS, alpha=alpha)])
     _, supp, _ = pop.read()
     for p in range(2):
-        np.testing.assert_array_equal(supp[p], mpr.update_support_size(vals[p].astype(complex), 0.0, 200.0))
+        np.testing.assert_array_equal(supp[p], mpr.update_support_size(vals[p].astype(complex), 0.0, alpha))
     pop.close()
     sh.close()
 
