@@ -86,6 +86,7 @@ struct spr_pop {
   float* maxv = nullptr;
   int* flags = nullptr;
   PopScalars* scal = nullptr;
+  int* stats_part = nullptr;  // per-workgroup support counts of STATS
   GenStatsDev* hist = nullptr;
   int hist_cap = 4096;
   float2* F = nullptr;
@@ -843,7 +844,8 @@ void run_schedule(spr_pop* pop, const spr_sched* sch, hipStream_t s) {
         break;
       case SPR_OP_STATS: {
         need_memetic(pop, "STATS");
-        StatsArgs sa{pop->P, pop->W, o.gen, o.gens, pop->table, pop->E, pop->S, pop->scal, record(pop, o.gen)};
+        StatsArgs sa{pop->P, pop->W, o.gen, o.gens, pop->table, pop->E, pop->S, pop->scal, record(pop, o.gen),
+                     pop->stats_part};
         launch_ok(launch_stats(sa, s), "stats");
         break;
       }
@@ -929,6 +931,7 @@ void destroy_pop(spr_pop* p) {
   dfree(p->maxv);
   dfree(p->flags);
   dfree(p->scal);
+  dfree(p->stats_part);
   dfree(p->hist);
   dfree(p->F);
   dfree(p->Cc);

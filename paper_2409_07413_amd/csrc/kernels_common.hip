@@ -619,47 +619,74 @@ __global__ __launch_bounds__(TKM_THREADS) void k_topkm_write(TopkMArgs t) {
 // Generation statistics of Alg. improve (parents only): best = lowest error
 // (ties to the lowest index), alpha_best, alpha_all (union), alpha_eval.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_stats(StatsArgs a) {
-  __shared__ int sh[16];
-  __shared__ int sh_best;
-  if (threadIdx.x == 0) {
-    int best = 0;
-    double be = a.E[a.table[0]];
-    for (int p = 1; p < a.P; ++p) {
-      const double e = a.E[a.table[p]];
-      if (e < be) {
-        be = e;
-        best = p;
-      }
+__host__ __device__ int stats_workgroups_of(int W) { return (W + 255) / 256; }
+// Best parent: lowest error, ties to the lowest index.
+__device__ int stats_best(const StatsArgs& a) {
+  int best = 0;
+  double be = a.E[a.table[0]];
+  for (int p = 1; p < a.P; ++p) {
+    const double e = a.E[a.table[p]];
+    if (e < be) {
+      be = e;
+      best = p;
     }
-    sh_best = best;
   }
+  return best;
+}
+
+constexpr int STATS_THREADS = 256;
+
+// Support counts over a range of words, one word per thread: the best
+// parent's bits and the union of every parent's bits.
+__global__ __launch_bounds__(STATS_THREADS) void k_stats_part(StatsArgs a) {
+  __shared__ int sh[STATS_THREADS / 64];
+  __shared__ int sh_best;
+  if (threadIdx.x == 0) sh_best = stats_best(a);
   __syncthreads();
-  const int best = sh_best;
-  const uint32_t* Sb = a.S + (size_t)a.table[best] * a.W;
+  const int w = blockIdx.x * STATS_THREADS + threadIdx.x;
   int cb = 0, ca = 0;
-  for (int w = threadIdx.x; w < a.W; w += blockDim.x) {
-    cb += __popc(Sb[w]);
+  if (w < a.W) {
+    cb = __popc(a.S[(size_t)a.table[sh_best] * a.W + w]);
     uint32_t u = 0;
-    for (int p = 0; p < a.P; ++p) u |= a.S[(size_t)a.table[p] * a.W + w];
-    ca += __popc(u);
+    int p = 0;
+    for (; p + 8 <= a.P; p += 8) {  // eight loads in flight
+      uint32_t v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = a.S[(size_t)a.table[p + q] * a.W + w];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) u |= v[q];
+    }
+    for (; p < a.P; ++p) u |= a.S[(size_t)a.table[p] * a.W + w];
+    ca = __popc(u);
   }
   cb = block_sum_int(cb, sh);
   ca = block_sum_int(ca, sh);
   if (threadIdx.x == 0) {
-    const double fr = (double)a.gen / (double)a.gens;
-    const double ev = fr * (double)cb + (1.0 - fr) * (double)ca;
-    a.scal->alpha[0] = (double)cb;
-    a.scal->alpha[1] = ev;
-    a.scal->alpha_all = (double)ca;
-    a.scal->best = best;
-    GenStatsDev* rec = a.rec;
-    rec->gen = a.gen;
-    rec->best = best;
-    rec->alpha_best = cb;
-    rec->alpha_all = ca;
-    rec->alpha_eval = ev;
+    a.part[2 * blockIdx.x] = cb;
+    a.part[2 * blockIdx.x + 1] = ca;
   }
+}
+
+__global__ __launch_bounds__(64) void k_stats(StatsArgs a) {
+  if (threadIdx.x != 0) return;
+  const int best = stats_best(a);
+  int cb = 0, ca = 0;
+  for (int b = 0; b < stats_workgroups_of(a.W); ++b) {
+    cb += a.part[2 * b];
+    ca += a.part[2 * b + 1];
+  }
+  const double fr = (double)a.gen / (double)a.gens;
+  const double ev = fr * (double)cb + (1.0 - fr) * (double)ca;
+  a.scal->alpha[0] = (double)cb;
+  a.scal->alpha[1] = ev;
+  a.scal->alpha_all = (double)ca;
+  a.scal->best = best;
+  GenStatsDev* rec = a.rec;
+  rec->gen = a.gen;
+  rec->best = best;
+  rec->alpha_best = cb;
+  rec->alpha_all = ca;
+  rec->alpha_eval = ev;
 }
 
 // Alg. select: child p replaces parent p iff E_child < E_parent (strict); the
@@ -1185,8 +1212,11 @@ hipError_t launch_topk(const TopkArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_topkm_write, grid, block, 0, s, t);
   return hipGetLastError();
 }
+int stats_workgroups(int W) { return stats_workgroups_of(W); }
+
 hipError_t launch_stats(const StatsArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(k_stats_part, dim3(stats_workgroups_of(a.W)), dim3(STATS_THREADS), 0, s, a);
+  hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_select(const SelectArgs& a, hipStream_t s) {

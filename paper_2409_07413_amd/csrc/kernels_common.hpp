@@ -80,7 +80,9 @@ struct StatsArgs {
   const uint32_t* S;
   PopScalars* scal;
   GenStatsDev* rec;
+  int* part;  // 2 * stats_workgroups(W) counts
 };
+int stats_workgroups(int W);
 
 struct SelectArgs {
   int P, gen;

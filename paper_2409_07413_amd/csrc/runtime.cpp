@@ -211,6 +211,7 @@ spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const ui
       pop->maxv = dalloc<float>(ns);
       pop->flags = dalloc<int>(1);
       pop->scal = dalloc<PopScalars>(1);
+      pop->stats_part = dalloc<int>(2 * stats_workgroups(pop->W));
       pop->hist = dalloc<GenStatsDev>(pop->hist_cap);
       std::vector<int> tbl(ns);
       for (size_t i = 0; i < ns; ++i) tbl[i] = (int)i;
