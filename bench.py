@@ -264,8 +264,9 @@ def serving_leg(ctx, B, rates, count, max_shots, budget, forms=("served", "plain
 def precision_study(ctx, B, generations=20, sample=4):
     """512^2 clustered-sphere shot, P = 64 sphere starts.  For each storage:
     the error against the FP64 oracle (exact modulus) of one RAAR step, of 20
-    ER iterations and of their Eq. error_calc fitness on `sample` members; the
-    throughput of MPR generations; and a full MPR run (`generations` x 100
+    ER iterations and of their Eq. error_calc fitness on `sample` members;
+    steady-state RAAR-only and ER-only throughput (64 members, 2000
+    iterations, no shrink-wrap); the throughput of MPR generations; and a full MPR run (`generations` x 100
     iterations) whose final best density and fitness are compared between the
     two storages, beside the divergence of two FP32 runs whose starts differ by
     FP32 rounding (how far any FP32 evaluation can drift on this trajectory)."""
@@ -298,6 +299,22 @@ def precision_study(ctx, B, generations=20, sample=4):
         rho, _, err = pop.read()
         rec["er20_rel_l2_max"] = max(rel(rho[p], ref_er[p]) for p in range(sample))
         rec["er20_fitness_rel_max"] = max(abs(err[p] - ref_e[p]) / ref_e[p] for p in range(sample))
+        pop.close()
+        # steady-state microbenchmarks: RAAR-only and ER-only, 64 members, no
+        # shrink-wrap, 2000 iterations (one launch chunk: the two work buffers
+        # fit the memory-side cache)
+        pop = shot.population(rho0[:64], supp0)
+        b_m = 2.0 if fp16 else 4.0
+        for alg, op, bpp in (("raar", B.OP_RAAR, 40.125), ("er", B.OP_ER, 32.125)):
+            pop.run(B.sched_ops([B.op(op, count=20, beta=0.9, chi=0.5)], ctx))
+            pop.sync()
+            t0 = time.perf_counter()
+            pop.run(B.sched_ops([B.op(op, count=2000, beta=0.9, chi=0.5)], ctx))
+            pop.sync()
+            dt = time.perf_counter() - t0
+            mit = 64 * 2000 / dt
+            rec[f"{alg}2000_member_iterations_per_s"] = mit
+            rec[f"{alg}2000_pct_hbm_peak"] = mit * (bpp + b_m / 64) * N * N / (HBM_PEAK_GBS * 1e9)
         pop.close()
         # full MPR run from the same starts
         runs = [("main", rho0)]
@@ -640,6 +657,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of 256 MiB (reference for HBM counters) and exit")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--timing-every", type=int, default=8,
+                    help="inside the timed region, HIP events around one launch in every N of each loop kernel")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving leg (one JSON line per rate on stderr, summary on stdout)")
     ap.add_argument("--serve-rates", type=str, default="50,5",
@@ -757,6 +776,9 @@ def main():
     # timed region: K generations; HIP events around the launches of the two
     # projection-loop kernels (k_col_proj; k_row_update, ER and HIO/RAAR forms),
     # which run in every iteration, on the launch stream
+    # (one launch in every args.timing_every of each, so that the events cost
+    # little of the measured throughput)
+    pop.timing_sample(args.timing_every)
     pop.timing(True, kernels=[B.KERNEL_COL_PROJ, B.KERNEL_ROW_UPDATE_ER, B.KERNEL_ROW_UPDATE_IA])
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -775,6 +797,7 @@ def main():
     n_l, ms = n_er + n_ia, ms_er + ms_ia
 
     # one more generation with every iteration kernel timed (breakdown only)
+    pop.timing_sample(1)
     pop.timing(True)
     pop.run(scheds[total], stream)
     pop.sync()
@@ -796,14 +819,15 @@ def main():
     roof_row = {"bound": "hbm", "kernel": "k_row_update", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": traffic, "launches": n_l, "avg_launch_us": ms / n_l * 1e3,
-                "total_ms": ms, "algorithmic_bytes_per_launch": bytes_per_launch,
-                "launch_mix": {"ER": n_er, "HIO/RAAR": n_ia}}
+                "timed_ms": ms, "algorithmic_bytes_per_launch": bytes_per_launch,
+                "launch_mix": {"ER": n_er, "HIO/RAAR": n_ia}, "sample_every": args.timing_every}
     cp_bytes = algorithmic_bytes_per_px(B.KERNEL_COL_PROJ, chunk) * N * N * chunk
     cp_achieved = cp_bytes / (ms_cp / n_cp * 1e-3) / 1e9
     roof_col = {"bound": "hbm", "kernel": "k_col_proj", "achieved": cp_achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": cp_achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic(B.KERNEL_COL_PROJ, chunk), "launches": n_cp,
-                "avg_launch_us": ms_cp / n_cp * 1e3, "total_ms": ms_cp, "algorithmic_bytes_per_launch": cp_bytes}
+                "avg_launch_us": ms_cp / n_cp * 1e3, "timed_ms": ms_cp, "algorithmic_bytes_per_launch": cp_bytes,
+                "sample_every": args.timing_every}
     # the dominant kernel: the larger share of event-timed time in the timed region
     roofline = roof_row if ms >= ms_cp else roof_col
     # whole-step algorithmic bytes: iterations only (ingest/shrink-wrap/fitness/crossover excluded)

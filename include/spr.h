@@ -346,6 +346,10 @@ spr_status spr_read_xover(spr_pop* pop, spr_xover_info* out, int32_t max_n);
 #define SPR_KERNEL_COUNT 4
 #define SPR_TIMING_ALL 0xF
 spr_status spr_timing_enable(spr_pop* pop, int32_t mask);
+/* Time only the first of every `every` (>= 1, default 1) launches of each    */
+/* selected kernel, so that the events cost little beside the kernels; the   */
+/* counts of spr_timing_read are then the timed launches.  Resets the totals. */
+spr_status spr_timing_sample(spr_pop* pop, int32_t every);
 spr_status spr_timing_read(spr_pop* pop, int32_t kernel, int64_t* launches, double* total_ms);
 
 /* Unitary 2D DFT of `batch` N x N complex images (device pointers, in != out */

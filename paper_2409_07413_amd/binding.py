@@ -133,7 +133,7 @@ EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_suppo
            "spr_shot_create", "spr_shot_destroy", "spr_pop_create", "spr_pop_destroy", "spr_pop_write",
            "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
            "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
-           "spr_timing_enable", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch",
+           "spr_timing_enable", "spr_timing_sample", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch",
            "spr_read_member", "spr_read_average", "spr_read_monitor", "spr_pop_init_spheres", "spr_shot_set_bounds", "spr_size_variants", "spr_ctx_autotune", "spr_ctx_set_variant",
            "spr_ctx_get_tuning", "spr_graph_create", "spr_graph_create_batch", "spr_graph_launch",
            "spr_graph_destroy", "spr_server_create", "spr_server_submit", "spr_server_poll", "spr_server_step", "spr_server_drain",
@@ -170,6 +170,7 @@ def _proto(lib):
         "spr_read_xover": (i32, [vp, C.POINTER(XoverInfo), i32]),
         "spr_fft2": (i32, [vp, i32, i32, vp, vp, i32, vp]),
         "spr_timing_enable": (i32, [vp, i32]),
+        "spr_timing_sample": (i32, [vp, i32]),
         "spr_timing_read": (i32, [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
         "spr_ctx_set_cache_budget": (i32, [vp, C.c_uint64]),
         "spr_run_batch": (i32, [vp, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), i32, vp]),
@@ -606,6 +607,10 @@ class Population:
         if enable:
             mask = 0xF if kernels is None else sum(1 << k for k in kernels)
         self.ctx._check(self.ctx.lib.spr_timing_enable(self.h, mask))
+
+    def timing_sample(self, every):
+        """Time one launch in every `every` of each selected kernel (resets the totals)."""
+        self.ctx._check(self.ctx.lib.spr_timing_sample(self.h, int(every)))
 
     def timing_read(self, kernel):
         """(launches, total event milliseconds) of one kernel since timing was enabled."""

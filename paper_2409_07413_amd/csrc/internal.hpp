@@ -117,6 +117,8 @@ struct spr_pop {
   hipEvent_t done = nullptr;  // recorded after the population's latest enqueued work
   // optional per-kernel timing: HIP events recorded around each launch
   uint32_t timing = 0;  // bit k: time kernel k
+  int timing_every = 1;  // time one launch in every timing_every of each kernel
+  int64_t timing_seen[SPR_KERNEL_COUNT] = {};
   struct Stamp {
     int kernel;
     hipEvent_t start, stop;
@@ -395,7 +397,7 @@ hipEvent_t pooled_event(spr_pop* pop) {
 // Launch through `fn`, bracketing it with events when timing is enabled.
 template <class Fn>
 void timed(spr_pop* pop, int kernel, hipStream_t s, const char* what, Fn&& fn) {
-  if (!(pop->timing & (1u << kernel))) {
+  if (!(pop->timing & (1u << kernel)) || pop->timing_seen[kernel]++ % pop->timing_every != 0) {
     launch_ok(fn(), what);
     return;
   }

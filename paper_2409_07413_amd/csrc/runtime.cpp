@@ -776,6 +776,21 @@ spr_status spr_timing_enable(spr_pop* pop, int32_t enable) {
     for (int k = 0; k < SPR_KERNEL_COUNT; ++k) {
       pop->kernel_ms[k] = 0.0;
       pop->kernel_launches[k] = 0;
+      pop->timing_seen[k] = 0;
+    }
+  });
+}
+
+spr_status spr_timing_sample(spr_pop* pop, int32_t every) {
+  if (!pop || every < 1 || !live_has(pop)) return SPR_E_INVALID_ARG;
+  return guarded(pop->ctx, [&] {
+    use_device(pop->ctx);
+    sync_pop(pop);
+    pop->timing_every = every;
+    for (int k = 0; k < SPR_KERNEL_COUNT; ++k) {
+      pop->kernel_ms[k] = 0.0;
+      pop->kernel_launches[k] = 0;
+      pop->timing_seen[k] = 0;
     }
   });
 }

@@ -472,3 +472,24 @@ def test_invalid_inputs_are_rejected(ctx, B):
     assert e.value.code == -6
     pop.close()
     sh.close()
+
+
+def test_launch_timing_counts_and_sampling(ctx, B):
+    # every launch timed, then one in every 4: counts follow the schedule
+    c = Case(64, 3, seed=21)
+    sh, pop = c.population(ctx)
+    sched = B.sched_ops([B.op(B.OP_RAAR, count=6, beta=0.9, chi=0.5), B.op(B.OP_ER, count=6, chi=0.5)], ctx)
+    pop.timing(True)
+    pop.run(sched)
+    n_col, ms_col = pop.timing_read(B.KERNEL_COL_PROJ)
+    n_ia, _ = pop.timing_read(B.KERNEL_ROW_UPDATE_IA)
+    n_er, _ = pop.timing_read(B.KERNEL_ROW_UPDATE_ER)
+    assert (n_col, n_ia + n_er) == (12, 12) and ms_col > 0
+    pop.timing_sample(4)
+    pop.timing(True)
+    pop.run(sched)
+    assert pop.timing_read(B.KERNEL_COL_PROJ)[0] == 3
+    with pytest.raises(B.SprError):
+        pop.timing_sample(0)
+    pop.close()
+    sh.close()
