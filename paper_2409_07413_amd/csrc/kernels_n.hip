@@ -90,9 +90,6 @@ __device__ __forceinline__ float2 gload(const float2* p, size_t i) {
   return make_float2(v.x, v.y);
 }
 
-__device__ __forceinline__ bool bit_at(const uint32_t* __restrict__ S, int idx) {
-  return (S[idx >> 5] >> (idx & 31)) & 1u;
-}
 
 // Nearest point of {|arg z| <= chi pi} (positivity: Re z >= 0 exactly).
 // The real-space arithmetic below spells out every rounding (__fmul_rn,
@@ -242,17 +239,7 @@ __global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
 // ---------------------------------------------------------------------------
 // Column projection: column FFT -> masked P_M -> column IFFT.
 // ---------------------------------------------------------------------------
-#ifdef SPR_ROW_WPE
-#define SPR_ROW_OCC __attribute__((amdgpu_waves_per_eu(SPR_ROW_WPE)))
-#else
-#define SPR_ROW_OCC
-#endif
-#ifdef SPR_COL_WPE
-#define SPR_COL_OCC __attribute__((amdgpu_waves_per_eu(SPR_COL_WPE)))
-#else
-#define SPR_COL_OCC
-#endif
-__global__ __launch_bounds__(C* T) SPR_COL_OCC void k_col_proj(ColProjArgs a) {
+__global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const int c = tid % C, t = tid / C;
@@ -287,7 +274,7 @@ __global__ __launch_bounds__(C* T) SPR_COL_OCC void k_col_proj(ColProjArgs a) {
 // ER, HIO and RAAR compiled alone, which frees the registers of the paths a
 // uniform launch never takes.
 template <int SPEC>
-__global__ __launch_bounds__(RW* T) SPR_ROW_OCC void k_row_update(RowUpdateArgs a) {
+__global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
   const int r = tid / T, t = tid % T;
