@@ -434,14 +434,18 @@ def test_mpr_one_generation_small(ctx, B):
 # Full-size launch configuration of the benchmark: 512^2, P = 64 memetic
 # (128 members), sampled members checked against the oracle one by one.
 # ---------------------------------------------------------------------------
-def test_full_size_sampled(ctx, B):
-    n, P = 512, 64
-    c = Case(n, P, seed=1004, kind="spheres", photons=1e8, gap=4, side=180)
-    sh, pop = c.population(ctx, memetic=True, seed=3004)
+@pytest.mark.parametrize("n,seed,sample", [(512, 1004, (0, 37, 63)), (1024, 1002, (0, 63))])
+def test_full_size_sampled(ctx, B, n, seed, sample):
+    # 512^2 is the benchmark's shot, 1024^2 the large MPR shot; P = 64 memetic
+    # (128 members), launched in the benchmark's member chunks
+    P = 64
+    c = Case(n, P, seed=seed, kind="spheres", photons=1e8, gap=4, side=180)
+    ctx.set_cache_budget(256 << 20)
+    sh, pop = c.population(ctx, memetic=True, seed=seed + 2000)
     run_ops(pop, B, [B.op(B.OP_RAAR, count=1, beta=0.9, chi=0.5), B.op(B.OP_ER, count=1, chi=0.5),
                      B.op(B.OP_GET_ERROR, scope=B.SCOPE_PARENTS)])
     rho, _, err = pop.read()
-    for p in (0, 37, 63):
+    for p in sample:
         ref = mpr.sequence(c.rho[p], c.S[p], c.M, c.known, 0.5, "RAAR", 0.9, 1, 1)
         assert rel(rho[p], ref) <= 1e-5
         e_ref = mpr.get_error(ref, c.S[p], c.M, c.known)
