@@ -602,7 +602,7 @@ class HipExec : public Exec {
           launches += 3;
         } else if (kind == STEP_AREA) {
           support_area(g, sigma, nullptr, 0, alpha, s_);
-          launches += 3;
+          launches += 2 + (topk_scratch_words(n) ? 9 : 1);  // smoothing, then the selection
         } else {
           get_error(g, s_);
           launches += 3;
