@@ -295,21 +295,34 @@ __global__ __launch_bounds__(256) void k_member_max(MemberMaxArgs a) {
 }
 
 // S' = {a_sigma > tau * max a_sigma}, compared in double; unchanged if max = 0.
-// One thread per pixel; a wavefront covers 64 consecutive pixels = 2 words.
+// One thread per four pixels; eight lanes form one support word.
 __global__ __launch_bounds__(256) void k_threshold(ThresholdArgs a) {
   const long nn = (long)a.n * a.n;
   const int m = blockIdx.y;
-  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long p0 = ((long)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   const float mx = a.maxv[m];
   if (!(mx > 0.f)) return;  // uniform over the workgroup
   const double thr = a.tau * (double)mx;
-  const bool bit = p < nn && (double)a.in[(size_t)m * nn + p] > thr;
-  const unsigned long long b = __ballot(bit);
+  const float* in = a.in + (size_t)m * nn;
+  float v[4];
+  if (p0 + 4 <= nn) {
+    const float4 q = *reinterpret_cast<const float4*>(in + p0);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+  } else {
+    for (int j = 0; j < 4; ++j) v[j] = p0 + j < nn ? in[p0 + j] : 0.f;
+  }
+  uint32_t nib = 0;
+  for (int j = 0; j < 4; ++j) nib |= (p0 + j < nn && (double)v[j] > thr ? 1u : 0u) << j;
   const int lane = threadIdx.x & 63;
-  const long w0 = (p - lane) >> 5;  // first word of this wavefront
-  uint32_t* Sm = a.desc[a.slots[m]].S;
-  if (lane == 0 && w0 < a.W) Sm[w0] = (uint32_t)b;
-  if (lane == 1 && w0 + 1 < a.W) Sm[w0 + 1] = (uint32_t)(b >> 32);
+  uint32_t word = nib << (4 * (lane & 7));
+  word |= __shfl_xor(word, 1, 64);
+  word |= __shfl_xor(word, 2, 64);
+  word |= __shfl_xor(word, 4, 64);
+  const long wi = p0 >> 5;
+  if ((lane & 7) == 0 && wi < a.W) a.desc[a.slots[m]].S[wi] = word;
 }
 
 // ---------------------------------------------------------------------------
@@ -807,6 +820,27 @@ __global__ void k_support_mix(SupportMixArgs a) {
     al[k] = a.align[3 * p + k];
   }
   const uint32_t* Sp = a.S + (size_t)a.table[p] * a.W;
+  if (a.n % 32 == 0) {
+    // the word's 32 pixels lie in one row; each aligned support supplies a
+    // 32-bit window of one of its rows (reversed for the twin)
+    const int n = a.n, wr = n / 32;
+    const int yr = (int)(((long)w * 32) / n), yc0 = (int)(((long)w * 32) % n);
+    uint32_t s[3];
+    for (int k = 0; k < 3; ++k) {
+      const bool twin = al[k].twin;
+      int sr = twin ? al[k].dr - yr : yr - al[k].dr;
+      sr = ((sr % n) + n) % n;
+      int c0 = twin ? al[k].dc - yc0 - 31 : yc0 - al[k].dc;
+      c0 = ((c0 % n) + n) % n;
+      const uint32_t* row = Sq[k] + (size_t)sr * wr;
+      const int i = c0 >> 5, o = c0 & 31;
+      const uint32_t lo = row[i], hi = row[(i + 1) % wr];
+      const uint32_t win = o ? (lo >> o) | (hi << (32 - o)) : lo;
+      s[k] = twin ? __builtin_bitreverse32(win) : win;
+    }
+    a.S[(size_t)a.table[a.P + p] * a.W + w] = s[0] | (s[1] & s[2] & Sp[w]);
+    return;
+  }
   uint32_t bits = 0;
   for (int b = 0; b < 32; ++b) {
     const long idx = (long)w * 32 + b;
@@ -1178,7 +1212,7 @@ hipError_t launch_smooth(const SmoothArgs& sa, const MemberMaxArgs& mx, hipStrea
   return hipGetLastError();
 }
 hipError_t launch_threshold(const ThresholdArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_threshold, dim3(blocks_for((long)a.n * a.n, 256), a.nm), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_threshold, dim3(blocks_for(((long)a.n * a.n + 3) / 4, 256), a.nm), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 // Sizes from 96 up spread the selection over workgroups (their work area fits
