@@ -772,17 +772,29 @@ __device__ __forceinline__ bool better_rec(const ArgmaxRec& x, const ArgmaxRec& 
   return x.val > y.val || (x.val == y.val && x.idx < y.idx);
 }
 
-__global__ void k_align(AlignArgs a) {
-  const int pair = blockIdx.x * blockDim.x + threadIdx.x;
-  if (pair >= a.npairs) return;
-  ArgmaxRec b[2];
-  for (int tw = 0; tw < 2; ++tw) {
-    const ArgmaxRec* src = a.partial + (size_t)(2 * pair + tw) * a.blocks;
-    ArgmaxRec best = src[0];
-    for (int i = 1; i < a.blocks; ++i)
-      if (better_rec(src[i], best)) best = src[i];
-    b[tw] = best;
+// One wavefront per pair: each lane takes a stride of the row partials, then
+// a butterfly reduction under the same order (larger value, then lower index).
+__device__ ArgmaxRec wave_best(const ArgmaxRec* src, int count) {
+  const int lane = threadIdx.x & 63;
+  ArgmaxRec best = src[0];
+  for (int i = lane; i < count; i += 64)
+    if (better_rec(src[i], best)) best = src[i];
+  for (int o = 32; o > 0; o >>= 1) {
+    ArgmaxRec other;
+    other.val = __shfl_xor(best.val, o, 64);
+    other.idx = __shfl_xor(best.idx, o, 64);
+    other.re = __shfl_xor(best.re, o, 64);
+    other.im = __shfl_xor(best.im, o, 64);
+    if (better_rec(other, best)) best = other;
   }
+  return best;
+}
+
+__global__ __launch_bounds__(64) void k_align(AlignArgs a) {
+  const int pair = blockIdx.x;
+  ArgmaxRec b[2];
+  for (int tw = 0; tw < 2; ++tw) b[tw] = wave_best(a.partial + (size_t)(2 * pair + tw) * a.blocks, a.blocks);
+  if (threadIdx.x != 0) return;
   const int twin = b[1].val > b[0].val ? 1 : 0;
   const ArgmaxRec& c = b[twin];
   AlignRec r;
@@ -1262,7 +1274,7 @@ hipError_t launch_choice(const ChoiceArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_align(const AlignArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_align, dim3(blocks_for(a.npairs, 64)), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_align, dim3(a.npairs), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_support_mix(const SupportMixArgs& a, hipStream_t s) {
