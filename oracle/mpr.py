@@ -290,6 +290,30 @@ def sequence(x, S, M, known, chi, alg, beta, n_ia, n_er):
     return x
 
 
+def fourier_error(x, M, known):
+    """The measure of Eq. error_calc applied to an iterate without its support:
+    sqrt(sum Xi (|F[x]| - M)^2 / sum Xi M^2), the distance of F[x] from the
+    measured moduli relative to their norm (the per-iteration trace)."""
+    den = float(np.sum(M[known] ** 2))
+    A = np.abs(fft2(x))
+    return float(np.sqrt(np.sum((A[known] - M[known]) ** 2) / den))
+
+
+def sequence_trace(x, S, M, known, chi, alg, beta, n_ia, n_er):
+    """Eq. sequence, recording before every iteration the Fourier error of the
+    density whose spectrum that iteration projects: x for the HIO/RAAR steps,
+    P_C x for the ER steps.  Returns (final x, list of errors)."""
+    step = {"HIO": hio, "RAAR": raar}[alg]
+    errs = []
+    for _ in range(n_ia):
+        errs.append(fourier_error(x, M, known))
+        x = step(x, S, M, known, chi, beta)
+    for _ in range(n_er):
+        errs.append(fourier_error(proj_constraint(x, S, chi), M, known))
+        x = er(x, S, M, known, chi)
+    return x, errs
+
+
 def schedule_at(g, G, j, j_er, j_end, sigma, sigma_end, tau, tau_end):
     """Linear parameter changes over generations (appendix "changing values").
 
