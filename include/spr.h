@@ -192,6 +192,12 @@ spr_status spr_pop_write(spr_pop* pop, const float* rho, const uint8_t* supp, co
 #define SPR_OP_AVERAGE 10     /* Alg. mpr's Average of the parents (Eq. avgrec), members aligned */
                               /* to the best one; also the average modulus used when c_a > 0    */
 #define SPR_OP_MONITOR 11     /* indicators of the parents for generation gen (spr_read_monitor) */
+/* ER/HIO/RAAR flag (spr_op.which): record, for every iteration of the op, the */
+/* Fourier error sqrt(sum Xi (|X| - M)^2 / sum Xi M^2) of the spectrum X that  */
+/* the iteration projects (Eq. error_calc's measure applied to the iterate,    */
+/* x for HIO/RAAR, P_C x for ER), summed in FP64 inside the column pass.       */
+/* Single populations only (spr_run, population graphs).                       */
+#define SPR_ITER_TRACE 1
 
 #define SPR_ALG_HIO 1
 #define SPR_ALG_RAAR 2
@@ -208,7 +214,7 @@ typedef struct spr_op {
   int32_t kind;   /* SPR_OP_* */
   int32_t count;  /* ER/HIO/RAAR: iterations */
   int32_t scope;  /* SPR_SCOPE_* (iterations, support updates, GET_ERROR) */
-  int32_t which;  /* SUPPORT_AREA: SPR_AREA_* */
+  int32_t which;  /* SUPPORT_AREA: SPR_AREA_*; ER/HIO/RAAR: 0 or SPR_ITER_TRACE */
   int32_t gen;    /* STATS/CROSSOVER/SELECT: generation g (1-based, absolute) */
   int32_t gens;   /* STATS: total generations G */
   int32_t t_min;  /* CROSSOVER: tile side range [t_min, t_max] */
@@ -318,6 +324,12 @@ typedef struct spr_monitor {
 } spr_monitor;
 /* Monitor records, oldest first; at most max_n; *n_out gets the count. */
 spr_status spr_read_monitor(spr_pop* pop, spr_monitor* out, int32_t max_n, int32_t* n_out);
+/* Traced iterations of the last run (SPR_ITER_TRACE): *rows traced iterations  */
+/* in schedule order, each a row of *cols values (one per slot position: the  */
+/* P parents, then the P children of a memetic population; NaN where the      */
+/* iteration's scope left the member out).  out holds max_rows * cols doubles */
+/* (host memory); rows beyond max_rows are not copied.                         */
+spr_status spr_read_trace(spr_pop* pop, double* out, int32_t max_rows, int32_t* rows, int32_t* cols);
 /* Generation records, oldest first; at most max_n; *n_out gets the count. */
 spr_status spr_read_stats(spr_pop* pop, spr_gen_stats* out, int32_t max_n, int32_t* n_out);
 

@@ -30,6 +30,7 @@ READ_CHILDREN = 0x8
 INIT_RANDOM_PHASE = 0x10
 AMP_FP16 = 0x20
 
+ITER_TRACE = 1
 OP_ER, OP_HIO, OP_RAAR, OP_SHRINKWRAP, OP_SUPPORT_AREA, OP_GET_ERROR, OP_STATS, OP_CROSSOVER, OP_SELECT, OP_AVERAGE, \
     OP_MONITOR = range(1, 12)
 ALG_HIO, ALG_RAAR = 1, 2
@@ -134,7 +135,7 @@ EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_suppo
            "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
            "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
            "spr_timing_enable", "spr_timing_sample", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch",
-           "spr_read_member", "spr_read_average", "spr_read_monitor", "spr_pop_init_spheres", "spr_shot_set_bounds", "spr_size_variants", "spr_ctx_autotune", "spr_ctx_set_variant",
+           "spr_read_member", "spr_read_average", "spr_read_monitor", "spr_read_trace", "spr_pop_init_spheres", "spr_shot_set_bounds", "spr_size_variants", "spr_ctx_autotune", "spr_ctx_set_variant",
            "spr_ctx_get_tuning", "spr_graph_create", "spr_graph_create_batch", "spr_graph_launch",
            "spr_graph_destroy", "spr_server_create", "spr_server_submit", "spr_server_poll", "spr_server_step", "spr_server_drain",
            "spr_server_stats_get", "spr_server_last_error", "spr_server_destroy"]
@@ -177,6 +178,7 @@ def _proto(lib):
         "spr_read_member": (i32, [vp, i32, vp, vp, u32]),
         "spr_read_average": (i32, [vp, vp, vp, vp, u32]),
         "spr_read_monitor": (i32, [vp, C.POINTER(Monitor), i32, C.POINTER(i32)]),
+        "spr_read_trace": (i32, [vp, vp, i32, C.POINTER(i32), C.POINTER(i32)]),
         "spr_pop_init_spheres": (i32, [vp, C.POINTER(SphereParams)]),
         "spr_shot_set_bounds": (i32, [vp, C.c_double, C.c_double, C.POINTER(i32)]),
         "spr_size_variants": (i32, [i32]),
@@ -538,6 +540,16 @@ class Population:
         n = C.c_int32()
         self.ctx._check(self.ctx.lib.spr_read_monitor(self.h, arr, max_n, C.byref(n)))
         return [{k: getattr(arr[i], k) for k, _ in Monitor._fields_ if k != "pad"} for i in range(n.value)]
+
+    def trace(self, max_rows=100000):
+        """Fourier errors of the traced iterations of the last run: (rows, slots) float64."""
+        rows, cols = C.c_int32(), C.c_int32()
+        self.ctx._check(self.ctx.lib.spr_read_trace(self.h, None, 0, C.byref(rows), C.byref(cols)))
+        k = min(rows.value, max_rows)
+        out = np.empty((k, cols.value), dtype=np.float64)
+        if k:
+            self.ctx._check(self.ctx.lib.spr_read_trace(self.h, out.ctypes.data, k, C.byref(rows), C.byref(cols)))
+        return out
 
     def init_spheres(self, sigma_init, n_init=5, diam=(0.2, 0.9), phase=(0.0, 0.0), gamma=1.0,
                      set_support=True):

@@ -80,6 +80,7 @@ struct ColProjArgs {
   const float2* T;       // row-FFT'd iterate [member][N*N]
   float2* Y;             // out: column-IFFT of the projected spectrum [member][N*N]
   const float2* tw;
+  double* trace_partial; // null, or out: FP64 sums of Xi (|X| - M)^2 per [member][column tile]
 };
 
 struct RowUpdateArgs {

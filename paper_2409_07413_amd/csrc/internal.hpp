@@ -87,6 +87,10 @@ struct spr_pop {
   int* flags = nullptr;
   PopScalars* scal = nullptr;
   int* stats_part = nullptr;  // per-workgroup support counts of STATS
+  // per-iteration Fourier error of traced iterations: [row][slot position]
+  double* trace = nullptr;
+  int trace_cap = 0;   // rows allocated
+  int trace_rows = 0;  // rows written by the last run
   GenStatsDev* hist = nullptr;
   int hist_cap = 4096;
   float2* F = nullptr;
@@ -425,6 +429,7 @@ struct Iter {
   int alg;
   float beta;
   double chi;
+  bool trace = false;  // record the Fourier error of the spectrum this iteration projects
 };
 
 // A launch group: members of one size reached through slot descriptors, and
@@ -446,6 +451,9 @@ struct Group {
   spr_pop* timing = nullptr;     // where launch timings are kept (may be null)
   int chunk = 0;                 // members per iteration launch
   int t_by_slot = 0;             // row transforms in each member's own buffer (desc.T)
+  double* trace = nullptr;       // trace rows of the population (traced iterations only)
+  int trace_cols = 0;            // slot positions per trace row
+  int pos0 = 0;                  // slot position of slots[0]
 };
 
 int chunk_for(spr_ctx* ctx, int n, int nm) {
@@ -474,6 +482,9 @@ Group pop_group(spr_pop* pop, int scope) {
   g.flags = pop->flags;
   g.timing = pop;
   g.chunk = chunk_for(pop->ctx, pop->n, sc.nm);
+  g.trace = pop->trace;
+  g.trace_cols = pop->nslots;
+  g.pos0 = scope == SPR_SCOPE_CHILDREN ? pop->P : 0;
   return g;
 }
 
@@ -485,15 +496,25 @@ void launch_timed(spr_pop* tp, int kernel, hipStream_t s, const char* what, Fn&&
 
 // One Sequence over members slots[0..nm): ingest, then per iteration a column
 // pass and a row pass.
-void run_iterations_on(const Group& g, const std::vector<Iter>& its, const int* slots, int nm, hipStream_t s) {
+void run_iterations_on(const Group& g, const std::vector<Iter>& its, int c0, int nm, int trace_row0,
+                       hipStream_t s) {
+  const int* slots = g.slots + c0;
   const SizeKernels* K = g.K;
   const float2* tw = twiddles(g.ctx, g.n);
   RowIngestArgs ia{slots, nm, g.desc, g.T, g.W, g.t_by_slot,
                    its[0].alg == ALG_ER ? INGEST_PC : INGEST_PLAIN, phase_of(its[0].chi), tw};
   launch_timed(g.timing, SPR_KERNEL_ROW_INGEST, s, "row_ingest", [&] { return K->row_ingest(ia, s); });
+  int trace_row = trace_row0;
   for (size_t i = 0; i < its.size(); ++i) {
-    ColProjArgs ca{slots, nm, g.desc, g.t_by_slot, g.T, g.Y, tw};
+    ColProjArgs ca{slots, nm, g.desc, g.t_by_slot, g.T, g.Y, tw, its[i].trace ? g.err_partial : nullptr};
     launch_timed(g.timing, SPR_KERNEL_COL_PROJ, s, "col_proj", [&] { return K->col_proj(ca, s); });
+    if (its[i].trace) {
+      if (!g.trace) fail(SPR_E_INVALID_ARG, "iteration traces are recorded for single populations only");
+      TraceFinalArgs ta{g.err_partial, g.n / K->C, nm, slots, g.desc,
+                        g.trace + (size_t)trace_row * g.trace_cols, g.pos0 + c0};
+      launch_ok(launch_trace_final(ta, s), "trace_final");
+      ++trace_row;
+    }
     const bool last = i + 1 == its.size();
     RowUpdateArgs ra;
     ra.slots = slots;
@@ -518,10 +539,26 @@ void run_iterations_on(const Group& g, const std::vector<Iter>& its, const int* 
 // Members are independent inside a Sequence, so the run may proceed chunk by
 // chunk; with a cache budget the chunk's buffers stay cache-resident across
 // its iterations.
-void run_iterations(const Group& g, const std::vector<Iter>& its, hipStream_t s) {
+void run_iterations(const Group& g, const std::vector<Iter>& its, hipStream_t s, int trace_row0 = 0) {
   if (its.empty() || g.nm == 0) return;
   const int chunk = g.chunk > 0 ? g.chunk : g.nm;
-  for (int c0 = 0; c0 < g.nm; c0 += chunk) run_iterations_on(g, its, g.slots + c0, std::min(chunk, g.nm - c0), s);
+  for (int c0 = 0; c0 < g.nm; c0 += chunk) run_iterations_on(g, its, c0, std::min(chunk, g.nm - c0), trace_row0, s);
+}
+
+int traced_iterations(const spr_sched* sch) {
+  int rows = 0;
+  for (const auto& o : sch->ops)
+    if ((o.kind == SPR_OP_ER || o.kind == SPR_OP_HIO || o.kind == SPR_OP_RAAR) && (o.which & SPR_ITER_TRACE))
+      rows += o.count;
+  return rows;
+}
+
+void trace_buffers(spr_pop* pop, int rows) {
+  if (rows <= pop->trace_cap) return;
+  double* t = dalloc<double>((size_t)rows * pop->nslots);
+  dfree(pop->trace);
+  pop->trace = t;
+  pop->trace_cap = rows;
 }
 
 void smooth(const Group& g, double sigma, hipStream_t s) {
@@ -771,6 +808,7 @@ void validate_op(const spr_op& o) {
     case SPR_OP_HIO:
     case SPR_OP_RAAR:
       if (o.count < 0) fail(SPR_E_INVALID_ARG, "negative iteration count");
+      if (o.which & ~SPR_ITER_TRACE) fail(SPR_E_INVALID_ARG, "unknown iteration flags");
       if (o.kind != SPR_OP_ER && !(o.beta > 0.0 && o.beta <= 1.0)) fail(SPR_E_INVALID_ARG, "beta outside (0, 1]");
       break;
     case SPR_OP_SHRINKWRAP:
@@ -813,6 +851,15 @@ void run_schedule(spr_pop* pop, const spr_sched* sch, hipStream_t s) {
       fail(SPR_E_INVALID_ARG, "schedule needs a population created with SPR_POP_MEMETIC");
     if (o.kind == SPR_OP_CROSSOVER && pop->P < 4) fail(SPR_E_INVALID_ARG, "crossover needs P >= 4");
   }
+  // traced iterations: one row per traced iteration, NaN where a slot is not traced
+  const int rows = traced_iterations(sch);
+  if (rows > 0) {
+    trace_buffers(pop, rows);
+    FillArgs fa{pop->trace, (long)rows * pop->nslots, std::numeric_limits<double>::quiet_NaN()};
+    launch_ok(launch_fill(fa, s), "fill");
+    pop->trace_rows = rows;
+  }
+  int trace_row = 0;
   size_t i = 0;
   while (i < ops.size()) {
     const spr_op& o = ops[i];
@@ -824,10 +871,13 @@ void run_schedule(spr_pop* pop, const spr_sched* sch, hipStream_t s) {
              ops[i].scope == scope) {
         const spr_op& q = ops[i];
         const int alg = q.kind == SPR_OP_ER ? ALG_ER : (q.kind == SPR_OP_HIO ? ALG_HIO : ALG_RAAR);
-        for (int c = 0; c < q.count; ++c) its.push_back({alg, (float)q.beta, q.chi});
+        for (int c = 0; c < q.count; ++c) its.push_back({alg, (float)q.beta, q.chi, (q.which & SPR_ITER_TRACE) != 0});
         ++i;
       }
-      run_iterations(pop_group(pop, scope), its, s);
+      int traced = 0;
+      for (const auto& it : its) traced += it.trace ? 1 : 0;
+      run_iterations(pop_group(pop, scope), its, s, trace_row);
+      trace_row += traced;
       continue;
     }
     switch (o.kind) {
@@ -934,6 +984,7 @@ void destroy_pop(spr_pop* p) {
   dfree(p->flags);
   dfree(p->scal);
   dfree(p->stats_part);
+  dfree(p->trace);
   dfree(p->hist);
   dfree(p->F);
   dfree(p->Cc);
@@ -997,6 +1048,8 @@ void run_group_schedule(const Group& g, const spr_sched* sch, hipStream_t s) {
       while (i < ops.size() &&
              (ops[i].kind == SPR_OP_ER || ops[i].kind == SPR_OP_HIO || ops[i].kind == SPR_OP_RAAR)) {
         const spr_op& q = ops[i];
+        if (q.which & SPR_ITER_TRACE)
+          fail(SPR_E_INVALID_ARG, "iteration traces are recorded for single populations only");
         const int alg = q.kind == SPR_OP_ER ? ALG_ER : (q.kind == SPR_OP_HIO ? ALG_HIO : ALG_RAAR);
         for (int c = 0; c < q.count; ++c) its.push_back({alg, (float)q.beta, q.chi});
         ++i;
@@ -1025,6 +1078,7 @@ void run_group_schedule(const Group& g, const spr_sched* sch, hipStream_t s) {
 // Crossover buffers allocated ahead of a capture (no allocation may happen
 // while a stream is being captured).
 void prepare_buffers(spr_pop* pop, const spr_sched* sch) {
+  trace_buffers(pop, traced_iterations(sch));
   for (const auto& o : sch->ops) {
     if ((o.kind == SPR_OP_CROSSOVER && pop->memetic && pop->P >= 4) || o.kind == SPR_OP_AVERAGE)
       correlation_buffers(pop);

@@ -72,6 +72,20 @@ __global__ void k_err_final(ErrFinalArgs a) {
   if (!isfinite(e)) atomicOr(d.flags, 1);
 }
 
+__global__ void k_trace_final(TraceFinalArgs a) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= a.nm) return;
+  double s = 0.0;
+  for (int i = 0; i < a.ntiles; ++i) s += a.partial[(size_t)m * a.ntiles + i];
+  a.row[a.pos0 + m] = sqrt(s / a.desc[a.slots[m]].den);
+}
+
+// A fill kernel (not a memset), so that it can sit in a captured graph.
+__global__ void k_fill(FillArgs a) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.count) a.dst[i] = a.value;
+}
+
 // ---------------------------------------------------------------------------
 // Shrink-wrap: |x| smoothed by a circular separable Gaussian (rows, columns).
 // ---------------------------------------------------------------------------
@@ -1191,6 +1205,15 @@ inline unsigned blocks_for(long n, int tpb) { return (unsigned)((n + tpb - 1) / 
 
 }  // namespace
 
+hipError_t launch_trace_final(const TraceFinalArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_trace_final, dim3(blocks_for(a.nm, 64)), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_fill(const FillArgs& a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for(a.count, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
 hipError_t launch_err_final(const ErrFinalArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_err_final, dim3(blocks_for(a.nm, 64)), dim3(64), 0, s, a);
   return hipGetLastError();

@@ -32,6 +32,22 @@ struct ErrFinalArgs {
   const SlotDesc* desc;  // fitness slot, sum of Xi M^2 and status word per member
 };
 
+// Per-iteration Fourier error of nm members into one trace row:
+// row[pos0 + m] = sqrt(sum of the member's tile partials / sum Xi M^2).
+struct TraceFinalArgs {
+  const double* partial;
+  int ntiles, nm;
+  const int* slots;
+  const SlotDesc* desc;
+  double* row;
+  int pos0;
+};
+struct FillArgs {
+  double* dst;
+  long count;
+  double value;
+};
+
 // Shrink-wrap smoothing of |x| (Gaussian of radius r, periodic, rows then
 // columns) for nm members; also the maximum per tile (block_max).
 struct SmoothArgs {
@@ -206,6 +222,8 @@ struct MonitorArgs {
 int smooth_blocks_per_member(int n);
 
 hipError_t launch_err_final(const ErrFinalArgs& a, hipStream_t s);
+hipError_t launch_trace_final(const TraceFinalArgs& a, hipStream_t s);
+hipError_t launch_fill(const FillArgs& a, hipStream_t s);
 hipError_t launch_smooth(const SmoothArgs& a, const MemberMaxArgs& mx,
                          hipStream_t s);
 hipError_t launch_threshold(const ThresholdArgs& a, hipStream_t s);

@@ -181,6 +181,12 @@ __device__ __forceinline__ TileId col_tile_id() {
   return {ltile % ntiles, ltile / ntiles};
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // Masked modulus replacement (Eq. pm_full) on the unnormalised column
 // spectrum X = N * (unitary value), returning the projected unitary value
 // divided by N, the input of the unnormalised inverse column transform; both
@@ -239,6 +245,9 @@ __global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
 // ---------------------------------------------------------------------------
 // Column projection: column FFT -> masked P_M -> column IFFT.
 // ---------------------------------------------------------------------------
+// TRACE also sums the FP64 residual Xi (|X| - M)^2 of the spectrum being
+// projected over the tile (the iterate's Fourier error, before P_M).
+template <bool TRACE>
 __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
   extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
@@ -259,11 +268,33 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
   load_twiddle_set<N>(ws, t, a.tw);
   fft<N, -1, ColL>(v, lds + c, t, a.tw, ws);
   const float inv = 1.0f / (float)N;
+  double acc = 0.0;
+  if constexpr (TRACE) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      if (!signbit(mv[m])) {
+        const float m2 = fmaf(v[m].x, v[m].x, __fmul_rn(v[m].y, v[m].y));
+        const double df = (double)__fmul_rn(sqrtf(m2), inv) - (double)__fmul_rn(mv[m], amp_scale);
+        acc = fma(df, df, acc);
+      }
+    }
+  }
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = modulus_replace(v[m], mv[m], amp_scale, inv);
   fft<N, +1, ColL>(v, lds + c, t, a.tw, ws);
 #pragma unroll
   for (int m = 0; m < E; ++m) dst[(size_t)(t + T * m) * N + col] = v[m];
+  if constexpr (TRACE) {
+    acc = wave_sum(acc);
+    double* wsum = reinterpret_cast<double*>(lds);  // the transform left the tile buffer free
+    if ((tid & 63) == 0) wsum[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < (C * T + 63) / 64; ++w) sum += wsum[w];
+      a.trace_partial[(size_t)id.img * (N / C) + id.tile] = sum;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -379,11 +410,6 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
 // Fitness column pass: column FFT of rowFFT(S x), FP64 partial sums of
 // Xi (|X| - M)^2 per tile (Eq. error_calc numerator).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 __global__ __launch_bounds__(C* T) void k_col_err(ColErrArgs a) {
   extern __shared__ float2 lds[];
@@ -659,9 +685,12 @@ hipError_t l_row_ingest(const RowIngestArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t l_col_proj(const ColProjArgs& a, hipStream_t s) {
-  static const hipError_t init = set_lds(k_col_proj, kColLds);
+  static const hipError_t init = set_lds(k_col_proj<false>, kColLds);
+  static const hipError_t init_t = set_lds(k_col_proj<true>, kColLds);
   if (init != hipSuccess) return init;
-  hipLaunchKernelGGL(k_col_proj, dim3(N / C, a.nm), dim3(C * T), kColLds, s, a);
+  if (init_t != hipSuccess) return init_t;
+  if (a.trace_partial) hipLaunchKernelGGL(k_col_proj<true>, dim3(N / C, a.nm), dim3(C * T), kColLds, s, a);
+  else hipLaunchKernelGGL(k_col_proj<false>, dim3(N / C, a.nm), dim3(C * T), kColLds, s, a);
   return hipGetLastError();
 }
 hipError_t l_row_update(const RowUpdateArgs& a, hipStream_t s) {

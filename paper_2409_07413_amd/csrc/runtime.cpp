@@ -658,6 +658,20 @@ spr_status spr_read_average(spr_pop* pop, float* rho, uint8_t* supp, double* err
   });
 }
 
+spr_status spr_read_trace(spr_pop* pop, double* out, int32_t max_rows, int32_t* rows, int32_t* cols) {
+  if (!pop || !rows || !cols || max_rows < 0 || (max_rows > 0 && !out) || !live_has(pop)) return SPR_E_INVALID_ARG;
+  spr_ctx* ctx = pop->ctx;
+  return guarded(ctx, [&] {
+    use_device(ctx);
+    sync_pop(pop);
+    *rows = pop->trace_rows;
+    *cols = pop->nslots;
+    const int k = std::min(max_rows, pop->trace_rows);
+    if (k > 0)
+      HIPCHK(hipMemcpy(out, pop->trace, sizeof(double) * (size_t)k * pop->nslots, hipMemcpyDeviceToHost));
+  });
+}
+
 spr_status spr_read_monitor(spr_pop* pop, spr_monitor* out, int32_t max_n, int32_t* n_out) {
   if (!pop || !n_out || (max_n > 0 && !out) || !live_has(pop)) return SPR_E_INVALID_ARG;
   spr_ctx* ctx = pop->ctx;

@@ -41,6 +41,8 @@ Program compile_program(const spr_sched* sch) {
              (ops[i].kind == SPR_OP_ER || ops[i].kind == SPR_OP_HIO || ops[i].kind == SPR_OP_RAAR)) {
         const spr_op& q = ops[i];
         if (q.scope != SPR_SCOPE_ALL) fail(SPR_E_INVALID_ARG, "served schedules act on every member (scope ALL)");
+        if (q.which & SPR_ITER_TRACE)
+          fail(SPR_E_INVALID_ARG, "iteration traces are recorded for single populations only");
         const int alg = q.kind == SPR_OP_ER ? ALG_ER : (q.kind == SPR_OP_HIO ? ALG_HIO : ALG_RAAR);
         for (int c = 0; c < q.count; ++c) pg.its.push_back({alg, (float)q.beta, q.chi});
         ++i;

@@ -172,3 +172,11 @@ def test_mpr_schedule_monitor_ops():
     assert kinds.count(K.OP_AVERAGE) == 3
     with pytest.raises(binding.SprError):
         binding.sched_ops([binding.op(K.OP_MONITOR, gen=0)])
+
+
+def test_iteration_trace_flag_validation():
+    binding, _ = _lib()
+    K = binding
+    binding.sched_ops([binding.op(K.OP_RAAR, count=3, beta=0.9, which=K.ITER_TRACE)])
+    with pytest.raises(binding.SprError):
+        binding.sched_ops([binding.op(K.OP_ER, count=3, which=2)])
