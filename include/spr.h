@@ -30,8 +30,12 @@
  *   destroy call.  Outputs go only into caller buffers.
  * - Work is enqueued asynchronously on a HIP stream (NULL = the context's
  *   stream); spr_sync and the read calls wait for it.
- * - A handle may be used by one thread at a time; distinct handles may be used
- *   from distinct threads.
+ * - Threads: calls on one context and on the handles created from it (shots,
+ *   populations, graphs, servers) must not overlap in time: one thread at a
+ *   time, or the caller's own locking.  Distinct contexts may be used from
+ *   distinct threads.  A server's engine thread is internal to the library
+ *   and needs no locking by the caller.  Schedule calls with a NULL context
+ *   touch no shared state.
  */
 #ifndef SPR_H
 #define SPR_H
