@@ -180,3 +180,17 @@ def test_iteration_trace_flag_validation():
     binding.sched_ops([binding.op(K.OP_RAAR, count=3, beta=0.9, which=K.ITER_TRACE)])
     with pytest.raises(binding.SprError):
         binding.sched_ops([binding.op(K.OP_ER, count=3, which=2)])
+
+
+def test_header_is_plain_c():
+    # the boundary header must compile as C99 on its own (no C++ constructs)
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = "#include <spr.h>\nint main(void) { spr_op o; o.kind = SPR_OP_ER; return o.kind == 0; }\n"
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-fsyntax-only",
+                        "-I", inc, "-x", "c", "-"], input=src, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
