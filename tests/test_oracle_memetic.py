@@ -143,6 +143,54 @@ def test_crossover_map_rotation_is_exact_integer_rotation():
             assert m[i, j] == (w < philox.bernoulli_threshold(0.5))
 
 
+def test_rotation_table_is_pythagorean_and_spans_a_quarter_turn():
+    # every rotation is exact in integers (a, b, h with a^2 + b^2 = h^2), the
+    # angles atan2(b, a) are distinct and lie in [0, 90) degrees, and the first
+    # entry is the identity
+    ang = []
+    for a, b, h in mpr.ROTATIONS:
+        assert a > 0 and b >= 0 and h > 0 and a * a + b * b == h * h
+        ang.append(np.degrees(np.arctan2(b, a)))
+    assert mpr.ROTATIONS[0] == (1, 0, 1)
+    assert len(set(np.round(ang, 9))) == len(ang) and min(ang) == 0.0 and max(ang) < 90.0
+
+
+def test_map_params_ranges_and_coverage():
+    # tile sides uniform on [t_min, t_max], shifts on [0, t), rotation index on
+    # the table: every value of each range is drawn and none outside it
+    t_min, t_max = 4, 8
+    tx_seen, sx_seen, rot_seen = set(), set(), set()
+    counts = np.zeros(t_max - t_min + 1, int)
+    for g in range(1, 201):
+        for p in range(5):
+            tx, ty, sx, sy, rot = mpr.map_params(64, 77, g, p, t_min, t_max)
+            assert t_min <= tx <= t_max and t_min <= ty <= t_max
+            assert 0 <= sx < tx and 0 <= sy < ty
+            assert 0 <= rot < len(mpr.ROTATIONS)
+            tx_seen.add(tx)
+            rot_seen.add(rot)
+            counts[tx - t_min] += 1
+            if tx == t_max:
+                sx_seen.add(sx)
+    assert tx_seen == set(range(t_min, t_max + 1))
+    assert rot_seen == set(range(len(mpr.ROTATIONS)))
+    assert sx_seen == set(range(t_max))
+    # 1000 draws over 5 sides: each count within 5 sigma of 200
+    assert np.all(np.abs(counts - 200) < 5 * np.sqrt(1000 * 0.2 * 0.8))
+    # the draws depend on (seed, generation, member) and not on the image size
+    assert mpr.map_params(64, 77, 3, 1, t_min, t_max) == mpr.map_params(512, 77, 3, 1, t_min, t_max)
+    assert len({mpr.map_params(64, 77, g, 0, t_min, t_max) for g in range(1, 30)}) > 20
+
+
+def test_default_tile_range():
+    # t_max = N / 8, never below t_min
+    assert mpr.default_t_max(512) == 64
+    assert mpr.default_t_max(1024) == 128
+    assert mpr.default_t_max(64) == 8
+    assert mpr.default_t_max(16) == 4
+    assert mpr.default_t_max(16, t_min=6) == 6
+
+
 def _small_population(n=32, P=4, seed=3):
     sh = synth.shot(n, "ellipses", seed, 1e6, beamstop=4, count=3, semi=(2.0, 5.0),
                     disk_diameter=14.0)

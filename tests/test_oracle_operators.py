@@ -294,6 +294,17 @@ def test_update_support_threshold():
     np.testing.assert_array_equal(mpr.update_support(np.zeros((n, n), complex), S1, 2.0, 0.1), S1)
 
 
+def test_support_area_count_rounds_half_up_and_clamps():
+    # round(alpha) with halves rounded up, at least one pixel, at most N^2
+    assert mpr.area_count(2.5, 100) == 3
+    assert mpr.area_count(2.499, 100) == 2
+    assert mpr.area_count(3.0, 100) == 3
+    assert mpr.area_count(0.4, 100) == 1
+    assert mpr.area_count(-7.0, 100) == 1
+    assert mpr.area_count(99.5, 100) == 100
+    assert mpr.area_count(1e9, 100) == 100
+
+
 def test_update_support_size_exact_topk_with_index_ties():
     n = 16
     rng = np.random.default_rng(0)
