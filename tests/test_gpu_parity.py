@@ -228,23 +228,29 @@ def test_twenty_iterations_random_start(ctx, B, n, alg):
 
 
 def test_twenty_iterations_with_shrinkwrap(ctx, B):
+    # ER^15, shrink-wrap, ER^5.  The support decision is checked on the GPU's
+    # own iterate (the oracle's FP64 smoothing of it; pixels outside the FP32
+    # band of the threshold must agree exactly); the oracle then continues
+    # from its own iterate with the support the GPU chose, and the final
+    # densities must agree to the 20-iteration bar.
     n, P = 128, 3
     c = Case(n, P, seed=77)
     sh, pop = c.population(ctx)
-    run_ops(pop, B, [B.op(B.OP_ER, count=15, chi=0.5),
-                     B.op(B.OP_SHRINKWRAP, sigma=2.0, tau=0.1),
-                     B.op(B.OP_ER, count=5, chi=0.5)])
-    rho, supp, _ = pop.read()
+    run_ops(pop, B, [B.op(B.OP_ER, count=15, chi=0.5)])
+    x15g, _, _ = pop.read()
+    run_ops(pop, B, [B.op(B.OP_SHRINKWRAP, sigma=2.0, tau=0.1), B.op(B.OP_ER, count=5, chi=0.5)])
+    x20g, supp, _ = pop.read()
     for p in range(P):
-        x = mpr.sequence(c.rho[p], c.S[p], c.M, c.known, 0.5, "HIO", 0.9, 0, 15)
-        a = mpr.smooth(np.abs(x), 2.0)
-        mism, inband = _band_compare(supp[p], a, 0.1 * a.max(), a.max())
-        if inband:
-            pytest.skip(f"{inband} support pixels within the FP32 band of the threshold")
-        assert mism == 0
-        S1 = a > 0.1 * a.max()
-        x = mpr.sequence(x, S1, c.M, c.known, 0.5, "HIO", 0.9, 0, 5)
-        assert rel(rho[p], x) <= 1e-3
+        x15 = mpr.sequence(c.rho[p], c.S[p], c.M, c.known, 0.5, "HIO", 0.9, 0, 15)
+        assert rel(x15g[p], x15) <= 1e-3
+        ag = mpr.smooth(np.abs(x15g[p].astype(np.complex128)), 2.0)
+        mism, _ = _band_compare(supp[p], ag, 0.1 * ag.max(), ag.max())
+        assert mism == 0, (p, mism)
+        a = mpr.smooth(np.abs(x15), 2.0)
+        flips = int((supp[p] != (a > 0.1 * a.max())).sum())
+        assert flips <= n * n // 500, (p, flips)
+        x20 = mpr.sequence(x15, supp[p].astype(bool), c.M, c.known, 0.5, "HIO", 0.9, 0, 5)
+        assert rel(x20g[p], x20) <= 1e-3
     pop.close()
     sh.close()
 
