@@ -59,7 +59,10 @@ def _compile(job):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    return obj
+    # source warnings (the host pass's notice about the packed-FP32 target
+    # feature it does not know is expected and left out)
+    warns = [l for l in r.stderr.splitlines() if "warning:" in l and "packed-fp32-ops" not in l]
+    return obj, sorted(set(warns))
 
 
 def build(jobs_parallel=None, verbose=False):
@@ -67,7 +70,11 @@ def build(jobs_parallel=None, verbose=False):
     jobs = _jobs()
     workers = jobs_parallel or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=workers) as ex:
-        objs = list(ex.map(_compile, jobs))
+        done = list(ex.map(_compile, jobs))
+    objs = [o for o, _ in done]
+    if verbose:
+        for w in sorted({w for _, ws in done for w in ws}):
+            print(w)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

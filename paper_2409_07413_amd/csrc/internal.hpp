@@ -761,7 +761,6 @@ void crossover(spr_pop* pop, const spr_op& op, hipStream_t s) {
   if (pop->P < 4) fail(SPR_E_INVALID_ARG, "crossover needs P >= 4");
   const SizeKernels* K = pop->K;
   const int n = pop->n, P = pop->P;
-  const size_t nn = (size_t)n * n;
   const float2* tw = twiddles(pop->ctx, n);
   int t_min = op.t_min > 0 ? op.t_min : 4;
   int t_max = op.t_max > 0 ? op.t_max : std::max(t_min, n / 8);

@@ -226,7 +226,7 @@ class SimExec : public Exec {
 class HipExec : public Exec {
  public:
   HipExec(spr_ctx* ctx, const Program& pg, const spr_server_cfg& cfg)
-      : ctx_(ctx), pg_(pg), P_(cfg.P), all_(cfg.flags & SPR_SERVER_ALL_MEMBERS),
+      : ctx_(ctx), pg_(pg), all_(cfg.flags & SPR_SERVER_ALL_MEMBERS),
         R_(cfg.max_inflight > 0 ? cfg.max_inflight : 2), t0_(std::chrono::steady_clock::now()) {
     use_device(ctx);
     members_ = (size_t)cfg.max_shots * cfg.P;
@@ -647,7 +647,6 @@ class HipExec : public Exec {
 
   spr_ctx* ctx_;
   const Program& pg_;
-  int P_;
   bool all_;
   int R_;
   std::chrono::steady_clock::time_point t0_;
