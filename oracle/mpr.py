@@ -158,7 +158,7 @@ def radial_bins(N):
     return np.floor(q + 0.5).astype(np.int64)
 
 
-def upper_bounds(M, known, eta=1.5, max_unknown=0.2):
+def upper_bounds(M, known, eta=1.5, max_unknown=0.2, saturated=None, max_saturated=0.05):
     """Amplitude upper bounds for unknown pixels (appendix on missing
     intensities, Eq. avgint, Eq. stdint, Eq. upperbound).
 
@@ -167,12 +167,20 @@ def upper_bounds(M, known, eta=1.5, max_unknown=0.2):
     U(q) = mu + eta * sigma.  A ring gets a bound only when its unknown pixels
     are at most `max_unknown` of the ring (and it has a known pixel).
     Readings: Eq. pm_bounds compares |rho~| with U, an amplitude with an
-    intensity; the amplitude bound taken is sqrt(U).  No saturation mask is
-    given, so the saturation rules do not apply.  Returns the bound per pixel
-    (NaN where there is none; known pixels get NaN too).
+    intensity; the amplitude bound taken is sqrt(U).
+    Saturation rules of the same appendix, with `saturated` (FFT order, a
+    subset of the unknown pixels, since saturated pixels carry no valid
+    measurement): a saturated pixel gets no bound, and a ring with more than
+    `max_saturated` (the paper's 5 %) of its pixels saturated gets none.
+    Saturated pixels count as unknown in the `max_unknown` rule.
+    Returns the bound per pixel (NaN where there is none; known pixels get
+    NaN too).
     """
     M = np.asarray(M, dtype=np.float64)
     N = M.shape[0]
+    sat = np.zeros((N, N), bool) if saturated is None else np.asarray(saturated, dtype=bool)
+    if np.any(sat & known):
+        raise ValueError("a saturated pixel must be unknown")
     bins = radial_bins(N)
     out = np.full((N, N), np.nan)
     for q in np.unique(bins):
@@ -181,10 +189,12 @@ def upper_bounds(M, known, eta=1.5, max_unknown=0.2):
         unk = ring & ~known
         if not kn.any() or unk.sum() > max_unknown * ring.sum():
             continue
+        if (ring & sat).sum() > max_saturated * ring.sum():
+            continue
         I = M[kn] ** 2
         mu = I.mean()
         var = max((I ** 2).mean() - mu ** 2, 0.0)
-        out[unk] = np.sqrt(mu + eta * np.sqrt(var))
+        out[unk & ~sat] = np.sqrt(mu + eta * np.sqrt(var))
     return out
 
 

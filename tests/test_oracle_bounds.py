@@ -59,6 +59,68 @@ def test_bound_needs_eighty_percent_known():
         assert bool(np.isfinite(U[tuple(pix[0])])) == has
 
 
+def test_saturated_pixels_get_no_bound():
+    # constant ring (bound = M): the unknown pixels that are saturated get no
+    # bound, the other unknown pixels keep theirs; no mask means no saturation
+    N = 32
+    pix = np.argwhere(_ring(N, 10))
+    M = np.full((N, N), 2.0)
+    known = np.ones((N, N), bool)
+    for i, j in pix[:4]:
+        known[i, j] = False
+    sat = np.zeros((N, N), bool)
+    sat[tuple(pix[0])] = True  # 1 of the ring's pixels: below 5 %
+    assert len(pix) > 20
+    U = mpr.upper_bounds(M, known, saturated=sat)
+    assert np.isnan(U[tuple(pix[0])])
+    for i, j in pix[1:4]:
+        assert U[i, j] == 2.0
+    np.testing.assert_array_equal(mpr.upper_bounds(M, known, saturated=np.zeros((N, N), bool)),
+                                  mpr.upper_bounds(M, known))
+
+
+def test_ring_more_than_five_percent_saturated_gets_no_bound():
+    N = 32
+    pix = np.argwhere(_ring(N, 10))
+    M = np.ones((N, N))
+    smax = int(np.floor(0.05 * len(pix)))  # most saturated pixels a bounded ring may have
+    assert smax >= 1
+    for k, has in ((smax, True), (smax + 1, False)):
+        known = np.ones((N, N), bool)
+        sat = np.zeros((N, N), bool)
+        for i, j in pix[:k]:
+            known[i, j] = False
+            sat[i, j] = True
+        free = tuple(pix[k])  # an unknown pixel that is not saturated
+        known[free] = False
+        U = mpr.upper_bounds(M, known, saturated=sat)
+        assert bool(np.isfinite(U[free])) == has
+        # the threshold follows max_saturated
+        U0 = mpr.upper_bounds(M, known, saturated=sat, max_saturated=0.0)
+        assert np.isnan(U0[free])
+    # other rings are untouched by the saturated pixels of ring 10
+    other = tuple(np.argwhere(_ring(N, 6))[0])
+    known = np.ones((N, N), bool)
+    known[other] = False
+    sat = np.zeros((N, N), bool)
+    for i, j in pix[:smax + 1]:
+        known[i, j] = False
+        sat[i, j] = True
+    assert mpr.upper_bounds(M, known, saturated=sat)[other] == 1.0
+
+
+def test_saturated_pixel_must_be_unknown():
+    N = 16
+    known = np.ones((N, N), bool)
+    sat = np.zeros((N, N), bool)
+    sat[3, 4] = True
+    try:
+        mpr.upper_bounds(np.ones((N, N)), known, saturated=sat)
+    except ValueError:
+        return
+    raise AssertionError("a known saturated pixel was accepted")
+
+
 def test_bounded_projector_properties():
     rng = np.random.default_rng(3)
     N = 24
