@@ -138,6 +138,16 @@ spr_status spr_shot_destroy(spr_shot* shot);
 /* marked unknown pixels of the stored modulus (no extra memory).  Waits for   */
 /* the device; *rings (may be NULL) gets the number of bounded rings.          */
 spr_status spr_shot_set_bounds(spr_shot* shot, double eta, double max_unknown, int32_t* rings);
+/* The same bounds with the saturation rules of that appendix: a saturated     */
+/* pixel gets no bound, and a ring with more than max_saturated of its pixels  */
+/* saturated (the paper's example: 0.05) gets none; saturated pixels count as   */
+/* unknown in the max_unknown rule.  saturated: N*N bytes, nonzero = saturated, */
+/* in the shot's layout (centred unless SPR_LAYOUT_FFT in flags; device memory  */
+/* with SPR_DEVICE_PTRS); read during the call only.  Every saturated pixel     */
+/* must be unknown in the shot's mask, else SPR_E_INVALID_ARG.  saturated ==    */
+/* NULL gives spr_shot_set_bounds (max_saturated and flags unused).             */
+spr_status spr_shot_set_bounds_sat(spr_shot* shot, double eta, double max_unknown, const uint8_t* saturated,
+                                   double max_saturated, uint32_t flags, int32_t* rings);
 
 /* ------------------------------------------------------------------------- */
 /* Population: P reconstructions (Alg. mpr / Alg. randomsearch, D1-D2 of the   */
@@ -446,6 +456,8 @@ typedef struct spr_shot_desc {
                           /* (the simulated executor admits no request before its arrival)  */
   double bound_eta;       /* > 0: upper bounds on unknown amplitudes as spr_shot_set_bounds */
   double bound_max_unknown;
+  const uint8_t* saturated;   /* NULL, or N*N saturation mask (host, layout of amp): the */
+  double bound_max_saturated; /* saturation rules of spr_shot_set_bounds_sat           */
 } spr_shot_desc;
 
 typedef struct spr_result {

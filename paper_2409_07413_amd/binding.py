@@ -104,7 +104,7 @@ class ShotDesc(C.Structure):
     _fields_ = [("n", C.c_int32), ("amp", C.c_void_p), ("mask", C.c_void_p), ("supp0", C.c_void_p),
                 ("supp_per_member", C.c_int32), ("flags", C.c_uint32), ("rho0", C.c_void_p),
                 ("seed", C.c_uint64), ("arrival", C.c_double), ("bound_eta", C.c_double),
-                ("bound_max_unknown", C.c_double)]
+                ("bound_max_unknown", C.c_double), ("saturated", C.c_void_p), ("bound_max_saturated", C.c_double)]
 
 
 class Result(C.Structure):
@@ -135,7 +135,7 @@ EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_suppo
            "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
            "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
            "spr_timing_enable", "spr_timing_sample", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch",
-           "spr_read_member", "spr_read_average", "spr_read_monitor", "spr_read_trace", "spr_pop_init_spheres", "spr_shot_set_bounds", "spr_size_variants", "spr_ctx_autotune", "spr_ctx_set_variant",
+           "spr_read_member", "spr_read_average", "spr_read_monitor", "spr_read_trace", "spr_pop_init_spheres", "spr_shot_set_bounds", "spr_shot_set_bounds_sat", "spr_size_variants", "spr_ctx_autotune", "spr_ctx_set_variant",
            "spr_ctx_get_tuning", "spr_graph_create", "spr_graph_create_batch", "spr_graph_launch",
            "spr_graph_destroy", "spr_server_create", "spr_server_submit", "spr_server_poll", "spr_server_step", "spr_server_drain",
            "spr_server_stats_get", "spr_server_last_error", "spr_server_destroy"]
@@ -181,6 +181,8 @@ def _proto(lib):
         "spr_read_trace": (i32, [vp, vp, i32, C.POINTER(i32), C.POINTER(i32)]),
         "spr_pop_init_spheres": (i32, [vp, C.POINTER(SphereParams)]),
         "spr_shot_set_bounds": (i32, [vp, C.c_double, C.c_double, C.POINTER(i32)]),
+        "spr_shot_set_bounds_sat": (i32, [vp, C.c_double, C.c_double, vp, C.c_double, C.c_uint32,
+                                          C.POINTER(i32)]),
         "spr_size_variants": (i32, [i32]),
         "spr_ctx_autotune": (i32, [vp, i32, i32, C.POINTER(TuneResult)]),
         "spr_ctx_set_variant": (i32, [vp, i32, i32, i32]),
@@ -426,6 +428,7 @@ class Shot:
         ctx._check(ctx.lib.spr_shot_create(ctx.h, self.n, pa, pm, flags, C.byref(h)))
         self.h = h
         self._keep = (amp, mask)
+        self._fft_order = bool(fft_order)
         ctx._shots.add(self)
 
     def close(self):
@@ -440,10 +443,19 @@ class Shot:
         except Exception:
             pass
 
-    def set_bounds(self, eta=1.5, max_unknown=0.2):
-        """Upper bounds on the unknown amplitudes from the radial profile; returns the bounded rings."""
+    def set_bounds(self, eta=1.5, max_unknown=0.2, saturated=None, max_saturated=0.05):
+        """Upper bounds on the unknown amplitudes from the radial profile; returns the bounded rings.
+        `saturated` (N*N, the shot's layout, host or device): the saturation rules apply."""
         r = C.c_int32()
-        self.ctx._check(self.ctx.lib.spr_shot_set_bounds(self.h, float(eta), float(max_unknown), C.byref(r)))
+        if saturated is None:
+            self.ctx._check(self.ctx.lib.spr_shot_set_bounds(self.h, float(eta), float(max_unknown), C.byref(r)))
+            return r.value
+        if isinstance(saturated, np.ndarray):
+            saturated = np.ascontiguousarray(saturated, dtype=np.uint8)
+        ps, ds = _ptr(saturated)
+        flags = (DEVICE_PTRS if ds else 0) | (LAYOUT_FFT if self._fft_order else 0)
+        self.ctx._check(self.ctx.lib.spr_shot_set_bounds_sat(self.h, float(eta), float(max_unknown), ps,
+                                                             float(max_saturated), flags, C.byref(r)))
         return r.value
 
     def population(self, rho0, supp0, memetic=False, seed=0, gen_offset=0, P=None):
@@ -679,7 +691,7 @@ class Server:
             raise SprError(st, raw.decode() if raw else "")
 
     def submit(self, amp, mask, supp0, rho0=None, seed=0, fft_order=False, arrival=None, fp16=False,
-               bound_eta=0.0, bound_max_unknown=0.2):
+               bound_eta=0.0, bound_max_unknown=0.2, saturated=None, bound_max_saturated=0.05):
         """Queue one shot (host arrays); rho0 None = device random-phase start."""
         n = int(amp.shape[0])
         amp = np.ascontiguousarray(amp, dtype=np.float32)
@@ -694,7 +706,10 @@ class Server:
             rp = rho0.ctypes.data
         d = ShotDesc(n, amp.ctypes.data, mask.ctypes.data, supp0.ctypes.data, 1 if supp0.ndim == 3 else 0,
                      flags, rp, int(seed) & 0xFFFFFFFFFFFFFFFF, -1.0 if arrival is None else float(arrival),
-                     float(bound_eta), float(bound_max_unknown))
+                     float(bound_eta), float(bound_max_unknown), None, float(bound_max_saturated))
+        if saturated is not None:
+            saturated = np.ascontiguousarray(saturated, dtype=np.uint8)
+            d.saturated = saturated.ctypes.data
         t = C.c_uint64()
         self._check(self.lib.spr_server_submit(self.h, C.byref(d), C.byref(t)))
         self._n[t.value] = n

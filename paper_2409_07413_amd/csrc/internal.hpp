@@ -312,9 +312,13 @@ float fp16_encode(const float* enc, size_t nn, std::vector<__half>& out, double&
 // goes into the unknown pixels of `enc` (stored values, FFT order) as -sqrt(U)
 // / scale, keeping the sign bit that marks them; -0 means no bound, and a zero
 // bound is kept as the smallest positive normal value.  eta <= 0 clears every
-// bound.  Returns the number of rings with a bound.
+// bound.  With `sat` (FFT order, nonzero = saturated, all unknown), the
+// saturation rules of the same appendix apply: a saturated pixel gets no bound
+// and a ring with more than max_sat of its pixels saturated gets none.
+// Returns the number of rings with a bound.
 int apply_upper_bounds(int n, float* enc, float scale, double eta, double max_unknown,
-                       float tiny = std::numeric_limits<float>::min()) {
+                       float tiny = std::numeric_limits<float>::min(), const uint8_t* sat = nullptr,
+                       double max_sat = 1.0) {
   const size_t nn = (size_t)n * n;
   std::vector<int> bin(nn);
   int nb = 0;
@@ -326,9 +330,10 @@ int apply_upper_bounds(int n, float* enc, float scale, double eta, double max_un
       nb = std::max(nb, b + 1);
     }
   std::vector<double> s1(nb, 0.0), s2(nb, 0.0);
-  std::vector<int64_t> known(nb, 0), total(nb, 0);
+  std::vector<int64_t> known(nb, 0), total(nb, 0), nsat(nb, 0);
   for (size_t k = 0; k < nn; ++k) {
     total[bin[k]]++;
+    if (sat && sat[k]) nsat[bin[k]]++;
     if (!std::signbit(enc[k])) {
       const double I = (double)enc[k] * scale * ((double)enc[k] * scale);
       s1[bin[k]] += I;
@@ -341,6 +346,7 @@ int apply_upper_bounds(int n, float* enc, float scale, double eta, double max_un
   for (int b = 0; b < nb; ++b) {
     if (!(eta > 0.0) || known[b] == 0) continue;
     if ((double)(total[b] - known[b]) > max_unknown * (double)total[b]) continue;
+    if ((double)nsat[b] > max_sat * (double)total[b]) continue;
     const double mu = s1[b] / (double)known[b];
     const double var = std::max(s2[b] / (double)known[b] - mu * mu, 0.0);
     bound[b] = std::sqrt(mu + eta * std::sqrt(var));
@@ -349,10 +355,24 @@ int apply_upper_bounds(int n, float* enc, float scale, double eta, double max_un
   for (size_t k = 0; k < nn; ++k) {
     if (!std::signbit(enc[k])) continue;
     const double b = bound[bin[k]];
-    if (b < 0.0) enc[k] = -0.0f;
+    if (b < 0.0 || (sat && sat[k])) enc[k] = -0.0f;
     else enc[k] = -std::max((float)(b / scale), tiny);
   }
   return rings;
+}
+
+// A saturation mask (layout as the shot's mask) in FFT order; every saturated
+// pixel must be unknown in the encoded modulus.
+std::vector<uint8_t> saturation_fft(int n, const uint8_t* sat, uint32_t flags, const float* enc) {
+  const int h = (flags & SPR_LAYOUT_FFT) ? 0 : n / 2;
+  std::vector<uint8_t> out((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const size_t k = (size_t)i * n + j;
+      out[k] = sat[(size_t)((i + h) % n) * n + (size_t)((j + h) % n)] != 0;
+      if (out[k] && !std::signbit(enc[k])) fail(SPR_E_INVALID_ARG, "a saturated pixel is marked as measured");
+    }
+  return out;
 }
 
 uint8_t* stage(spr_pop* pop, size_t bytes) {

@@ -996,32 +996,49 @@ spr_status spr_ctx_autotune(spr_ctx* ctx, int32_t n, int32_t members, spr_tune_r
   });
 }
 
-spr_status spr_shot_set_bounds(spr_shot* shot, double eta, double max_unknown, int32_t* rings) {
+spr_status spr_shot_set_bounds_sat(spr_shot* shot, double eta, double max_unknown, const uint8_t* saturated,
+                                   double max_saturated, uint32_t flags, int32_t* rings) {
   if (!shot || !live_has(shot)) return SPR_E_INVALID_ARG;
   spr_ctx* ctx = shot->ctx;
   return guarded(ctx, [&] {
     if (!(max_unknown >= 0.0 && max_unknown <= 1.0)) fail(SPR_E_INVALID_ARG, "max_unknown must lie in [0, 1]");
+    if (saturated && !(max_saturated >= 0.0 && max_saturated <= 1.0))
+      fail(SPR_E_INVALID_ARG, "max_saturated must lie in [0, 1]");
     use_device(ctx);
     HIPCHK(hipDeviceSynchronize());  // populations may be reading the modulus
     const int n = shot->n;
     const size_t nn = (size_t)n * n;
+    std::vector<uint8_t> sat_in;
+    if (saturated) to_host(sat_in, saturated, nn, flags & SPR_DEVICE_PTRS);
     std::vector<float> enc(nn);
-    int r = 0;
+    std::vector<__half> h;
     if (shot->amp16) {
-      std::vector<__half> h(nn);
+      h.resize(nn);
       HIPCHK(hipMemcpy(h.data(), shot->amp16, nn * sizeof(__half), hipMemcpyDeviceToHost));
       for (size_t k = 0; k < nn; ++k) enc[k] = __half2float(h[k]);
-      r = apply_upper_bounds(n, enc.data(), shot->amp_scale, eta, max_unknown, kHalfTiny);
+    } else {
+      HIPCHK(hipMemcpy(enc.data(), shot->amp, nn * sizeof(float), hipMemcpyDeviceToHost));
+    }
+    std::vector<uint8_t> sat;
+    if (saturated) sat = saturation_fft(n, sat_in.data(), flags, enc.data());
+    const uint8_t* sp = saturated ? sat.data() : nullptr;
+    const double ms = saturated ? max_saturated : 1.0;
+    int r = 0;
+    if (shot->amp16) {
+      r = apply_upper_bounds(n, enc.data(), shot->amp_scale, eta, max_unknown, kHalfTiny, sp, ms);
       for (size_t k = 0; k < nn; ++k)
         h[k] = __float2half(std::signbit(enc[k]) ? -std::min(-enc[k], 65504.0f) : enc[k]);
       HIPCHK(hipMemcpy(shot->amp16, h.data(), nn * sizeof(__half), hipMemcpyHostToDevice));
     } else {
-      HIPCHK(hipMemcpy(enc.data(), shot->amp, nn * sizeof(float), hipMemcpyDeviceToHost));
-      r = apply_upper_bounds(n, enc.data(), 1.0f, eta, max_unknown);
+      r = apply_upper_bounds(n, enc.data(), 1.0f, eta, max_unknown, std::numeric_limits<float>::min(), sp, ms);
       HIPCHK(hipMemcpy(shot->amp, enc.data(), nn * sizeof(float), hipMemcpyHostToDevice));
     }
     if (rings) *rings = r;
   });
+}
+
+spr_status spr_shot_set_bounds(spr_shot* shot, double eta, double max_unknown, int32_t* rings) {
+  return spr_shot_set_bounds_sat(shot, eta, max_unknown, nullptr, 0.0, 0u, rings);
 }
 
 }  // extern "C"

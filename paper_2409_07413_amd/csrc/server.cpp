@@ -837,7 +837,15 @@ spr_status spr_server_submit(spr_server* sv, const spr_shot_desc* sd, uint64_t* 
       if (sd->bound_eta > 0.0) {
         if (!(sd->bound_max_unknown >= 0.0 && sd->bound_max_unknown <= 1.0))
           fail(SPR_E_INVALID_ARG, "bound_max_unknown must lie in [0, 1]");
-        apply_upper_bounds(n, d->enc.data(), 1.0f, sd->bound_eta, sd->bound_max_unknown);
+        std::vector<uint8_t> sat;
+        if (sd->saturated) {
+          if (!(sd->bound_max_saturated >= 0.0 && sd->bound_max_saturated <= 1.0))
+            fail(SPR_E_INVALID_ARG, "bound_max_saturated must lie in [0, 1]");
+          sat = saturation_fft(n, sd->saturated, sd->flags, d->enc.data());
+        }
+        apply_upper_bounds(n, d->enc.data(), 1.0f, sd->bound_eta, sd->bound_max_unknown,
+                           std::numeric_limits<float>::min(), sd->saturated ? sat.data() : nullptr,
+                           sd->saturated ? sd->bound_max_saturated : 1.0);
       }
       if (sd->flags & SPR_AMP_FP16) {
         d->amp_scale = fp16_encode(d->enc.data(), nn, d->enc16, d->den);
