@@ -35,6 +35,8 @@ def ellipses(n, seed, count=5, semi=(4.0, 15.0), disk_diameter=40.0):
         a, b = rng.uniform(semi[0], semi[1], size=2)
         ang = rng.uniform(0.0, np.pi)
         reach = max(a, b)
+        if reach > rad:
+            raise ValueError(f"an ellipse with semi-axis {reach:.2f} does not fit a disk of radius {rad:.2f}")
         while True:
             c = rng.uniform(-rad, rad, size=2)
             if np.hypot(c[0], c[1]) + reach <= rad:

@@ -16,7 +16,8 @@ class Case:
 
     def __init__(self, n, P, seed=1, photons=1e6, gap=None, kind="ellipses", side=None, per_member_supp=False):
         if kind == "ellipses":
-            kw = dict(count=5, semi=(max(1.0, 0.03 * n), max(1.5, 0.11 * n)), disk_diameter=0.32 * n)
+            semi = (max(1.0, 0.03 * n), max(1.5, 0.11 * n))
+            kw = dict(count=5, semi=semi, disk_diameter=max(0.32 * n, 2.0 * semi[1] + 0.5))
         else:
             kw = dict(count=12, radius=(0.012 * n, 0.047 * n), spread=0.06 * n, extent=0.3 * n)
         bs = max(2, n // 16)

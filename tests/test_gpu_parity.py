@@ -87,6 +87,76 @@ def test_single_iterations(ctx, B, n, chi):
         sh.close()
 
 
+def _size_variants():
+    from paper_2409_07413_amd import build
+    return [(n, v) for n in ALL_SIZES for v in ((0, 1) if n in build.VARIANT_SIZES else (0,))]
+
+
+@pytest.mark.parametrize("n,variant", _size_variants())
+def test_iterations_every_size_and_variant(ctx, B, n, variant):
+    # every compiled loop kernel (both plans where a size has two): RAAR and ER
+    # steps in one schedule (the iterate stays a row transform between them),
+    # the fitness, and one HIO step, from per-member supports; three members,
+    # so that small sizes put rows of several members in one wavefront.  HIO's
+    # choice between y and x - beta y is discontinuous at the constraint
+    # boundary, so it is checked over one step only (longer HIO runs are
+    # compared between plans bit for bit below).
+    P = 3
+    c = Case(n, P, seed=n + 5 * variant + 11, per_member_supp=True)
+    ctx.set_variant(n, variant)
+    try:
+        sh, pop = c.population(ctx)
+        run_ops(pop, B, [B.op(B.OP_RAAR, count=2, beta=0.9, chi=0.5), B.op(B.OP_ER, count=2, chi=0.3),
+                         B.op(B.OP_GET_ERROR)])
+        rho, supp, err = pop.read()
+        pop.close()
+        sh.close()
+        sh, pop = c.population(ctx)
+        run_ops(pop, B, [B.op(B.OP_HIO, count=1, beta=0.8, chi=0.3)])
+        rho_h, _, _ = pop.read()
+        pop.close()
+        sh.close()
+    finally:
+        ctx.set_variant(n, 0)
+    for p in range(P):
+        x = c.rho[p]
+        for _ in range(2):
+            x = mpr.raar(x, c.S[p], c.M, c.known, 0.5, 0.9)
+        for _ in range(2):
+            x = mpr.er(x, c.S[p], c.M, c.known, 0.3)
+        assert rel(rho[p], x) <= 1e-4, (n, variant, p, rel(rho[p], x))
+        e = mpr.get_error(x, c.S[p], c.M, c.known)
+        assert abs(err[p] - e) <= 1e-4 * e
+        assert rel(rho_h[p], mpr.hio(c.rho[p], c.S[p], c.M, c.known, 0.3, 0.8)) <= 1e-5
+    np.testing.assert_array_equal(supp, c.S)
+
+
+@pytest.mark.parametrize("n", (256, 384, 512, 768))
+def test_plans_of_a_size_are_bit_identical(ctx, B, n):
+    # at these sizes the two plans differ only in the column-tile width, which
+    # changes no transform arithmetic: the same schedule, HIO steps included,
+    # gives the same density bits; the fitness sums one FP64 partial per tile,
+    # so its last bit follows the tile count (the two 1024 plans order their
+    # radices differently, so they round differently; both meet the oracle bar
+    # above)
+    P = 3
+    c = Case(n, P, seed=n + 400, per_member_supp=True)
+    outs = []
+    for variant in (0, 1):
+        ctx.set_variant(n, variant)
+        try:
+            sh, pop = c.population(ctx)
+            run_ops(pop, B, [B.op(B.OP_RAAR, count=2, beta=0.9, chi=0.5), B.op(B.OP_HIO, count=2, beta=0.8, chi=0.3),
+                             B.op(B.OP_ER, count=2, chi=0.5), B.op(B.OP_GET_ERROR)])
+            outs.append(pop.read())
+            pop.close()
+            sh.close()
+        finally:
+            ctx.set_variant(n, 0)
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_allclose(outs[0][2], outs[1][2], rtol=1e-14, atol=0)
+
+
 @pytest.mark.parametrize("n", OP_SIZES)
 def test_get_error(ctx, B, n):
     P = 4
