@@ -107,9 +107,12 @@ typedef struct spr_tune_result {
 } spr_tune_result;
 /* Number of compiled kernel variants of size n (0 if unsupported). */
 int32_t spr_size_variants(int32_t n);
+/* Times the candidates of size n on `members` synthetic members (as above); */
+/* waits for the device.  SPR_E_UNSUPPORTED_SIZE for an unsupported n.       */
 spr_status spr_ctx_autotune(spr_ctx* ctx, int32_t n, int32_t members, spr_tune_result* out);
 /* Set the choice by hand (chunk_members 0: the cache-budget rule). */
 spr_status spr_ctx_set_variant(spr_ctx* ctx, int32_t n, int32_t variant, int32_t chunk_members);
+/* The choice in force for size n (variant 0 and chunk 0 when none was made). */
 spr_status spr_ctx_get_tuning(spr_ctx* ctx, int32_t n, int32_t* variant, int32_t* chunk_members);
 
 /* ------------------------------------------------------------------------- */
@@ -166,6 +169,8 @@ spr_status spr_shot_set_bounds_sat(spr_shot* shot, double eta, double max_unknow
 spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const uint8_t* supp0,
                           int32_t supp_per_member, uint32_t flags, uint64_t seed,
                           int32_t gen_offset, spr_pop** out);
+/* Waits for the population's work and frees it; SPR_E_BUSY while a graph    */
+/* references it.                                                             */
 spr_status spr_pop_destroy(spr_pop* pop);
 /* The paper's Initialize (initialisation appendix) on the device, for the     */
 /* parents: each fills a centred sigma_init-wide square with n_init projected  */
@@ -280,6 +285,7 @@ spr_status spr_sched_plain(spr_ctx* ctx, const spr_plain_params* prm, spr_sched*
 /* Alg. improve operations on every member, SELECT; after generation G the     */
 /* final AVERAGE (read with spr_read_average).                                 */
 spr_status spr_sched_mpr(spr_ctx* ctx, const spr_mpr_params* prm, spr_sched** out);
+/* Frees a schedule (a host object; work already enqueued from it is kept).  */
 spr_status spr_sched_destroy(spr_sched* sched);
 /* Copy out the expanded op list (ops may be NULL to query the count). */
 spr_status spr_sched_ops(const spr_sched* sched, spr_op* ops, int32_t max_ops, int32_t* n_ops);
@@ -403,6 +409,7 @@ spr_status spr_graph_create_batch(spr_ctx* ctx, spr_pop* const* pops, const spr_
 /* Enqueues one replay on hip_stream (NULL = the context stream), ordered     */
 /* after the populations' earlier work.                                       */
 spr_status spr_graph_launch(spr_graph* g, void* hip_stream);
+/* Waits for the graph's replays and frees it (and the work buffers it owns). */
 spr_status spr_graph_destroy(spr_graph* g);
 
 /* ------------------------------------------------------------------------- */
@@ -498,7 +505,9 @@ spr_status spr_server_step(spr_server* sv, int64_t* pending);
 /* Wait until every submitted request is done (driving the engine in manual    */
 /* mode); SPR_E_NOT_READY after timeout_s seconds (< 0: no limit).             */
 spr_status spr_server_drain(spr_server* sv, double timeout_s);
+/* Counters and memory figures of the server so far (see spr_server_stats). */
 spr_status spr_server_stats_get(spr_server* sv, spr_server_stats* st);
+/* Message of the last failed call on this server (owned by the server).      */
 const char* spr_server_last_error(const spr_server* sv);
 /* Stops the engine, waits for the device and frees everything (pending       */
 /* results included).                                                          */
