@@ -695,9 +695,11 @@ hipError_t l_col_proj(const ColProjArgs& a, hipStream_t s) {
 }
 hipError_t l_row_update(const RowUpdateArgs& a, hipStream_t s) {
   const dim3 grid(row_blocks(a.nm)), block(RW * T);
-  // the HIO/RAAR-only kernels gain on power-of-two sizes and lose on the
-  // radix-3 ones, where the run-time form keeps fewer registers live
-  constexpr bool kSpecIA = (N & (N - 1)) == 0;
+  // the HIO/RAAR-only kernels gain on power-of-two sizes up to 512 and lose on
+  // the radix-3 ones and at 1024, where the run-time form keeps fewer
+  // registers live (at 1024: 165 against 197, three waves per SIMD instead of
+  // two)
+  constexpr bool kSpecIA = (N & (N - 1)) == 0 && N < 1024;
   if (a.ip) hipLaunchKernelGGL(k_row_update<0>, grid, block, kRowLds, s, a);
   else if (a.alg == ALG_ER) hipLaunchKernelGGL(k_row_update<1>, grid, block, kRowLds, s, a);
   else if (!kSpecIA) hipLaunchKernelGGL(k_row_update<0>, grid, block, kRowLds, s, a);
