@@ -240,8 +240,14 @@ def run_plain_fifo(ctx, B, pool, supp, stream, warm=True):
     return _latency_summary(lat, 0.0, fin, len(lat), float(sum(int(n) ** 2 for n in sizes)))
 
 
-def serving_leg(ctx, B, rates, count, max_shots, budget, forms=("served", "plain"), log=None, shortest=False):
+def serving_leg(ctx, B, rates, count, max_shots, budget, forms=("served", "plain"), log=None, shortest=False,
+                tune=True):
+    """Both forms run on the same context, so with `tune` both use the kernel
+    variant the run-time tuner picks per size (for the resident member count)."""
     pool, supp = serving_pool()
+    if tune:
+        for n in SERVE_SIZES:
+            ctx.autotune(int(n), SERVE_P * max_shots)
     out = []
     for rate, cnt in zip(rates, count):
         stream = serving_stream(rate, cnt)
@@ -669,6 +675,8 @@ def main():
     ap.add_argument("--serve-forms", type=str, default="served,plain")
     ap.add_argument("--serve-policy", choices=("shortest", "all"), default="shortest",
                     help="ticks advance the shots of the least remaining work first, or every resident shot")
+    ap.add_argument("--serve-no-tune", action="store_true",
+                    help="serve with each size's default kernel variant instead of the tuned one")
     ap.add_argument("--precision", action="store_true",
                     help="run the FP16-versus-FP32 modulus storage study and exit")
     ap.add_argument("--size-sweep", action="store_true",
@@ -736,7 +744,7 @@ def main():
         from paper_2409_07413_amd import binding as B
         ctx = B.Context(0)
         res = serving_leg(ctx, B, rates, counts, args.serve_max_shots, int(args.serve_budget_gib * (1 << 30)),
-                          forms, log, shortest=args.serve_policy == "shortest")
+                          forms, log, shortest=args.serve_policy == "shortest", tune=not args.serve_no_tune)
         print(json.dumps({"serving": res, "config": {
             "workload": "serving stream: Poisson arrivals, sizes uniform over 256..1024 (5 sizes), "
                         "5 ellipses in a 40-px disk, 1e6 photons, 8x8 beamstop, P=32, 500 iterations",
@@ -873,7 +881,7 @@ def main():
     shot.close()
     if not args.no_serve:
         srv = serving_leg(ctx, B, rates, counts, args.serve_max_shots, int(args.serve_budget_gib * (1 << 30)),
-                          forms, log, shortest=args.serve_policy == "shortest")
+                          forms, log, shortest=args.serve_policy == "shortest", tune=not args.serve_no_tune)
         out["serving"] = {"workload": "Poisson arrivals, sizes uniform over {256,384,512,768,1024}, "
                                       "5 ellipses in a 40-px disk, 1e6 photons, 8x8 beamstop, P=32, "
                                       "500 iterations (25 x [HIO^j ER^(20-j), shrink-wrap]) + GetError; "
