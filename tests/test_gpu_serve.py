@@ -81,6 +81,27 @@ def test_served_equals_population_run(ctx, B):
     assert st["bytes_in_use"] == 0 and st["completed"] == 1
 
 
+@pytest.mark.parametrize("n", (256, 384))
+def test_server_uses_the_context_variant(ctx, B, n):
+    # a server created while the alternative plan is selected runs it: its
+    # shot equals the population run on that plan bit for bit (and, since the
+    # plans differ only in column-tile width, the default plan's densities)
+    c = Case(n, 3, seed=n + 61)
+    s = plain(B, ctx, G=2)
+    base = alone_population(ctx, B, c, s)
+    ctx.set_variant(n, 1)
+    try:
+        rho_a, supp_a, err_a = alone_population(ctx, B, c, s)
+        (r,), _ = serve(ctx, B, [c], s, P=3)
+    finally:
+        ctx.set_variant(n, 0)
+    np.testing.assert_array_equal(r["rho"], rho_a)
+    np.testing.assert_array_equal(r["supp"], supp_a)
+    np.testing.assert_array_equal(r["err"], err_a)
+    np.testing.assert_array_equal(rho_a, base[0])
+    np.testing.assert_allclose(err_a, base[2], rtol=1e-14, atol=0)
+
+
 def test_alone_equals_mix(ctx, B):
     specs = [(64, 51), (96, 52), (64, 53), (128, 54), (32, 55), (96, 56)]
     cases = [Case(n, 4, seed=sd) for n, sd in specs]
