@@ -194,3 +194,36 @@ def test_header_is_plain_c():
     r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-fsyntax-only",
                         "-I", inc, "-x", "c", "-"], input=src, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_missing_library_fails_loudly():
+    # the product path has no fallback: without the HIP library every call
+    # into it raises at load time
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2409_07413_amd import binding\n"
+            "binding.LIB_PATH = '/nonexistent/libspr.so'\n"
+            "try:\n"
+            "    binding.Context(0)\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n"
+            "    sys.exit(0)\n"
+            "sys.exit(1)\n") % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "not built" in r.stdout
+
+
+def test_product_code_does_not_use_the_oracle():
+    # only the tests, the smoke entry point and the benchmark's CPU baseline
+    # may reach the oracle; the package and its native sources never do
+    pkg = os.path.join(ROOT, "paper_2409_07413_amd")
+    for dirpath, _, files in os.walk(pkg):
+        if "_build" in dirpath or "__pycache__" in dirpath:
+            continue
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b", txt, re.M), f
+                assert "oracle/" not in txt and "oracle." not in txt, f
