@@ -227,3 +227,21 @@ def test_product_code_does_not_use_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle\b", txt, re.M), f
                 assert "oracle/" not in txt and "oracle." not in txt, f
+
+
+def test_benchmark_reaches_the_oracle_only_in_its_cpu_baseline():
+    import ast
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    users = set()
+    for fn in ast.walk(tree):
+        if isinstance(fn, ast.FunctionDef):
+            for node in ast.walk(fn):
+                if isinstance(node, ast.ImportFrom) and node.module and node.module.split(".")[0] == "oracle":
+                    users.add(fn.name)
+                if isinstance(node, ast.Import) and any(a.name.split(".")[0] == "oracle" for a in node.names):
+                    users.add(fn.name)
+    top = [n for n in tree.body if isinstance(n, (ast.Import, ast.ImportFrom))
+           and "oracle" in ast.dump(n)]
+    assert not top
+    # cpu_baseline and the worker it forks per member
+    assert users == {"cpu_baseline", "_oracle_member"}, users
