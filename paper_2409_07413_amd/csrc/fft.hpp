@@ -80,13 +80,13 @@ SPR_DEFINE_PLAN(192, 24, 16, 3, 8, 8)
 #if SPR_VARIANT == 1
 SPR_DEFINE_PLAN(256, 8, 8, 4, 8, 8)
 SPR_DEFINE_PLAN(512, 8, 16, 8, 8, 8)
-SPR_DEFINE_PLAN(384, 12, 8, 4, 4, 4, 2, 3)
+SPR_DEFINE_PLAN(384, 12, 16, 4, 4, 4, 2, 3)
 SPR_DEFINE_PLAN(768, 12, 16, 4, 4, 4, 4, 3)
 SPR_DEFINE_PLAN(1024, 16, 8, 16, 8, 8)
 #else
 SPR_DEFINE_PLAN(256, 8, 16, 4, 8, 8)
 SPR_DEFINE_PLAN(512, 8, 8, 8, 8, 8)
-SPR_DEFINE_PLAN(384, 12, 16, 4, 4, 4, 2, 3)
+SPR_DEFINE_PLAN(384, 12, 8, 4, 4, 4, 2, 3)
 SPR_DEFINE_PLAN(768, 12, 8, 4, 4, 4, 4, 3)
 SPR_DEFINE_PLAN(1024, 16, 8, 8, 8, 16)
 #endif
