@@ -44,6 +44,29 @@ def test_trace_matches_oracle(ctx, B, n, alg, n_ia, n_er):
     sh.close()
 
 
+@pytest.mark.parametrize("n", (256, 384, 512, 768, 1024))
+@pytest.mark.parametrize("variant", (0, 1))
+def test_trace_every_plan(ctx, B, n, variant):
+    # the tracing column pass of both plans of each tuned size (its per-tile
+    # FP64 partials follow the tile width, its workgroup size C*T up to 1024)
+    P = 2
+    c = Case(n, P, seed=n + 3 * variant + 17)
+    ctx.set_variant(n, variant)
+    try:
+        sh, pop = c.population(ctx)
+        pop.run(B.sched_ops([B.op(B.OP_RAAR, count=2, beta=0.9, chi=0.5, which=B.ITER_TRACE),
+                             B.op(B.OP_ER, count=2, chi=0.5, which=B.ITER_TRACE)], ctx))
+        tr = pop.trace()
+        pop.close()
+        sh.close()
+    finally:
+        ctx.set_variant(n, 0)
+    assert tr.shape == (4, P)
+    for p in range(P):
+        _, ref = mpr.sequence_trace(c.rho[p], c.S[p], c.M, c.known, 0.5, "RAAR", 0.9, 2, 2)
+        np.testing.assert_allclose(tr[:, p], ref, rtol=1e-4, atol=1e-6)
+
+
 def test_trace_scope_chunks_and_untraced_ops(ctx, B):
     # children only: parents' columns stay NaN; member chunks smaller than the
     # scope; an untraced op in between adds no row
