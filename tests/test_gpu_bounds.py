@@ -31,7 +31,7 @@ def one_raar(B, ctx):
     return B.sched_ops([B.op(B.OP_RAAR, count=1, beta=0.9, chi=0.5), B.op(B.OP_GET_ERROR)], ctx)
 
 
-@pytest.mark.parametrize("n,fp16", [(64, False), (256, False), (128, True)])
+@pytest.mark.parametrize("n,fp16", [(64, False), (256, False), (128, True), (384, False), (1024, True)])
 def test_bounded_iteration_matches_oracle(ctx, B, n, fp16):
     c = Case(n, 3, seed=n + 31, photons=1e8, gap=4)
     sh = ctx.shot(c.amp32, c.mask8, fp16=fp16)
