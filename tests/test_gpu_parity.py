@@ -369,7 +369,7 @@ def _near_tie(info, tol=1e-4):
     return vals[1] >= vals[0] * (1 - tol)
 
 
-@pytest.mark.parametrize("n,P,structured", [(48, 5, True), (64, 6, True), (64, 5, False), (128, 4, True), (384, 4, True)])
+@pytest.mark.parametrize("n,P,structured", [(48, 5, True), (64, 6, True), (64, 5, False), (128, 4, True), (384, 4, True), (512, 4, True)])
 def test_crossover_parity(ctx, B, n, P, structured):
     c = _aligned_population(n, P, seed=n + P) if structured else Case(n, P, seed=n + 9)
     seed = 3002
