@@ -177,7 +177,7 @@ def _band_compare(got, a_sigma, thr, scale):
     return int(mism.sum()), int(band.sum())
 
 
-@pytest.mark.parametrize("n", (12, 32, 96, 128, 512))
+@pytest.mark.parametrize("n", (12, 32, 96, 128, 512, 1024))
 @pytest.mark.parametrize("sigma", (0.0, 1.0, 2.0))
 def test_shrinkwrap(ctx, B, n, sigma):
     P = 3
@@ -193,7 +193,7 @@ def test_shrinkwrap(ctx, B, n, sigma):
     sh.close()
 
 
-@pytest.mark.parametrize("n", (12, 32, 96, 128, 512))
+@pytest.mark.parametrize("n", (12, 32, 96, 128, 512, 1024))
 @pytest.mark.parametrize("alpha", (1.0, 37.5, 300.4, 5000.0))
 def test_support_area(ctx, B, n, alpha):
     P = 2
