@@ -50,7 +50,7 @@ def copies(n, P, seed):
     return amp, mask, np.stack(xs), np.stack(Ss)
 
 
-@pytest.mark.parametrize("n,P", [(64, 5), (128, 6)])
+@pytest.mark.parametrize("n,P", [(64, 5), (128, 6), (384, 4), (512, 4)])
 def test_average_matches_oracle(ctx, B, n, P):
     amp, mask, xs, Ss = copies(n, P, seed=n)
     M = mpr.to_fft_order(amp.astype(np.float64))

@@ -26,7 +26,7 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("n", [32, 128, 512])
+@pytest.mark.parametrize("n", [32, 128, 384, 512, 1024])
 def test_fp16_single_iteration_and_error(ctx, B, n):
     c = Case(n, 3, seed=n + 5, photons=1e8)
     Mq, s = mpr.fp16_modulus(c.M, c.known)

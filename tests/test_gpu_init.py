@@ -19,7 +19,7 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("n,P,seed", [(12, 3, 5), (64, 4, 2**33 + 7), (96, 2, 11), (256, 3, 123456789)])
+@pytest.mark.parametrize("n,P,seed", [(12, 3, 5), (64, 4, 2**33 + 7), (96, 2, 11), (256, 3, 123456789), (1024, 2, 77)])
 def test_random_phase_start_matches_oracle(ctx, n, P, seed):
     c = Case(n, 1, seed=n)
     sh = c.shot(ctx)

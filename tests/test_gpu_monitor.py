@@ -37,7 +37,7 @@ def check(rec, ref, with_avg):
         assert rec["err_avg"] == ref["err_avg"]
 
 
-@pytest.mark.parametrize("n,P,with_avg", [(64, 5, True), (64, 6, False), (128, 8, True)])
+@pytest.mark.parametrize("n,P,with_avg", [(64, 5, True), (64, 6, False), (128, 8, True), (512, 4, True)])
 def test_monitor_matches_oracle(ctx, B, n, P, with_avg):
     c = Case(n, P, seed=n + P)
     sh, pop = c.population(ctx)
