@@ -276,7 +276,7 @@ def test_twenty_iterations_near_solution(ctx, B, n, alg):
     sh.close()
 
 
-@pytest.mark.parametrize("n", (64, 256, 512))
+@pytest.mark.parametrize("n", (64, 256, 512, 1024))
 @pytest.mark.parametrize("alg", ("HIO", "RAAR"))
 def test_twenty_iterations_random_start(ctx, B, n, alg):
     # From random-phase starts HIO/RAAR amplify rounding-size differences by
