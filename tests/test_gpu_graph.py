@@ -39,8 +39,18 @@ def _same(pa, pb, children=False):
         np.testing.assert_array_equal(u, v)
 
 
-@pytest.mark.parametrize("n", [32, 128])
-def test_population_graph_replays_match_eager(ctx, B, n):
+@pytest.mark.parametrize("n,variant", [(32, 0), (128, 0), (384, 1), (512, 0)])
+def test_population_graph_replays_match_eager(ctx, B, n, variant):
+    # (384, 1): a graph recorded on a size's alternative plan, taken from the
+    # context when the populations are created
+    ctx.set_variant(n, variant)
+    try:
+        _graph_replays(ctx, B, n)
+    finally:
+        ctx.set_variant(n, 0)
+
+
+def _graph_replays(ctx, B, n):
     c = Case(n, 4, seed=n + 1)
     s = B.sched_ops([B.op(B.OP_RAAR, count=3, beta=0.9, chi=0.5), B.op(B.OP_SHRINKWRAP, sigma=1.5, tau=0.1),
                      B.op(B.OP_ER, count=2, chi=0.5),
