@@ -31,10 +31,24 @@ def plain_sched(B, ctx):
                          sigma_end=1.0, tau=0.1, tau_end=0.1)
 
 
-CASES = [(64, 3, 11), (32, 4, 12), (64, 2, 13), (96, 3, 14), (32, 1, 15)]
+CASES = [(64, 3, 11), (32, 4, 12), (64, 2, 13), (96, 3, 14), (32, 1, 15), (256, 2, 16), (256, 3, 17)]
 
 
-def test_batch_equals_alone_bitwise(ctx, B):
+@pytest.mark.parametrize("alt", (False, True))
+def test_batch_equals_alone_bitwise(ctx, B, alt):
+    # alt: every size with two plans runs its alternative (as after tuning)
+    from paper_2409_07413_amd import build
+    sizes = sorted({n for n, _, _ in CASES if n in build.VARIANT_SIZES})
+    for n in sizes:
+        ctx.set_variant(n, 1 if alt else 0)
+    try:
+        _batch_equals_alone(ctx, B)
+    finally:
+        for n in sizes:
+            ctx.set_variant(n, 0)
+
+
+def _batch_equals_alone(ctx, B):
     cases = [Case(n, P, seed=sd) for n, P, sd in CASES]
     # alone
     alone = []
