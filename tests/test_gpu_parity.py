@@ -178,7 +178,7 @@ def _band_compare(got, a_sigma, thr, scale):
 
 
 @pytest.mark.parametrize("n", (12, 32, 96, 128, 512, 1024))
-@pytest.mark.parametrize("sigma", (0.0, 1.0, 2.0))
+@pytest.mark.parametrize("sigma", (0.0, 1.0, 2.0, 3.5, 7.5))
 def test_shrinkwrap(ctx, B, n, sigma):
     P = 3
     c = Case(n, P, seed=n + 3)
