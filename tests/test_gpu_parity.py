@@ -62,6 +62,20 @@ def test_fft2_parity(ctx, n):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("n", (12, 128, 1024))
+def test_fft2_in_place(ctx, n):
+    # the entry point allows in == out: forward then inverse on one buffer
+    import torch
+    x = synth.random_complex((2, n, n), n + 1).astype(np.complex64)
+    buf = torch.from_numpy(x).cuda()
+    ctx.fft2(buf, buf, inverse=False)
+    got = buf.cpu().numpy()
+    assert rel(got, np.stack([mpr.fft2(v.astype(np.complex128)) for v in x])) <= 1e-5
+    ctx.fft2(buf, buf, inverse=True)
+    assert rel(buf.cpu().numpy(), x) <= 1e-5
+    torch.cuda.synchronize()
+
+
 # ---------------------------------------------------------------------------
 # Single operator applications
 # ---------------------------------------------------------------------------
