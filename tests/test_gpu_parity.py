@@ -76,6 +76,39 @@ def test_fft2_in_place(ctx, n):
     torch.cuda.synchronize()
 
 
+def test_device_pointer_forms_equal_host_forms(ctx, B):
+    # SPR_DEVICE_PTRS: shot, population, read and write from device memory
+    # give the same bits as the host forms
+    import torch
+    n, P = 96, 3
+    c = Case(n, P, seed=96 + 41, per_member_supp=True)
+    ops = [B.op(B.OP_RAAR, count=2, beta=0.9, chi=0.5), B.op(B.OP_ER, count=1, chi=0.5), B.op(B.OP_GET_ERROR)]
+    sh, pop = c.population(ctx)
+    run_ops(pop, B, ops)
+    rho_h, supp_h, err_h = pop.read()
+    pop.close()
+    sh.close()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    shd = ctx.shot(dev(c.amp32), dev(c.mask8))
+    popd = shd.population(dev(c.rho32), dev(c.supp8))
+    run_ops(popd, B, ops)
+    rho_d = torch.empty((P, n, n), dtype=torch.complex64, device="cuda")
+    supp_d = torch.empty((P, n, n), dtype=torch.uint8, device="cuda")
+    err_d = torch.empty(P, dtype=torch.float64, device="cuda")
+    popd.read_into(rho_d, supp_d, err_d)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(rho_d.cpu().numpy(), rho_h)
+    np.testing.assert_array_equal(supp_d.cpu().numpy().astype(bool), supp_h.astype(bool))
+    np.testing.assert_array_equal(err_d.cpu().numpy(), err_h)
+    # write from device memory, then read back on the host
+    popd.write(rho=torch.flip(rho_d, dims=(0,)).contiguous(), err=torch.flip(err_d, dims=(0,)).contiguous())
+    rho_b, _, err_b = popd.read()
+    np.testing.assert_array_equal(rho_b, rho_h[::-1])
+    np.testing.assert_array_equal(err_b, err_h[::-1])
+    popd.close()
+    shd.close()
+
+
 # ---------------------------------------------------------------------------
 # Single operator applications
 # ---------------------------------------------------------------------------
