@@ -50,16 +50,28 @@ def copies(n, P, seed):
     return amp, mask, np.stack(xs), np.stack(Ss)
 
 
-@pytest.mark.parametrize("n,P", [(64, 5), (128, 6), (384, 4), (512, 4)])
-def test_average_matches_oracle(ctx, B, n, P):
-    amp, mask, xs, Ss = copies(n, P, seed=n)
+AVG_CASES = [(64, 5, 0), (128, 6, 0), (256, 4, 0), (384, 4, 0), (512, 4, 0), (768, 4, 0), (1024, 4, 0),
+             (256, 4, 1), (384, 4, 1), (512, 4, 1), (768, 4, 1), (1024, 4, 1)]
+
+
+@pytest.mark.parametrize("n,P,variant", AVG_CASES)
+def test_average_matches_oracle(ctx, B, n, P, variant):
+    # every size on both plans of the tuned sizes: Reshift to the best member
+    # (correlations, argmax, alignment), the average spectra and support
+    amp, mask, xs, Ss = copies(n, P, seed=n + 7 * variant)
     M = mpr.to_fft_order(amp.astype(np.float64))
     known = mpr.to_fft_order(mask.astype(bool))
-    sh = ctx.shot(amp, mask)
-    pop = sh.population(xs, Ss.astype(np.uint8))
-    pop.run(B.sched_ops([B.op(B.OP_GET_ERROR), B.op(B.OP_AVERAGE, scope=B.SCOPE_PARENTS)], ctx))
-    rho, supp, e_avg = pop.average()
-    err = pop.errors()
+    if variant:
+        ctx.set_variant(n, variant)
+    try:
+        sh = ctx.shot(amp, mask)
+        pop = sh.population(xs, Ss.astype(np.uint8))
+        pop.run(B.sched_ops([B.op(B.OP_GET_ERROR), B.op(B.OP_AVERAGE, scope=B.SCOPE_PARENTS)], ctx))
+        rho, supp, e_avg = pop.average()
+        err = pop.errors()
+    finally:
+        if variant:
+            ctx.set_variant(n, 0)
     x64 = [x.astype(np.complex128) for x in xs]
     E = [mpr.get_error(x, S, M, known) for x, S in zip(x64, Ss)]
     assert int(np.argmin(err)) == int(np.argmin(E))

@@ -314,3 +314,106 @@ def test_mpr_driver_counts_and_selection(monkeypatch):
             (last["E_par"][p] == last["E_kid"][p] and out["E"][p] == last["E_par"][p])
     # every member has the evaluation support size alpha_eval... then the final SW
     assert all(S.dtype == bool for S in out["S"])
+
+
+@pytest.mark.parametrize("rot", range(len(mpr.ROTATIONS)))
+def test_crossover_map_cells_are_rotated_rectangles(rot):
+    # Fig. crossmap: the map is a tiling of the Fourier domain by t_x x t_y
+    # rectangles, here rotated by the angle atan2(b, a) of the table entry
+    # and shifted by (s_x, s_y), each tile elected at random.  The cells of
+    # the oracle's map are recovered without its integer formula: maps with
+    # the same geometry and 40 different seeds give every pixel a 40-bit
+    # signature, equal on one tile and (almost surely) different on two.
+    # The geometric cells come from floating-point coordinates in the rotated
+    # frame (cos, sin of the angle), half-open at the upper side.
+    n = 48
+    tx, ty, sx, sy = 5, 7, 2, 3
+    params = (tx, ty, sx, sy, rot)
+    sig = np.zeros((n, n), dtype=np.uint64)
+    for k in range(40):
+        m = mpr.crossover_map_with(n, params, 1000 + 7 * k, 1, 0, 0.5)
+        sig |= m.astype(np.uint64) << np.uint64(k)
+    a, b, h = mpr.ROTATIONS[rot]
+    th = np.arctan2(b, a)
+    f = np.where(np.arange(n) < n // 2, np.arange(n), np.arange(n) - n).astype(np.float64)
+    U, V = np.meshgrid(f, f, indexing="ij")          # row frequency u, column frequency v
+    fx = (np.cos(th) * U + np.sin(th) * V + sx) / tx
+    fy = (-np.sin(th) * U + np.cos(th) * V + sy) / ty
+
+    def cell(c):
+        r = np.round(c)
+        # a point on a tile edge (exactly, up to the rounding of cos/sin)
+        # belongs to the tile above it
+        return np.where(np.abs(c - r) < 1e-9, r, np.floor(c)).astype(np.int64)
+
+    cx, cy = cell(fx), cell(fy)
+    cells = {}
+    for i in range(n):
+        for j in range(n):
+            cells.setdefault((cx[i, j], cy[i, j]), set()).add(int(sig[i, j]))
+    # one signature per geometric cell, and distinct cells distinct signatures
+    assert all(len(s) == 1 for s in cells.values())
+    assert len({next(iter(s)) for s in cells.values()}) == len(cells)
+    # the rectangles have the sides drawn: along the rotated axes the cell
+    # index changes every t_x (t_y) units, so the number of cells met by the
+    # grid matches the area of the domain over t_x t_y up to the border cells
+    assert 0.6 < len(cells) * tx * ty / (n * n) < 2.0
+
+
+def test_improve_member_follows_alg_improve(monkeypatch):
+    # Alg. improve for one reconstruction: (R - 2) x [Sequence; UpdateSupport],
+    # Sequence; UpdateSupportSize(alpha_best); Sequence;
+    # UpdateSupportSize(alpha_eval); EvalSequence (ER^j_eval); E <- GetError;
+    # UpdateSupport -- every step fed by the outputs of the previous ones.
+    # Tokens stand for densities and supports so that the data flow is
+    # recorded exactly; alpha_best and alpha_eval differ so a swap is seen.
+    class Tok:
+        def __init__(self, name):
+            self.name = name
+
+    log = []
+    count = {"x": 0, "S": 0}
+
+    def new(kind):
+        count[kind] += 1
+        return Tok(f"{kind}{count[kind]}")
+
+    def seq(x, S, M, known, chi, alg, beta, n_ia, n_er):
+        out = new("x")
+        log.append(("Seq", x.name, S.name, n_ia, n_er, out.name))
+        return out
+
+    def sw(x, S, sigma, tau):
+        out = new("S")
+        log.append(("SW", x.name, S.name, sigma, tau, out.name))
+        return out
+
+    def swsize(x, sigma, alpha):
+        out = new("S")
+        log.append(("SWsize", x.name, sigma, alpha, out.name))
+        return out
+
+    def get_error(x, S, M, known):
+        log.append(("GetError", x.name, S.name))
+        return 0.25
+
+    monkeypatch.setattr(mpr, "sequence", seq)
+    monkeypatch.setattr(mpr, "update_support", sw)
+    monkeypatch.setattr(mpr, "update_support_size", swsize)
+    monkeypatch.setattr(mpr, "get_error", get_error)
+    prm = dict(alg="RAAR", beta=0.9, chi=0.5, G=5, R=4, j=16, j_er=4, j_end=0, j_eval=40,
+               sigma=2.0, sigma_end=0.5, tau=0.1, tau_end=0.05)
+    g = 3
+    jg, jer, sg, tg = mpr.schedule_at(g, 5, 16, 4, 0, 2.0, 0.5, 0.1, 0.05)
+    assert (jg, jer) == (8, 12)
+    stats = {"alpha_best": 123.0, "alpha_eval": 456.5}
+    x, S, E = mpr.improve_member(Tok("x0"), Tok("S0"), None, None, prm, g, stats)
+    assert log == [
+        ("Seq", "x0", "S0", jg, jer, "x1"), ("SW", "x1", "S0", sg, tg, "S1"),
+        ("Seq", "x1", "S1", jg, jer, "x2"), ("SW", "x2", "S1", sg, tg, "S2"),
+        ("Seq", "x2", "S2", jg, jer, "x3"), ("SWsize", "x3", sg, 123.0, "S3"),
+        ("Seq", "x3", "S3", jg, jer, "x4"), ("SWsize", "x4", sg, 456.5, "S4"),
+        ("Seq", "x4", "S4", 0, 40, "x5"),
+        ("GetError", "x5", "S4"),
+        ("SW", "x5", "S4", sg, tg, "S5")]
+    assert (x.name, S.name, E) == ("x5", "S5", 0.25)
