@@ -330,7 +330,8 @@ def test_twenty_iterations_near_solution(ctx, B, n, alg):
             gated += 1
         print(f"{alg} near solution {n}^2 member {p}: rel L2 {r:.2e}, oracle self-sensitivity {sens:.2e}"
               f" ({'gated at 1e-3' if sens < 1e-4 else 'reported only'})")
-    if alg == "RAAR":
+    if alg == "RAAR" and n <= 128:
+        # measured: the oracle's own sensitivity stays below 1e-4 here
         assert gated == P
     pop.close()
     sh.close()
