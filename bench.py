@@ -309,6 +309,41 @@ def size_sweep(ctx, B, iters=20):
     return out
 
 
+def steady_loop(ctx, B, n, members, iters, variant=0):
+    """One warm-up pass and one timed pass of RAAR^iters then ER^iters on
+    `members` random members of a synthetic N x N shot (24 x 24 beamstop,
+    4-px gap), all members in one launch chunk: the launches a kernel profile
+    of the projection loop is taken over."""
+    import torch
+    from paper_2409_07413_amd import synth
+    rng = np.random.default_rng(0)
+    amp = np.abs(rng.standard_normal((n, n))).astype(np.float32)
+    mask = synth.beamstop_gap_mask(n, 24, 4).astype(np.uint8)
+    rho = (rng.standard_normal((members, n, n)) + 1j * rng.standard_normal((members, n, n))).astype(np.complex64)
+    supp = synth.centred_square(n, n // 3).astype(np.uint8)
+    ctx.set_cache_budget(members * 2 * n * n * 8)
+    ctx.set_variant(n, variant)
+    shot = ctx.shot(amp, mask)
+    pop = shot.population(rho, supp)
+    s = B.sched_ops([B.op(B.OP_RAAR, count=iters, beta=0.9), B.op(B.OP_ER, count=iters)], ctx)
+    stream = torch.cuda.Stream()
+    pop.run(s, stream)
+    pop.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    pop.run(s, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    pop.close()
+    shot.close()
+    s.close()
+    ctx.set_variant(n, 0)
+    ctx.set_cache_budget(CACHE_BUDGET)
+    return {"n": n, "members": members, "iterations": 2 * iters, "variant": variant,
+            "ms": ms, "member_iterations_per_s": members * 2 * iters / (ms * 1e-3)}
+
+
 def graph_study(ctx, B, passes=10):
     """The plain schedule (10 blocks of HIO^j ER^(20-j), shrink-wrap each) run
     eagerly and replayed from a captured graph on twin populations."""
@@ -526,7 +561,18 @@ def main():
     ap.add_argument("--mpr-1024", action="store_true", help="1024^2 MPR run (20 generations) and exit")
     ap.add_argument("--batch-study", action="store_true",
                     help="32 uneven shots: one at a time, one batch, one captured batch (after tuning) and exit")
+    ap.add_argument("--loop", type=str, default=None, metavar="N,MEMBERS,ITERS[,VARIANT]",
+                    help="steady-state projection loop only (RAAR^ITERS then ER^ITERS on MEMBERS random members "
+                         "of one N x N shot, one launch chunk), for kernel profiles, and exit")
     args = ap.parse_args()
+    if args.loop:
+        import torch  # noqa: F401
+        from paper_2409_07413_amd import binding as B
+        v = [int(t) for t in args.loop.split(",")]
+        ctx = B.Context(0)
+        print(json.dumps({"loop": steady_loop(ctx, B, *v)}), flush=True)
+        ctx.close()
+        return
     if args.copy_calibration:
         copy_calibration()
         return

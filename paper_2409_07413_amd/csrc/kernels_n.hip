@@ -125,16 +125,20 @@ __device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
 
 // The modulus values of a column tile's elements t + T*m of column col; the
 // storage form (FP32 or FP16) is uniform, so it is resolved once.
-__device__ __forceinline__ void load_col_amp(float (&mv)[E], const SlotDesc& d, int t, int col) {
-  if (d.amp16) {
-    GPtr<unsigned short> p = gview(reinterpret_cast<const unsigned short*>(d.amp16));
+__device__ __forceinline__ void load_col_amp(float (&mv)[E], const float* amp, const __half* amp16, int t,
+                                             int col) {
+  if (amp16) {
+    GPtr<unsigned short> p = gview(reinterpret_cast<const unsigned short*>(amp16));
 #pragma unroll
     for (int m = 0; m < E; ++m) mv[m] = __half2float(__ushort_as_half(p[(size_t)(t + T * m) * N + col]));
   } else {
-    GPtr<float> p = gview(d.amp);
+    GPtr<float> p = gview(amp);
 #pragma unroll
     for (int m = 0; m < E; ++m) mv[m] = p[(size_t)(t + T * m) * N + col];
   }
+}
+__device__ __forceinline__ void load_col_amp(float (&mv)[E], const SlotDesc& d, int t, int col) {
+  load_col_amp(mv, d.amp, d.amp16, t, col);
 }
 
 template <int M> using ModeC = std::integral_constant<int, M>;
@@ -245,28 +249,15 @@ __global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
 // ---------------------------------------------------------------------------
 // Column projection: column FFT -> masked P_M -> column IFFT.
 // ---------------------------------------------------------------------------
-// TRACE also sums the FP64 residual Xi (|X| - M)^2 of the spectrum being
-// projected over the tile (the iterate's Fourier error, before P_M).
+// One member's column tile, loaded into v (and its modulus values into mv):
+// transform, project, transform back, store into dst.  TRACE also sums the
+// FP64 residual Xi (|X| - M)^2 of the spectrum being projected over the tile
+// (the iterate's Fourier error, before P_M) and writes it to *trace_out.
 template <bool TRACE>
-__global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
-  extern __shared__ float2 lds[];
-  const int tid = threadIdx.x;
-  const int c = tid % C, t = tid / C;
-  const TileId id = col_tile_id();
-  const int col = id.tile * C + c;
-  float2* dst = a.Y + (size_t)id.img * NN;
-  const SlotDesc d = a.desc[a.slots[id.img]];
-  const float2* src = a.t_by_slot ? d.T : a.T + (size_t)id.img * NN;
-  const float amp_scale = d.amp_scale;
-  float2 v[E];
-  float mv[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = gload(src, (size_t)(t + T * m) * N + col);
-  load_col_amp(mv, d, t, col);
-  issue_fence();
-  TwSet<N> ws;
-  load_twiddle_set<N>(ws, t, a.tw);
-  fft<N, -1, ColL>(v, lds + c, t, a.tw, ws);
+__device__ __forceinline__ void col_proj_tile(float2 (&v)[E], const float (&mv)[E], float amp_scale, float2* lds,
+                                              int tid, int c, int t, int col, const TwSet<N>& ws,
+                                              const float2* __restrict__ tw, float2* dst, double* trace_out) {
+  fft<N, -1, ColL>(v, lds + c, t, tw, ws);
   const float inv = 1.0f / (float)N;
   double acc = 0.0;
   if constexpr (TRACE) {
@@ -281,7 +272,7 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
   }
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = modulus_replace(v[m], mv[m], amp_scale, inv);
-  fft<N, +1, ColL>(v, lds + c, t, a.tw, ws);
+  fft<N, +1, ColL>(v, lds + c, t, tw, ws);
 #pragma unroll
   for (int m = 0; m < E; ++m) dst[(size_t)(t + T * m) * N + col] = v[m];
   if constexpr (TRACE) {
@@ -292,9 +283,32 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
     if (tid == 0) {
       double sum = 0.0;
       for (int w = 0; w < (C * T + 63) / 64; ++w) sum += wsum[w];
-      a.trace_partial[(size_t)id.img * (N / C) + id.tile] = sum;
+      *trace_out = sum;
     }
+    __syncthreads();  // the tile buffer is reused by the next transform
   }
+}
+
+template <bool TRACE>
+__global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+  const int c = tid % C, t = tid / C;
+  const TileId id = col_tile_id();
+  const int col = id.tile * C + c;
+  float2* dst = a.Y + (size_t)id.img * NN;
+  const SlotDesc d = a.desc[a.slots[id.img]];
+  const float2* src = a.t_by_slot ? d.T : a.T + (size_t)id.img * NN;
+  float2 v[E];
+  float mv[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = gload(src, (size_t)(t + T * m) * N + col);
+  load_col_amp(mv, d, t, col);
+  issue_fence();
+  TwSet<N> ws;
+  load_twiddle_set<N>(ws, t, a.tw);
+  col_proj_tile<TRACE>(v, mv, d.amp_scale, lds, tid, c, t, col, ws, a.tw, dst,
+                       TRACE ? a.trace_partial + (size_t)id.img * (N / C) + id.tile : nullptr);
 }
 
 // ---------------------------------------------------------------------------

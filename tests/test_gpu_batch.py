@@ -34,6 +34,38 @@ def plain_sched(B, ctx):
 CASES = [(64, 3, 11), (32, 4, 12), (64, 2, 13), (96, 3, 14), (32, 1, 15), (256, 2, 16), (256, 3, 17)]
 
 
+def test_batch_of_many_members_equals_alone_bitwise(ctx, B):
+    # two shots of each size share every launch (their members reach their
+    # own modulus through the slot descriptors): the same bits as alone
+    cases = [Case(n, P, seed=sd) for n, P, sd in ((512, 12, 31), (512, 12, 32), (1024, 3, 33), (1024, 3, 34))]
+    ctx.set_cache_budget(1 << 30)
+    try:
+        alone = []
+        for c in cases:
+            sh, pop = c.population(ctx)
+            pop.run(plain_sched(B, ctx))
+            alone.append(pop.read())
+            pop.close()
+            sh.close()
+        shots, pops = [], []
+        for c in cases:
+            sh, pop = c.population(ctx)
+            shots.append(sh)
+            pops.append(pop)
+        ctx.run_batch(pops, [plain_sched(B, ctx) for _ in cases])
+        for pop, (rho_a, supp_a, err_a) in zip(pops, alone):
+            rho, supp, err = pop.read()
+            np.testing.assert_array_equal(rho, rho_a)
+            np.testing.assert_array_equal(supp, supp_a)
+            np.testing.assert_array_equal(err, err_a)
+        for pop in pops:
+            pop.close()
+        for sh in shots:
+            sh.close()
+    finally:
+        ctx.set_cache_budget(256 << 20)
+
+
 @pytest.mark.parametrize("alt", (False, True))
 def test_batch_equals_alone_bitwise(ctx, B, alt):
     # alt: every size with two plans runs its alternative (as after tuning)

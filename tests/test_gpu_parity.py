@@ -605,6 +605,47 @@ def test_mpr_one_generation_small(ctx, B, n, P, seed):
 
 
 # ---------------------------------------------------------------------------
+# Launches of many members (one launch chunk of the whole population) against
+# a launch of two of them: a member's arithmetic does not depend on the launch,
+# so both give the same bits, and sampled members match the oracle.
+# ---------------------------------------------------------------------------
+MANY = [(256, 0, 64), (256, 1, 64), (384, 0, 40), (384, 1, 40), (512, 0, 40), (512, 1, 40),
+        (768, 0, 24), (768, 1, 24), (1024, 0, 24), (1024, 1, 24)]
+
+
+@pytest.mark.parametrize("n,variant,P", MANY)
+def test_many_member_launch(ctx, B, n, variant, P):
+    c = Case(n, P, seed=n + 71 * variant + P)
+    ops = [B.op(B.OP_RAAR, count=2, beta=0.9, chi=0.5, which=B.ITER_TRACE),
+           B.op(B.OP_ER, count=1, chi=0.5, which=B.ITER_TRACE), B.op(B.OP_GET_ERROR)]
+    ctx.set_variant(n, variant)
+    ctx.set_cache_budget(P * 2 * n * n * 8)  # one launch chunk of all members
+    try:
+        sh, pop = c.population(ctx)
+        run_ops(pop, B, ops)
+        rho, _, err = pop.read()
+        tr = pop.trace()
+        pop.close()
+        few = sh.population(c.rho32[:2], c.supp8[:2])
+        run_ops(few, B, ops)
+        rho2, _, err2 = few.read()
+        tr2 = few.trace()
+        few.close()
+        sh.close()
+    finally:
+        ctx.set_variant(n, 0)
+        ctx.set_cache_budget(256 << 20)
+    np.testing.assert_array_equal(rho[:2], rho2)
+    np.testing.assert_array_equal(err[:2], err2)
+    np.testing.assert_array_equal(tr[:, :2], tr2)
+    for p in (0, P // 2, P - 1):
+        ref = mpr.sequence(c.rho[p], c.S[p], c.M, c.known, 0.5, "RAAR", 0.9, 2, 1)
+        assert rel(rho[p], ref) <= 1e-5, p
+        e_ref = mpr.get_error(ref, c.S[p], c.M, c.known)
+        assert abs(err[p] - e_ref) <= 1e-5 * e_ref
+
+
+# ---------------------------------------------------------------------------
 # Full-size launch configuration of the benchmark: 512^2, P = 64 memetic
 # (128 members), sampled members checked against the oracle one by one.
 # ---------------------------------------------------------------------------
