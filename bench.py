@@ -92,36 +92,122 @@ def measured_traffic(kernel_key, chunk):
     return t.get("kernels", {}).get(str(kernel_key), {}).get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(sh, rho0, supp0, seconds_target=15.0):
-    """FP64 oracle RAAR iterations at 512^2 on the host cores (bounded sample)."""
+def trace_averages(chunk):
+    """Average kernel durations (us) of the loop kernels from the committed
+    rocprofv3 kernel trace of the benchmark (profiles/kernel_trace_512_pop64.json),
+    or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "kernel_trace_512_pop64.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except ValueError:
+        return None
+    if t.get("sources_digest") != kernel_sources_digest() or t.get("members_per_launch") != chunk:
+        return None
+    return {k: v.get("avg_us") for k, v in t.get("kernels", {}).items()}
+
+
+CPU_WORKERS_MAX = 16  # the host-core share of one GPU on the benchmark machines
+
+
+def gpu_step_check(ctx, B, amp, mask, rho, supp):
+    """The library's RAAR step (beta 0.9, chi 0.5) and ER step with the fitness
+    after it, from given states of one shot: the device side of the oracle
+    check (a fresh population per step; nothing else runs on it)."""
+    shot = ctx.shot(amp, mask)
+    pop = shot.population(rho, supp)
+    pop.run(B.sched_ops([B.op(B.OP_RAAR, count=1, beta=0.9, chi=0.5)], ctx))
+    raar, _, _ = pop.read()
+    pop.close()
+    pop = shot.population(rho, supp)
+    pop.run(B.sched_ops([B.op(B.OP_ER, count=1, chi=0.5), B.op(B.OP_GET_ERROR)], ctx))
+    er, _, err = pop.read()
+    pop.close()
+    shot.close()
+    return {"amp": amp, "mask": mask, "rho": rho, "supp": supp, "raar": raar, "er": er, "err": err}
+
+
+def _oracle_timed(a):
+    """Worker: k RAAR then k ER oracle iterations on one member; seconds."""
+    from oracle import mpr
+    x, S, M, known, k = a
+    t0 = time.perf_counter()
+    mpr.sequence(x.astype(np.complex128), S, M, known, 0.5, "RAAR", 0.9, k, 0)
+    mpr.sequence(x.astype(np.complex128), S, M, known, 0.5, "RAAR", 0.9, 0, k)
+    return time.perf_counter() - t0
+
+
+def _oracle_check(a):
+    """Worker: one member's oracle RAAR step, ER step and fitness, against the
+    device's; relative L2 errors and the fitness's relative error."""
+    from oracle import mpr
+    x, S, M, known, g_raar, g_er, g_err = a
+    x = x.astype(np.complex128)
+    ref_raar = mpr.raar(x, S, M, known, 0.5, 0.9)
+    ref_er = mpr.er(x, S, M, known, 0.5)
+    ref_e = mpr.get_error(ref_er, S, M, known)
+
+    def rel(u, v):
+        return float(np.linalg.norm(u - v) / np.linalg.norm(v))
+    return rel(g_raar, ref_raar), rel(g_er, ref_er), abs(g_err - ref_e) / ref_e
+
+
+def oracle_pool():
+    """Worker processes for the oracle leg, started before this process
+    initialises the GPU (they never touch it)."""
     import multiprocessing as mp
-    from oracle import mpr
-    workers = max(1, min(16, len(os.sched_getaffinity(0))))
-    M = mpr.to_fft_order(sh["amp"])
-    known = mpr.to_fft_order(sh["mask"])
-    S = supp0.astype(bool)
-    # calibrate: one member, 2 iterations
-    t0 = time.perf_counter()
-    mpr.sequence(rho0[0].astype(np.complex128), S, M, known, 0.5, "RAAR", 0.9, 2, 0)
-    per_it = (time.perf_counter() - t0) / 2
-    iters = int(max(2, min(40, seconds_target / max(per_it, 1e-3))))
-    members = workers
-    args = [(rho0[p % P], S, M, known, iters) for p in range(members)]
-    t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(workers) as pool:
-        pool.map(_oracle_member, args)
-    dt = time.perf_counter() - t0
-    return {"value": members * iters / dt, "unit": "member-iterations/s", "cores": workers,
-            "kind": "oracle",
-            "sample": f"{members} members x {iters} RAAR iterations (beta 0.9, chi 0.5) at 512x512, "
-                      f"FP64 NumPy oracle, one process per member over {workers} host cores"}
+    workers = max(1, min(CPU_WORKERS_MAX, len(os.sched_getaffinity(0))))
+    return mp.get_context("spawn").Pool(workers), workers
 
 
-def _oracle_member(a):
+def cpu_baseline(states, checks, pool, workers, seconds_target=20.0):
+    """The FP64 oracle on the host cores (reported, not the target), plus the
+    device's error against it.
+
+    Timing: k RAAR then k ER iterations on each of the benchmark's 64 parent
+    states (after the timed generations), one process per member over
+    min(16, affinity) workers (the host share of one GPU); k is chosen so
+    that the whole sample is about `seconds_target` of CPU work.  Also the
+    single-core rate of one member.  Checks: for each (shot, states, device
+    step results), the oracle's RAAR and ER steps and fitness from the same
+    states (`gpu_step_check`)."""
     from oracle import mpr
-    x, S, M, known, iters = a
-    mpr.sequence(x.astype(np.complex128), S, M, known, 0.5, "RAAR", 0.9, iters, 0)
-    return 0
+    amp, mask, rho, supp = states
+    M = mpr.to_fft_order(amp.astype(np.float64))
+    known = mpr.to_fft_order(mask.astype(bool))
+    affinity = len(os.sched_getaffinity(0))
+    members = rho.shape[0]
+    # single core: one member, one RAAR and one ER iteration (also calibrates k)
+    t_one = _oracle_timed((rho[0], supp[0], M, known, 1))
+    single = 2.0 / t_one
+    k = int(max(1, min(20, round(seconds_target / (2 * members * (t_one / 2))))))
+    t0 = time.perf_counter()
+    pool.map(_oracle_timed, [(rho[p], supp[p], M, known, k) for p in range(members)])
+    wall = time.perf_counter() - t0
+    jobs, tags = [], []
+    for c in checks:
+        Mc = mpr.to_fft_order(c["amp"].astype(np.float64))
+        kc = mpr.to_fft_order(c["mask"].astype(bool))
+        for p in range(c["rho"].shape[0]):
+            jobs.append((c["rho"][p], c["supp"][p], Mc, kc, c["raar"][p], c["er"][p], float(c["err"][p])))
+            tags.append(c["tag"])
+    res = pool.map(_oracle_check, jobs)
+    check = {}
+    for tag, (r1, r2, r3) in zip(tags, res):
+        d = check.setdefault(tag, {"members": 0, "raar_step_rel_l2_max": 0.0, "er_step_rel_l2_max": 0.0,
+                                   "fitness_rel_max": 0.0})
+        d["members"] += 1
+        d["raar_step_rel_l2_max"] = max(d["raar_step_rel_l2_max"], r1)
+        d["er_step_rel_l2_max"] = max(d["er_step_rel_l2_max"], r2)
+        d["fitness_rel_max"] = max(d["fitness_rel_max"], r3)
+    base = {"value": members * 2 * k / wall, "unit": "member-iterations/s", "cores": workers, "kind": "oracle",
+            "sample": f"{members} parent states of the benchmark population after the timed generations, "
+                      f"{k} RAAR (beta 0.9, chi 0.5) then {k} ER iterations each at {rho.shape[1]}x{rho.shape[1]}, "
+                      f"FP64 NumPy oracle, one process per member over {workers} host cores",
+            "single_core_value": single, "cpu_count": os.cpu_count(), "affinity": affinity,
+            "seconds": wall}
+    return base, check
 
 
 # ---------------------------------------------------------------------------
@@ -193,16 +279,19 @@ def run_served(ctx, B, pool, supp, stream, max_shots, budget, warm=True, shortes
         tickets.append(sv.submit(amp, mask, supp[int(n)], seed=5000 + i, arrival=target + off))
     if not sv.drain(600.0):
         raise RuntimeError("served stream did not finish")
-    res = [sv.poll(t, want_data=False) for t in tickets]
+    last = {int(n): i for i, n in enumerate(sizes)}  # the last shot of every size keeps its data
+    res = [sv.poll(t, want_data=(last.get(int(n)) == i)) for i, (t, n) in enumerate(zip(tickets, sizes))]
     st = sv.stats()
     sv.close()
     sched.close()
+    samples = [(int(sizes[i]), int(picks[i]), res[i]["rho"], res[i]["supp"]) for i in sorted(last.values())]
     lat = [r["t_finish"] - r["t_arrival"] for r in res]
     out = _latency_summary(lat, min(r["t_arrival"] for r in res), [r["t_finish"] for r in res], len(res),
                            float(sum(int(n) ** 2 for n in sizes)))
     out.update({"max_resident": st["max_active"], "ticks": st["ticks"], "launches": st["launches"],
                 "peak_shot_bytes": st["bytes_peak"], "max_shots": max_shots,
                 "policy": "shortest-first" if shortest else "all"})
+    out["_samples"] = samples
     return out
 
 
@@ -262,6 +351,23 @@ def serving_leg(ctx, B, rates, count, max_shots, budget, forms=("served", "plain
                     + json.dumps({k: round(v, 3) for k, v in rec[form].items() if isinstance(v, float)}))
         out.append(rec)
     return out
+
+
+def served_checks(ctx, B, srv):
+    """Device steps from the served results kept by the serving leg (the best
+    member of the last shot of every size at the first rate) for the oracle
+    check; removes the kept data from the records."""
+    pool, _ = serving_pool()
+    checks = []
+    for rec in srv:
+        samples = rec.get("served", {}).pop("_samples", None)
+        if samples and not checks:
+            for n, k, rho, supp in samples:
+                amp, mask = pool[n][k]
+                c = gpu_step_check(ctx, B, amp, mask, rho, supp.astype(np.uint8))
+                c["tag"] = "served"
+                checks.append(c)
+    return checks
 
 
 # ---------------------------------------------------------------------------
@@ -531,6 +637,129 @@ def copy_calibration():
                       "GBps_read_plus_write": 2 * n * 8 / (ms * 1e-3) / 1e9}), flush=True)
 
 
+# ---------------------------------------------------------------------------
+# Summaries of rocprofv3 outputs (kernel traces and counter collections)
+# ---------------------------------------------------------------------------
+def _rocprof_rows(d, kind):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", f"*_{kind}.csv"), recursive=True)):
+        rows += list(csv.DictReader(open(f)))
+    if not rows:
+        raise SystemExit(f"no *_{kind}.csv under {d}")
+    return rows
+
+
+def _loop_kernel_key(name):
+    """Kernel key of a loop kernel's demangled name, or None."""
+    base = name.replace("void ", "").replace("spr::(anonymous namespace)::", "").split("(")[0]
+    if base.startswith("k_col_proj"):
+        return "k_col_proj"
+    if base == "k_row_update<1>":
+        return "k_row_update_er"
+    if base.startswith("k_row_update<"):
+        return "k_row_update_ia"
+    if base == "k_row_ingest":
+        return "k_row_ingest"
+    if "copyBuffer" in base:
+        return "copy"
+    return None
+
+
+def profile_summary(d):
+    """profiles/kernel_trace_512_pop64.json and profiles/traffic_512_pop64.json
+    from the rocprofv3 outputs of the benchmark under d: d/trace (kernel trace),
+    d/fetch and d/write (FETCH_SIZE, WRITE_SIZE) of `bench.py --steps 2 --warmup
+    1 --no-cpu-baseline --no-serve`, and d/fetch_cal, d/write_cal of `bench.py
+    --copy-calibration` (256 MiB read + written per copy)."""
+    chunk = min(2 * P, max(1, CACHE_BUDGET // (2 * N * N * 8)))
+    digest = kernel_sources_digest()
+    dur = {}
+    for r in _rocprof_rows(os.path.join(d, "trace"), "kernel_trace"):
+        k = _loop_kernel_key(r["Kernel_Name"])
+        if k and k != "copy":
+            dur.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    trace = {"workload": "bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-serve (512x512, 128 members, "
+                         f"{chunk} per launch)", "members_per_launch": chunk, "sources_digest": digest,
+             "kernels": {k: {"calls": len(v), "avg_us": float(np.mean(v)), "median_us": float(np.median(v))}
+                         for k, v in sorted(dur.items())}}
+
+    def counter(sub, name):
+        vals = {}
+        for r in _rocprof_rows(os.path.join(d, sub), "counter_collection"):
+            if r["Counter_Name"] != name:
+                continue
+            k = _loop_kernel_key(r["Kernel_Name"])
+            if k:
+                vals.setdefault(k, []).append(float(r["Counter_Value"]))
+        return vals
+    fcal, wcal = counter("fetch_cal", "FETCH_SIZE")["copy"], counter("write_cal", "WRITE_SIZE")["copy"]
+    copy_bytes = 256 << 20
+    fetch_factor = copy_bytes / (max(fcal) * 1024)
+    write_factor = copy_bytes / (max(wcal) * 1024)
+    fetch, write = counter("fetch", "FETCH_SIZE"), counter("write", "WRITE_SIZE")
+    alg = {"k_col_proj": algorithmic_bytes_per_px(1, chunk), "k_row_update_er": algorithmic_bytes_per_px(2, chunk),
+           "k_row_update_ia": algorithmic_bytes_per_px(3, chunk), "k_row_ingest": algorithmic_bytes_per_px(0, chunk)}
+    kern = {}
+    for k in sorted(fetch):
+        if k == "copy" or k not in write:
+            continue
+        f, w = float(np.mean(fetch[k])), float(np.mean(write[k]))
+        hbm = (f * fetch_factor + w * write_factor) * 1024
+        a = alg[k] * N * N * chunk
+        kern[k] = {"dispatches": len(fetch[k]), "FETCH_SIZE_KiB_avg": f, "WRITE_SIZE_KiB_avg": w,
+                   "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": a, "ratio_to_algorithmic": hbm / a}
+    traffic = {"workload": trace["workload"], "members_per_launch": chunk, "sources_digest": digest,
+               "copy_calibration": {"bytes_read": copy_bytes, "bytes_written": copy_bytes,
+                                    "FETCH_SIZE_KiB": max(fcal), "WRITE_SIZE_KiB": max(wcal),
+                                    "fetch_factor": fetch_factor, "write_factor": write_factor},
+               "kernels": kern}
+    for name, obj in (("kernel_trace_512_pop64.json", trace), ("traffic_512_pop64.json", traffic)):
+        with open(os.path.join(ROOT, "profiles", name), "w") as fh:
+            json.dump(obj, fh, indent=1)
+    print(json.dumps({"trace": trace, "traffic": traffic}, indent=1))
+
+
+def counter_summary(d, sizes=("512", "1024")):
+    """Markdown table of the loop kernels' hardware counters from the passes
+    under d (d/p1_<n> ... d/p4_<n>, `bench.py --loop` runs): VALU busy, VALU
+    instructions per wave, mean resident waves per CU, LDS bank-conflict
+    share, memory-unit busy and stalled, average L2 read latency."""
+    rows = []
+    for n in sizes:
+        acc = {}
+        for pss in ("p1", "p2", "p3", "p4"):
+            for r in _rocprof_rows(os.path.join(d, f"{pss}_{n}"), "counter_collection"):
+                k = _loop_kernel_key(r["Kernel_Name"])
+                if k in (None, "copy", "k_row_ingest"):
+                    continue
+                acc.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        for k, c in sorted(acc.items()):
+            m = {name: float(np.mean(v)) for name, v in c.items()}
+            cus, ses, xcds = 256, 32, 8
+            gui = m["GRBM_GUI_ACTIVE"] / xcds  # cycles of one XCD (the counter sums the 8)
+            rows.append({
+                "n": n, "kernel": k,
+                "VALU busy %": 100 * m["SQ_ACTIVE_INST_VALU"] / cus / gui,
+                "VALU instr per wave": m["SQ_INSTS_VALU"] / m["SQ_WAVES"],
+                "waves per CU (mean)": m.get("MeanOccupancyPerCU", float("nan")),
+                "LDS bank conflict %": 100 * m["SQ_LDS_BANK_CONFLICT"] / cus / gui,
+                "LDS instr per wave": m["SQ_INSTS_LDS"] / m["SQ_WAVES"],
+                "TA busy %": 100 * m["TA_TA_BUSY_sum"] / cus / gui,
+                "TCP data stall %": 100 * m["TCP_TCP_TA_DATA_STALL_CYCLES_sum"] / cus / gui,
+                "L2 read latency (cycles)": m["TCP_TCC_READ_REQ_LATENCY_sum"] / m["TCP_TCC_READ_REQ_sum"],
+                "L2 read requests per wave": m["TCP_TCC_READ_REQ_sum"] / m["SQ_WAVES"],
+                "vector memory instr per wave": (m["SQ_INSTS_VMEM_RD"] + m["SQ_INSTS_VMEM_WR"]) / m["SQ_WAVES"],
+                "wait for dependencies % of wave time": 100 * m["SQ_WAIT_INST_ANY"] / m["SQ_WAVE_CYCLES"],
+            })
+    keys = list(rows[0].keys())
+    print("| " + " | ".join(keys) + " |")
+    print("|" + "---|" * len(keys))
+    for r in rows:
+        print("| " + " | ".join(f"{v:.1f}" if isinstance(v, float) else str(v) for v in r.values()) + " |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -564,7 +793,18 @@ def main():
     ap.add_argument("--loop", type=str, default=None, metavar="N,MEMBERS,ITERS[,VARIANT]",
                     help="steady-state projection loop only (RAAR^ITERS then ER^ITERS on MEMBERS random members "
                          "of one N x N shot, one launch chunk), for kernel profiles, and exit")
+    ap.add_argument("--profile-summary", type=str, default=None, metavar="DIR",
+                    help="write profiles/kernel_trace_512_pop64.json and profiles/traffic_512_pop64.json from "
+                         "rocprofv3 outputs under DIR (trace, fetch, write, fetch_cal, write_cal) and exit")
+    ap.add_argument("--counter-summary", type=str, default=None, metavar="DIR",
+                    help="print a table of the loop kernels' counters from rocprofv3 passes under DIR and exit")
     args = ap.parse_args()
+    if args.profile_summary:
+        profile_summary(args.profile_summary)
+        return
+    if args.counter_summary:
+        counter_summary(args.counter_summary)
+        return
     if args.loop:
         import torch  # noqa: F401
         from paper_2409_07413_amd import binding as B
@@ -631,9 +871,8 @@ def main():
         sys.exit(2)
 
     sh, rho0, supp0 = make_inputs()
-    # the oracle leg runs first, in forked worker processes, before anything
-    # touches the GPU in this process
-    base = None if args.no_cpu_baseline else cpu_baseline(sh, rho0, supp0)
+    # the oracle leg's worker processes start before anything touches the GPU
+    pool = None if args.no_cpu_baseline else oracle_pool()
 
     import torch
     from paper_2409_07413_amd import binding as B
@@ -688,6 +927,18 @@ def main():
         if nk:
             kern[k] = (nk, mk)
 
+    # the parents after the timed generations: the CPU baseline's sample, and
+    # four of them for the device-against-oracle check
+    amp32, mask8 = sh["amp"].astype(np.float32), sh["mask"].astype(np.uint8)
+    st_rho, st_supp, _ = pop.read()
+    st_supp = st_supp.astype(np.uint8)
+    checks = []
+    if not args.no_cpu_baseline:
+        pick = [0, P // 3, 2 * P // 3, P - 1]
+        c = gpu_step_check(ctx, B, amp32, mask8, st_rho[pick], st_supp[pick])
+        c["tag"] = "benchmark"
+        checks.append(c)
+
     member_its = 2 * P * (R * (J + J_ER) + J_EVAL) * args.steps
     value = member_its / wall
     chunk = min(2 * P, max(1, CACHE_BUDGET // (2 * N * N * 8)))
@@ -709,6 +960,16 @@ def main():
                 "traffic": measured_traffic(B.KERNEL_COL_PROJ, chunk), "launches": n_cp,
                 "avg_launch_us": ms_cp / n_cp * 1e3, "timed_ms": ms_cp, "algorithmic_bytes_per_launch": cp_bytes,
                 "sample_every": args.timing_every}
+    tr = trace_averages(chunk)
+    if tr is not None:
+        er_us, ia_us, cp_us = tr.get("k_row_update_er"), tr.get("k_row_update_ia"), tr.get("k_col_proj")
+        if er_us and ia_us:
+            us = (n_er * er_us + n_ia * ia_us) / n_l
+            roof_row["trace_avg_launch_us"] = us
+            roof_row["trace_frac"] = bytes_per_launch / (us * 1e-6) / 1e9 / HBM_PEAK_GBS
+        if cp_us:
+            roof_col["trace_avg_launch_us"] = cp_us
+            roof_col["trace_frac"] = cp_bytes / (cp_us * 1e-6) / 1e9 / HBM_PEAK_GBS
     # the dominant kernel: the larger share of event-timed time in the timed region
     roofline = roof_row if ms >= ms_cp else roof_col
     # whole-step algorithmic bytes: iterations only (ingest/shrink-wrap/fitness/crossover excluded)
@@ -752,6 +1013,7 @@ def main():
     }
     pop.close()
     shot.close()
+    srv = None
     if not args.no_serve:
         srv = serving_leg(ctx, B, rates, counts, args.serve_max_shots, int(args.serve_budget_gib * (1 << 30)),
                           forms, log, shortest=args.serve_policy == "shortest", tune=not args.serve_no_tune)
@@ -763,9 +1025,21 @@ def main():
         if "served" in srv[0]:
             out["shot_latency_p50_ms"] = srv[0]["served"]["p50_ms"]
             out["shot_latency_p99_ms"] = srv[0]["served"]["p99_ms"]
-    if base is not None:
+        if not args.no_cpu_baseline:
+            checks += served_checks(ctx, B, srv)
+        for rec in srv:
+            rec.get("served", {}).pop("_samples", None)
+    if not args.no_cpu_baseline:
+        # the oracle runs in spawned worker processes (none of them touches the GPU)
+        base, check = cpu_baseline((amp32, mask8, st_rho, st_supp), checks, *pool)
+        pool[0].close()
+        pool[0].join()
         out["cpu_baseline"] = base
         out["gpu_over_oracle"] = value / base["value"]
+        out["oracle_check"] = dict(check, bars={"step_rel_l2": 1e-5, "fitness_rel": 1e-5}, what=(
+            "one RAAR step and one ER step with the Eq. error_calc fitness, from device states, on the device "
+            "and in the FP64 oracle: 4 parents of the benchmark population after the timed generations, and the "
+            "best member of the last served shot of every size"))
     print(json.dumps(out), flush=True)
 
 

@@ -185,14 +185,21 @@ struct ColMixArgs {
   const float* Mavg;     // (|F[rho_avg]| + mean |F[rho_p]|) / 2, FFT order (used when c_a > 0)
 };
 
-// Per-size kernel table.
+// Optional events that the dispatch of a kernel records at its start and end
+// (its own execution interval, as a kernel trace reports it).
+struct LaunchEvents {
+  hipEvent_t start, stop;
+};
+
+// Per-size kernel table.  The projection-loop launchers take optional
+// LaunchEvents (null: none).
 struct SizeKernels {
   int n, E, T, C, RW;
   int RWI;               // rows per workgroup of the correlation argmax
   size_t col_lds, row_lds;
-  hipError_t (*row_ingest)(const RowIngestArgs&, hipStream_t);
-  hipError_t (*col_proj)(const ColProjArgs&, hipStream_t);
-  hipError_t (*row_update)(const RowUpdateArgs&, hipStream_t);
+  hipError_t (*row_ingest)(const RowIngestArgs&, hipStream_t, const LaunchEvents*);
+  hipError_t (*col_proj)(const ColProjArgs&, hipStream_t, const LaunchEvents*);
+  hipError_t (*row_update)(const RowUpdateArgs&, hipStream_t, const LaunchEvents*);
   hipError_t (*col_err)(const ColErrArgs&, hipStream_t);
   hipError_t (*row_fft)(const RowFftArgs&, hipStream_t);
   hipError_t (*col_fft)(const ColFftArgs&, hipStream_t);

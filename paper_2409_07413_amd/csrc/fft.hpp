@@ -126,18 +126,19 @@ template <int DIR> __device__ __forceinline__ void dft8(float2* a) {
   float2 o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
   dft4<DIR>(e0, e1, e2, e3);
   dft4<DIR>(o0, o1, o2, o3);
-  // w = exp(DIR i pi/4)
-  float2 w1o1 = make_float2(c * (o1.x - DIR * o1.y), c * (o1.y + DIR * o1.x));
-  float2 w2o2 = mul_i<DIR>(o2);
-  float2 w3o3 = make_float2(c * (-o3.x - DIR * o3.y), c * (-o3.y + DIR * o3.x));
+  // w = exp(DIR i pi/4): w o1 = c u1 and w^3 o3 = c u3 with u1 = (1 + DIR i) o1,
+  // u3 = (-1 + DIR i) o3; the factor c goes into multiply-adds
+  const float2 u1 = make_float2(o1.x - DIR * o1.y, o1.y + DIR * o1.x);
+  const float2 w2o2 = mul_i<DIR>(o2);
+  const float2 u3 = make_float2(-o3.x - DIR * o3.y, -o3.y + DIR * o3.x);
   a[0] = cadd(e0, o0);
   a[4] = csub(e0, o0);
-  a[1] = cadd(e1, w1o1);
-  a[5] = csub(e1, w1o1);
+  a[1] = make_float2(fmaf(c, u1.x, e1.x), fmaf(c, u1.y, e1.y));
+  a[5] = make_float2(fmaf(-c, u1.x, e1.x), fmaf(-c, u1.y, e1.y));
   a[2] = cadd(e2, w2o2);
   a[6] = csub(e2, w2o2);
-  a[3] = cadd(e3, w3o3);
-  a[7] = csub(e3, w3o3);
+  a[3] = make_float2(fmaf(c, u3.x, e3.x), fmaf(c, u3.y, e3.y));
+  a[7] = make_float2(fmaf(-c, u3.x, e3.x), fmaf(-c, u3.y, e3.y));
 }
 
 template <int DIR> __device__ __forceinline__ void dft16(float2* a) {

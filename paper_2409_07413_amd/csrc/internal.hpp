@@ -418,18 +418,17 @@ hipEvent_t pooled_event(spr_pop* pop) {
   return e;
 }
 
-// Launch through `fn`, bracketing it with events when timing is enabled.
+// Launch through `fn(const LaunchEvents*)`; when timing is enabled the
+// dispatch itself records a pair of events at the kernel's start and end.
 template <class Fn>
 void timed(spr_pop* pop, int kernel, hipStream_t s, const char* what, Fn&& fn) {
   if (!(pop->timing & (1u << kernel)) || pop->timing_seen[kernel]++ % pop->timing_every != 0) {
-    launch_ok(fn(), what);
+    launch_ok(fn(nullptr), what);
     return;
   }
-  hipEvent_t a = pooled_event(pop), b = pooled_event(pop);
-  HIPCHK(hipEventRecord(a, s));
-  launch_ok(fn(), what);
-  HIPCHK(hipEventRecord(b, s));
-  pop->stamps.push_back({kernel, a, b});
+  const LaunchEvents ev{pooled_event(pop), pooled_event(pop)};
+  launch_ok(fn(&ev), what);
+  pop->stamps.push_back({kernel, ev.start, ev.stop});
 }
 
 // Fold finished stamps into the per-kernel totals (after a synchronisation).
@@ -511,7 +510,7 @@ Group pop_group(spr_pop* pop, int scope) {
 template <class Fn>
 void launch_timed(spr_pop* tp, int kernel, hipStream_t s, const char* what, Fn&& fn) {
   if (tp) timed(tp, kernel, s, what, fn);
-  else launch_ok(fn(), what);
+  else launch_ok(fn(nullptr), what);
 }
 
 // One Sequence over members slots[0..nm): ingest, then per iteration a column
@@ -523,11 +522,13 @@ void run_iterations_on(const Group& g, const std::vector<Iter>& its, int c0, int
   const float2* tw = twiddles(g.ctx, g.n);
   RowIngestArgs ia{slots, nm, g.desc, g.T, g.W, g.t_by_slot,
                    its[0].alg == ALG_ER ? INGEST_PC : INGEST_PLAIN, phase_of(its[0].chi), tw};
-  launch_timed(g.timing, SPR_KERNEL_ROW_INGEST, s, "row_ingest", [&] { return K->row_ingest(ia, s); });
+  launch_timed(g.timing, SPR_KERNEL_ROW_INGEST, s, "row_ingest",
+               [&](const LaunchEvents* ev) { return K->row_ingest(ia, s, ev); });
   int trace_row = trace_row0;
   for (size_t i = 0; i < its.size(); ++i) {
     ColProjArgs ca{slots, nm, g.desc, g.t_by_slot, g.T, g.Y, tw, its[i].trace ? g.err_partial : nullptr};
-    launch_timed(g.timing, SPR_KERNEL_COL_PROJ, s, "col_proj", [&] { return K->col_proj(ca, s); });
+    launch_timed(g.timing, SPR_KERNEL_COL_PROJ, s, "col_proj",
+                 [&](const LaunchEvents* ev) { return K->col_proj(ca, s, ev); });
     if (its[i].trace) {
       if (!g.trace) fail(SPR_E_INVALID_ARG, "iteration traces are recorded for single populations only");
       TraceFinalArgs ta{g.err_partial, g.n / K->C, nm, slots, g.desc,
@@ -552,7 +553,7 @@ void run_iterations_on(const Group& g, const std::vector<Iter>& its, int c0, int
     ra.ph_next = last ? phase_of(1.0) : phase_of(its[i + 1].chi);
     ra.tw = tw;
     const int kid = ra.alg == ALG_ER ? SPR_KERNEL_ROW_UPDATE_ER : SPR_KERNEL_ROW_UPDATE_IA;
-    launch_timed(g.timing, kid, s, "row_update", [&] { return K->row_update(ra, s); });
+    launch_timed(g.timing, kid, s, "row_update", [&](const LaunchEvents* ev) { return K->row_update(ra, s, ev); });
   }
 }
 
@@ -640,7 +641,7 @@ void get_error(const Group& g, hipStream_t s) {
   const SizeKernels* K = g.K;
   const float2* tw = twiddles(g.ctx, g.n);
   RowIngestArgs ia{g.slots, g.nm, g.desc, g.T, g.W, g.t_by_slot, INGEST_SMASK, phase_of(1.0), tw};
-  launch_ok(K->row_ingest(ia, s), "row_ingest");
+  launch_ok(K->row_ingest(ia, s, nullptr), "row_ingest");
   ColErrArgs ea{g.slots, g.nm, g.desc, g.t_by_slot, g.T, g.err_partial, tw};
   launch_ok(K->col_err(ea, s), "col_err");
   ErrFinalArgs fa{g.err_partial, g.n / K->C, g.nm, g.slots, g.desc};

@@ -15,6 +15,8 @@
 // iterate's row transform, so each iteration is one read-write sweep per pass.
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 #include "fft.hpp"
 
@@ -191,6 +193,17 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// 1/sqrt(x) for x > 0 from the hardware reciprocal square root; a subnormal x
+// (|X| below 1e-19, which FFT outputs of measured data do not reach) is first
+// scaled into the normal range (2^24 x, result times 2^12).  The test is a
+// wavefront vote, so the common case is one compare and one rsq.
+__device__ __forceinline__ float rsqrt_pos(float x) {
+  const bool tiny = x < 1.17549435e-38f;
+  if (__builtin_expect(__builtin_amdgcn_ballot_w64(tiny) != 0, 0))
+    return tiny ? __fmul_rn(__builtin_amdgcn_rsqf(__fmul_rn(x, 16777216.f)), 4096.f) : __builtin_amdgcn_rsqf(x);
+  return __builtin_amdgcn_rsqf(x);
+}
+
 // Masked modulus replacement (Eq. pm_full) on the unnormalised column
 // spectrum X = N * (unitary value), returning the projected unitary value
 // divided by N, the input of the unnormalised inverse column transform; both
@@ -199,16 +212,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 // stores minus its amplitude bound (-0: none); a unitary value above the
 // bound b is brought down to it with its phase (Eq. pm_bounds).  The branches
 // follow the mask, which is coherent over neighbouring pixels.
-__device__ __forceinline__ float2 modulus_replace(float2 X, float stored, float scale, float inv) {
+__device__ __forceinline__ float2 modulus_replace(float2 X, float stored, float scale, float inv, float scale_inv) {
   const float m2 = fmaf(X.x, X.x, __fmul_rn(X.y, X.y));
   if (signbit(stored)) {
     const float b = __fmul_rn(-stored, scale);
     const float bn = __fmul_rn(b, (float)N);  // the bound on |X|
-    if (b > 0.f && m2 > __fmul_rn(bn, bn)) return cscale(X, __fmul_rn(__fmul_rn(b, inv), rsqrtf(m2)));
+    if (b > 0.f && m2 > __fmul_rn(bn, bn)) return cscale(X, __fmul_rn(__fmul_rn(b, inv), rsqrt_pos(m2)));
     return cscale(X, __fmul_rn(inv, inv));
   }
-  const float Mn = __fmul_rn(__fmul_rn(stored, scale), inv);
-  if (m2 > 0.f) return cscale(X, __fmul_rn(Mn, rsqrtf(m2)));
+  const float Mn = __fmul_rn(stored, scale_inv);  // scale_inv = scale / N
+  if (m2 > 0.f) return cscale(X, __fmul_rn(Mn, rsqrt_pos(m2)));
   return make_float2(Mn, 0.f);
 }
 
@@ -270,8 +283,9 @@ __device__ __forceinline__ void col_proj_tile(float2 (&v)[E], const float (&mv)[
       }
     }
   }
+  const float scale_inv = __fmul_rn(amp_scale, inv);
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = modulus_replace(v[m], mv[m], amp_scale, inv);
+  for (int m = 0; m < E; ++m) v[m] = modulus_replace(v[m], mv[m], amp_scale, inv, scale_inv);
   fft<N, +1, ColL>(v, lds + c, t, tw, ws);
 #pragma unroll
   for (int m = 0; m < E; ++m) dst[(size_t)(t + T * m) * N + col] = v[m];
@@ -694,31 +708,38 @@ hipError_t set_lds(K kernel, size_t bytes) {
 
 int row_blocks(int nm) { return (nm * N + RW - 1) / RW; }
 
-hipError_t l_row_ingest(const RowIngestArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_row_ingest, dim3(row_blocks(a.nm)), dim3(RW * T), kRowLds, s, a);
+// Launch, with the dispatch recording ev's events around the kernel when given.
+template <typename K, typename A>
+void launch_k(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, const LaunchEvents* ev, const A& a) {
+  if (ev) hipExtLaunchKernelGGL(kernel, grid, block, lds, s, ev->start, ev->stop, 0, a);
+  else hipLaunchKernelGGL(kernel, grid, block, lds, s, a);
+}
+
+hipError_t l_row_ingest(const RowIngestArgs& a, hipStream_t s, const LaunchEvents* ev) {
+  launch_k(k_row_ingest, dim3(row_blocks(a.nm)), dim3(RW * T), kRowLds, s, ev, a);
   return hipGetLastError();
 }
-hipError_t l_col_proj(const ColProjArgs& a, hipStream_t s) {
+hipError_t l_col_proj(const ColProjArgs& a, hipStream_t s, const LaunchEvents* ev) {
   static const hipError_t init = set_lds(k_col_proj<false>, kColLds);
   static const hipError_t init_t = set_lds(k_col_proj<true>, kColLds);
   if (init != hipSuccess) return init;
   if (init_t != hipSuccess) return init_t;
-  if (a.trace_partial) hipLaunchKernelGGL(k_col_proj<true>, dim3(N / C, a.nm), dim3(C * T), kColLds, s, a);
-  else hipLaunchKernelGGL(k_col_proj<false>, dim3(N / C, a.nm), dim3(C * T), kColLds, s, a);
+  if (a.trace_partial) launch_k(k_col_proj<true>, dim3(N / C, a.nm), dim3(C * T), kColLds, s, ev, a);
+  else launch_k(k_col_proj<false>, dim3(N / C, a.nm), dim3(C * T), kColLds, s, ev, a);
   return hipGetLastError();
 }
-hipError_t l_row_update(const RowUpdateArgs& a, hipStream_t s) {
+hipError_t l_row_update(const RowUpdateArgs& a, hipStream_t s, const LaunchEvents* ev) {
   const dim3 grid(row_blocks(a.nm)), block(RW * T);
   // the HIO/RAAR-only kernels gain on power-of-two sizes up to 512 and lose on
   // the radix-3 ones and at 1024, where the run-time form keeps fewer
   // registers live (at 1024: 165 against 197, three waves per SIMD instead of
   // two)
   constexpr bool kSpecIA = (N & (N - 1)) == 0 && N < 1024;
-  if (a.ip) hipLaunchKernelGGL(k_row_update<0>, grid, block, kRowLds, s, a);
-  else if (a.alg == ALG_ER) hipLaunchKernelGGL(k_row_update<1>, grid, block, kRowLds, s, a);
-  else if (!kSpecIA) hipLaunchKernelGGL(k_row_update<0>, grid, block, kRowLds, s, a);
-  else if (a.alg == ALG_HIO) hipLaunchKernelGGL(k_row_update<2>, grid, block, kRowLds, s, a);
-  else hipLaunchKernelGGL(k_row_update<3>, grid, block, kRowLds, s, a);
+  if (a.ip) launch_k(k_row_update<0>, grid, block, kRowLds, s, ev, a);
+  else if (a.alg == ALG_ER) launch_k(k_row_update<1>, grid, block, kRowLds, s, ev, a);
+  else if (!kSpecIA) launch_k(k_row_update<0>, grid, block, kRowLds, s, ev, a);
+  else if (a.alg == ALG_HIO) launch_k(k_row_update<2>, grid, block, kRowLds, s, ev, a);
+  else launch_k(k_row_update<3>, grid, block, kRowLds, s, ev, a);
   return hipGetLastError();
 }
 hipError_t l_col_err(const ColErrArgs& a, hipStream_t s) {

@@ -539,7 +539,7 @@ class HipExec : public Exec {
           RowIngestArgs ia{ds, (int)kv.second.size(), dev<SlotDesc>(o_table_), nullptr, 0, 1, kv.first.first,
                            phase_of(kv.first.second), tw};
           ia.W = (int)((nn + 31) / 32);
-          ops_.push_back([=] { launch(K->row_ingest(ia, s_), "row_ingest"); });
+          ops_.push_back([=] { launch(K->row_ingest(ia, s_, nullptr), "row_ingest"); });
         }
         std::vector<IterParam> ip(cm);
         for (int i = 0; i < L.nit; ++i) {
@@ -583,8 +583,8 @@ class HipExec : public Exec {
           ra.ph_next = ip[0].ph_next;
           ra.tw = tw;
           ops_.push_back([=] {
-            launch(K->col_proj(ca, s_), "col_proj");
-            launch(K->row_update(ra, s_), "row_update");
+            launch(K->col_proj(ca, s_, nullptr), "col_proj");
+            launch(K->row_update(ra, s_, nullptr), "row_update");
           });
         }
       }

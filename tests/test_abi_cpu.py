@@ -243,5 +243,6 @@ def test_benchmark_reaches_the_oracle_only_in_its_cpu_baseline():
     top = [n for n in tree.body if isinstance(n, (ast.Import, ast.ImportFrom))
            and "oracle" in ast.dump(n)]
     assert not top
-    # cpu_baseline and the worker it forks per member
-    assert users == {"cpu_baseline", "_oracle_member"}, users
+    # cpu_baseline and the workers it runs per member (timing and the
+    # device-against-oracle check)
+    assert users == {"cpu_baseline", "_oracle_timed", "_oracle_check"}, users
