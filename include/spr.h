@@ -389,6 +389,20 @@ spr_status spr_timing_read(spr_pop* pop, int32_t kernel, int64_t* launches, doub
 spr_status spr_fft2(spr_ctx* ctx, int32_t n, int32_t batch, const float* in, float* out,
                     int32_t inverse, void* hip_stream);
 
+/* The same transform for callers that cannot allocate device memory (code   */
+/* under HIP graph capture, tight serving loops, harnesses that forbid       */
+/* hipMalloc): it calls no device allocation or free.  Its twiddle table and  */
+/* row-transform intermediate live in a fixed 64 MiB device array that the    */
+/* library holds on every GPU it runs on until the process ends, so          */
+/* batch * (8 n^2) + 8 n (the table, rounded up to 256 bytes) must not        */
+/* exceed 64 MiB (e.g. 7 images of 1024^2): larger requests give              */
+/* SPR_E_INVALID_ARG before anything is launched.  in and out are device      */
+/* pointers and may alias.  Every call on one GPU shares the array, so calls  */
+/* that overlap on one GPU (other streams, or threads) race; calls on one     */
+/* stream are ordered.  Results agree with spr_fft2 to FP32 rounding.         */
+spr_status spr_fft2_noalloc(spr_ctx* ctx, int32_t n, int32_t batch, const float* in, float* out,
+                            int32_t inverse, void* hip_stream);
+
 /* ------------------------------------------------------------------------- */
 /* Graphs: the launches of a schedule recorded once into a HIP graph and      */
 /* replayed with one call, for schedules whose per-launch host cost matters   */

@@ -133,7 +133,7 @@ SERVER_SHORTEST_FIRST = 0x4
 EXPORTS = ["spr_ctx_create", "spr_ctx_destroy", "spr_ctx_last_error", "spr_supported_size",
            "spr_shot_create", "spr_shot_destroy", "spr_pop_create", "spr_pop_destroy", "spr_pop_write",
            "spr_sched_create", "spr_sched_plain", "spr_sched_mpr", "spr_sched_destroy", "spr_sched_ops",
-           "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2",
+           "spr_run", "spr_sync", "spr_read", "spr_read_stats", "spr_read_xover", "spr_fft2", "spr_fft2_noalloc",
            "spr_timing_enable", "spr_timing_sample", "spr_timing_read", "spr_ctx_set_cache_budget", "spr_run_batch",
            "spr_read_member", "spr_read_average", "spr_read_monitor", "spr_read_trace", "spr_pop_init_spheres", "spr_shot_set_bounds", "spr_shot_set_bounds_sat", "spr_size_variants", "spr_ctx_autotune", "spr_ctx_set_variant",
            "spr_ctx_get_tuning", "spr_graph_create", "spr_graph_create_batch", "spr_graph_launch",
@@ -170,6 +170,7 @@ def _proto(lib):
         "spr_read_stats": (i32, [vp, C.POINTER(GenStats), i32, C.POINTER(i32)]),
         "spr_read_xover": (i32, [vp, C.POINTER(XoverInfo), i32]),
         "spr_fft2": (i32, [vp, i32, i32, vp, vp, i32, vp]),
+        "spr_fft2_noalloc": (i32, [vp, i32, i32, vp, vp, i32, vp]),
         "spr_timing_enable": (i32, [vp, i32]),
         "spr_timing_sample": (i32, [vp, i32]),
         "spr_timing_read": (i32, [vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
@@ -411,6 +412,23 @@ class Context:
             import torch
             torch.cuda.synchronize()
         self._check(self.lib.spr_fft2(self.h, n, batch, pi, po, 1 if inverse else 0, sp))
+        if not sp:
+            torch.cuda.synchronize()
+
+    def fft2_noalloc(self, x_in, x_out, inverse=False, stream=None):
+        """The same transform through the allocation-free entry point (its
+        intermediate in the library's fixed device scratch array)."""
+        n = x_in.shape[-1]
+        batch = x_in.numel() // (n * n)
+        pi, di = _ptr(x_in)
+        po, do = _ptr(x_out)
+        if not (di and do):
+            raise ValueError("fft2_noalloc takes device tensors")
+        sp = _stream_ptr(stream)
+        if not sp:
+            import torch
+            torch.cuda.synchronize()
+        self._check(self.lib.spr_fft2_noalloc(self.h, n, batch, pi, po, 1 if inverse else 0, sp))
         if not sp:
             torch.cuda.synchronize()
 

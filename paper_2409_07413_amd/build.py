@@ -50,6 +50,7 @@ def _jobs():
     jobs.append((os.path.join(CSRC, "runtime.cpp"), os.path.join(OBJ, "runtime.o"), ["-x", "hip"]))
     jobs.append((os.path.join(CSRC, "server.cpp"), os.path.join(OBJ, "server.o"), ["-x", "hip"]))
     jobs.append((os.path.join(CSRC, "graph.cpp"), os.path.join(OBJ, "graph.o"), ["-x", "hip"]))
+    jobs.append((os.path.join(CSRC, "noalloc.cpp"), os.path.join(OBJ, "noalloc.o"), ["-x", "hip"]))
     return jobs
 
 

@@ -159,6 +159,10 @@ inline bool live_has(const void* h) {
 }  // namespace spr_live
 using namespace spr_live;
 
+// Device address of the allocation-free entry point's scratch array on this
+// device (noalloc.cpp), looked up once per device at context creation.
+spr_status noalloc_setup(int device, std::string* err);
+
 namespace {
 
 struct Fail {

@@ -75,6 +75,8 @@ spr_status spr_ctx_create(int32_t hip_device, spr_ctx** out) {
     if (hip_device < 0 || hip_device >= count) fail(SPR_E_INVALID_ARG, "no such device");
     ctx->device = hip_device;
     use_device(ctx);
+    std::string why;
+    if (noalloc_setup(hip_device, &why) != SPR_OK) fail(SPR_E_HIP, why);
     HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
   });
   if (st != SPR_OK) {
