@@ -67,10 +67,11 @@ def algorithmic_bytes_per_px(kernel, members_sharing_m):
 
 
 def kernel_sources_digest():
-    """Digest of the sources that define the iteration kernels and their launch."""
+    """Digest of the sources that define the iteration kernels, their launch
+    configuration and their arguments."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("fft.hpp", "kernels_n.hip", "common.hpp", "internal.hpp", "runtime.cpp"):
+    for f in ("fft.hpp", "kernels_n.hip", "common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2409_07413_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
