@@ -570,6 +570,81 @@ def batch_study(ctx, B, shots=32, P_batch=32, G=50):
         t = res[k + "_s"]
         res[k] = {"member_iterations_per_s": member_its / t, "iteration_pixels_per_s": px_its / t,
                   "pct_hbm_peak_iterations": px_its * 40.0 / t / (HBM_PEAK_GBS * 1e9)}
+    res["small"] = small_batch_study(ctx, B)
+    return res
+
+
+def small_batch_study(ctx, B, shots=24, P_batch=8, G=10, reps=5):
+    """Small uneven shots, whose launches cannot fill the device: 24 shots with
+    sides drawn from {48, 64, 96, 128, 192}, P = 8, 200 iterations (10 blocks
+    of HIO^j ER^(20-j) with shrink-wrap) + GetError; one population at a time
+    against one batch, whose size groups overlap on the device, and against
+    the same batch with the groups one after another (a cache budget below
+    the groups' sum and above each group's work buffers)."""
+    import torch
+    from paper_2409_07413_amd import synth
+    rng = np.random.default_rng(1103)
+    sides = (48, 64, 96, 128, 192)
+    sizes = rng.choice(sides, size=shots)
+    data = []
+    for i, n in enumerate(sizes):
+        sh = synth.shot(int(n), "ellipses", 1103 + 7 * i, 1e6, beamstop=4, count=3,
+                        semi=(0.03 * n, 0.1 * n), disk_diameter=0.3 * n)
+        data.append((int(n), sh["amp"].astype(np.float32), sh["mask"].astype(np.uint8)))
+    supp = {n: synth.centred_square(n, n // 3).astype(np.uint8) for n in sides}
+    sched = B.sched_plain(ctx, alg=B.ALG_HIO, G=G, j=16, j_er=4, j_end=0, beta=0.9, chi=0.5, sigma=2.0,
+                          sigma_end=1.0, tau=0.10, tau_end=0.10)
+
+    def make():
+        out = []
+        for i, (n, amp, mask) in enumerate(data):
+            shot = ctx.shot(amp, mask)
+            out.append((shot, shot.population(None, supp[n], seed=9100 + i, P=P_batch)))
+        return out
+
+    res = {"shots": shots, "P": P_batch, "iterations": 20 * G, "sizes": [int(n) for n in sizes]}
+    times = {}
+    errs = {}
+    serial_budget = 30 << 20  # above each group's 2 x chunk x n^2 x 8 bytes, below their sum
+    for form in ("one_at_a_time", "batch", "batch_groups_serial"):
+        ctx.set_cache_budget(serial_budget if form == "batch_groups_serial" else CACHE_BUDGET)
+        pops = make()
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if form != "one_at_a_time":
+                ctx.run_batch([p for _, p in pops], [sched] * shots)
+            else:
+                for _, pop in pops:
+                    pop.run(sched)
+            for _, pop in pops:
+                pop.sync()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        times[form] = best
+        for shot, pop in pops:
+            pop.close()
+            shot.close()
+        # one more fresh run for the comparison of results
+        pops = make()
+        if form != "one_at_a_time":
+            ctx.run_batch([p for _, p in pops], [sched] * shots)
+        else:
+            for _, pop in pops:
+                pop.run(sched)
+        errs[form] = [pop.errors() for _, pop in pops]
+        for shot, pop in pops:
+            pop.close()
+            shot.close()
+    ctx.set_cache_budget(CACHE_BUDGET)
+    sched.close()
+    member_its = shots * P_batch * 20 * G
+    for form, t in times.items():
+        res[form] = {"seconds": t, "member_iterations_per_s": member_its / t}
+    res["batch_equals_one_at_a_time"] = bool(all(
+        np.array_equal(a, b) and np.array_equal(a, c)
+        for a, b, c in zip(errs["one_at_a_time"], errs["batch"], errs["batch_groups_serial"])))
     return res
 
 

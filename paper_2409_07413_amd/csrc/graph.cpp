@@ -111,9 +111,7 @@ spr_status spr_graph_create_batch(spr_ctx* ctx, spr_pop* const* pops, const spr_
           if (o.kind != SPR_OP_ER && o.kind != SPR_OP_HIO && o.kind != SPR_OP_RAAR && o.kind != SPR_OP_SHRINKWRAP &&
               o.kind != SPR_OP_SUPPORT_AREA && o.kind != SPR_OP_GET_ERROR)
             fail(SPR_E_INVALID_ARG, "batched runs take ER/HIO/RAAR, SHRINKWRAP, SUPPORT_AREA and GET_ERROR only");
-      capture(g, [&](hipStream_t cs) {
-        for (auto& bg : groups) run_group_schedule(bg.g, bg.sched, cs);
-      });
+      capture(g, [&](hipStream_t cs) { run_groups(ctx, groups, cs); });
     } catch (...) {
       release(g);
       delete g;

@@ -53,6 +53,7 @@ struct spr_ctx {
   std::set<spr_pop*> pops;
   std::set<spr_server*> servers;
   std::set<spr_graph*> graphs;
+  std::vector<hipStream_t> side;  // streams of the size groups of a batch after the first (default priority)
   std::mutex mu;
 };
 
@@ -1189,6 +1190,57 @@ std::vector<BatchGroup> plan_batch(spr_ctx* ctx, spr_pop* const* pops, const spr
     out.push_back(bg);
   }
   return out;
+}
+
+// Run the size groups of a batch.  Groups touch disjoint members and work
+// buffers, so their order does not matter.  When the groups' iteration
+// chunks together fit the cache budget (small shots, whose launches cannot
+// fill the device alone), they overlap on the device: the first on s, each
+// other one on a stream of its own that starts when s reaches this point,
+// and s then waits for all of them.  Otherwise they run one after another:
+// each group's chunk already fills the memory-side cache, and overlapping
+// groups would evict each other's work buffers (measured: 32 shots of
+// 256^2..1024^2 ran 5 % slower overlapped).  Under stream capture the side
+// streams join the capture through the events, and the graph gets the same
+// fork and join.
+void run_groups(spr_ctx* ctx, std::vector<BatchGroup>& groups, hipStream_t s) {
+  size_t resident = 0;
+  for (const auto& bg : groups) resident += 2 * (size_t)bg.g.chunk * bg.n * bg.n * sizeof(float2);
+  if (groups.size() <= 1 || ctx->cache_budget == 0 || resident > ctx->cache_budget) {
+    for (auto& bg : groups) run_group_schedule(bg.g, bg.sched, s);
+    return;
+  }
+  while (ctx->side.size() + 1 < groups.size()) {
+    hipStream_t t = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+    ctx->side.push_back(t);
+  }
+  std::vector<hipEvent_t> ev;
+  auto event = [&]() {
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ev.push_back(e);
+    return e;
+  };
+  try {
+    hipEvent_t fork = event();
+    HIPCHK(hipEventRecord(fork, s));
+    std::vector<hipEvent_t> joins;
+    for (size_t k = 1; k < groups.size(); ++k) {
+      hipStream_t t = ctx->side[k - 1];
+      HIPCHK(hipStreamWaitEvent(t, fork, 0));
+      run_group_schedule(groups[k].g, groups[k].sched, t);
+      hipEvent_t j = event();
+      HIPCHK(hipEventRecord(j, t));
+      joins.push_back(j);
+    }
+    run_group_schedule(groups[0].g, groups[0].sched, s);
+    for (hipEvent_t j : joins) HIPCHK(hipStreamWaitEvent(s, j, 0));
+  } catch (...) {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    throw;
+  }
+  for (hipEvent_t e : ev) HIPCHK(hipEventDestroy(e));
 }
 
 // Work buffers of a batch of `members` members of size n.

@@ -104,8 +104,10 @@ void spr_ctx_destroy(spr_ctx* ctx) {
   live_remove(ctx);
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (hipStream_t t : ctx->side) (void)hipStreamSynchronize(t);
   for (auto& kv : ctx->tw) (void)hipFree(kv.second);
   for (auto& kv : ctx->ws) workspace_free(kv.second);
+  for (hipStream_t t : ctx->side) (void)hipStreamDestroy(t);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -550,16 +552,14 @@ spr_status spr_run_batch(spr_ctx* ctx, spr_pop* const* pops, const spr_sched* co
           w.last = s;
           return w;
         });
-    for (auto& bg : groups) {
-      for (int i : bg.idx) pops[i]->last = s;
-      try {
-        run_group_schedule(bg.g, bg.sched, s);
-      } catch (...) {
-        for (int i : bg.idx) (void)hipEventRecord(pops[i]->done, s);
-        throw;
-      }
-      for (int i : bg.idx) HIPCHK(hipEventRecord(pops[i]->done, s));
+    for (int i = 0; i < n; ++i) pops[i]->last = s;
+    try {
+      run_groups(ctx, groups, s);
+    } catch (...) {
+      for (int i = 0; i < n; ++i) (void)hipEventRecord(pops[i]->done, s);
+      throw;
     }
+    for (int i = 0; i < n; ++i) HIPCHK(hipEventRecord(pops[i]->done, s));
   });
 }
 
