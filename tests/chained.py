@@ -50,12 +50,13 @@ def feasibility_margin(y, chi):
     return y.real * np.sin(th) - np.abs(y.imag) * np.cos(th)
 
 
-def hio_step_banded(x, g_next, S, M, known, chi, beta, band=BAND):
-    """One oracle HIO step from x with the band rule above.
+def hio_step_banded(x, g_next, S, M, known, chi, beta, band=BAND, bound=None):
+    """One oracle HIO step from x with the band rule above (with `bound`, the
+    upper-bounded modulus projector of Eq. pm_bounds).
 
     Returns (expected next state, pixels decided inside the band, decisions
     outside the band that disagree with the device)."""
-    y = mpr.proj_modulus(x, M, known)
+    y = mpr.proj_modulus(x, M, known) if bound is None else mpr.proj_modulus_bounded(x, M, known, bound)
     feas_o = S & (mpr.proj_phase(y, chi) == y)
     A = y
     Bv = x - beta * y
@@ -154,9 +155,11 @@ def _same(a, b):
     return all(np.array_equal(u, v) for u, v in zip(a, b))
 
 
-def check_trajectory(traj, M, known, seed=0, band=BAND, step_bar=1e-5, err_bar=1e-5):
+def check_trajectory(traj, M, known, seed=0, band=BAND, step_bar=1e-5, err_bar=1e-5, bound=None):
     """Walk the steps of traj.ops, checking each against the oracle applied to
-    the device's previous state.  Returns a report dict (maxima and counts)."""
+    the device's previous state (M as the shot stores it; `bound` the upper
+    bounds of the unknown pixels, if the shot has them).  Returns a report
+    dict (maxima and counts)."""
     B = traj.B
     ops = traj.ops
     rep = {"steps": 0, "max_step_rel": 0.0, "hio_band_px": 0, "sw_band_px": 0, "area_band_px": 0,
@@ -172,12 +175,12 @@ def check_trajectory(traj, M, known, seed=0, band=BAND, step_bar=1e-5, err_bar=1
                 x, S = before[(t, p)]
                 x64 = x.astype(np.complex128)
                 if o.kind == B.OP_ER:
-                    ref = mpr.er(x64, S, M, known, o.chi)
+                    ref = mpr.er(x64, S, M, known, o.chi, bound=bound)
                 elif o.kind == B.OP_RAAR:
-                    ref = mpr.raar(x64, S, M, known, o.chi, o.beta)
+                    ref = mpr.raar(x64, S, M, known, o.chi, o.beta, bound=bound)
                 else:
                     ref, nb, hard = hio_step_banded(x64, g.astype(np.complex128), S, M, known, o.chi, o.beta,
-                                                    band)
+                                                    band, bound)
                     assert hard == 0, (where, t, p, "HIO decisions outside the FP32 band differ", hard)
                     rep["hio_band_px"] += nb
                 r = rel(g, ref)

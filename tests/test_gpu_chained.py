@@ -170,3 +170,45 @@ def test_mpr_generation_chained(ctx, B, n, j, j_er, j_eval):
     _report(f"MPR generation {n}^2, P = {P}", rep)
     assert rep["selections"] == P and rep["xover_children"] == P
     assert rep["xover_flagged"] <= P // 2
+
+
+# ---------------------------------------------------------------------------
+# The same step by step with the modulus stored in FP16 (the oracle uses the
+# stored values, reading of the FP16 storage) and with upper bounds on the
+# unknown pixels (Eq. pm_bounds), from starts that put energy on them so that
+# the clamp acts in every step.
+# ---------------------------------------------------------------------------
+def _energetic_starts(c, rng):
+    obj = c.obj / max(c.obj.max(), 1e-30)
+    scale = np.sqrt(np.sum(c.M ** 2) / max(np.sum(np.abs(mpr.fft2(obj)) ** 2), 1e-30))
+    n = c.n
+    return np.stack([(3.0 * scale * obj * np.exp(1j * 0.3 * p)
+                      + 0.1 * scale * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))))
+                     for p in range(c.P)]).astype(np.complex64)
+
+
+@pytest.mark.parametrize("n,fp16,bounds,alg", [(512, True, False, "RAAR"), (256, False, True, "HIO"),
+                                               (1024, True, True, "RAAR")])
+def test_chained_fp16_and_bounds(ctx, B, n, fp16, bounds, alg):
+    P = 2 if n <= 512 else 1
+    c = Case(n, P, seed=n + 61, photons=1e8, gap=4)
+    sh = ctx.shot(c.amp32, c.mask8, fp16=fp16)
+    M, s = (mpr.fp16_modulus(c.M, c.known) if fp16 else (c.M, 1.0))
+    U = None
+    if bounds:
+        assert sh.set_bounds(1.5, 0.2) > 0
+        U = mpr.upper_bounds(M, c.known, 1.5, 0.2)
+        if fp16:
+            U = np.where(np.isfinite(U), (U / s).astype(np.float16).astype(np.float64) * s, np.nan)
+        rho32 = _energetic_starts(c, np.random.default_rng(n))
+    else:
+        rho32 = c.rho32
+    kind = B.OP_HIO if alg == "HIO" else B.OP_RAAR
+    ops = [B.op(kind, count=8, beta=0.9, chi=0.5), B.op(B.OP_ER, count=4, chi=0.5), B.op(B.OP_GET_ERROR)]
+    try:
+        traj = chained.Trajectory(ctx, B, lambda: sh.population(rho32, c.supp8), ops)
+        rep = chained.check_trajectory(traj, M, c.known, bound=U)
+    finally:
+        sh.close()
+    _report(f"{alg}^8 ER^4 at {n}^2, FP16 storage {fp16}, upper bounds {bounds}", rep)
+    assert rep["steps"] == 13
