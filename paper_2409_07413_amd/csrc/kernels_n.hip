@@ -92,6 +92,33 @@ __device__ __forceinline__ float2 gload(const float2* p, size_t i) {
   return make_float2(v.x, v.y);
 }
 
+// Buffer descriptors for the column tiles: a lane's E accesses t + T*m of
+// one column split into one per-lane byte offset (a VGPR) and a per-element
+// constant (an SGPR), so they need no vector address arithmetic.  The
+// descriptor's range check (num_records bytes) makes any offset outside the
+// array read 0 and drop its write.
+typedef __amdgpu_buffer_rsrc_t BufRes;
+__device__ __forceinline__ BufRes buf_res(const void* p, size_t bytes) {
+  // gfx9 descriptor word 3: raw (untyped) 32-bit data format
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(BufRes(), 0, 0, 0)) B64;
+constexpr int kColStep8 = T * N * 8;  // bytes between a lane's column elements (complex FP32)
+__device__ __forceinline__ void col_load(float2 (&v)[E], BufRes r, int voff) {
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const F2v q = __builtin_bit_cast(F2v, __builtin_amdgcn_raw_buffer_load_b64(r, voff, m * kColStep8, 0));
+    v[m] = make_float2(q.x, q.y);
+  }
+}
+__device__ __forceinline__ void col_store(const float2 (&v)[E], BufRes r, int voff) {
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const F2v q = {v[m].x, v[m].y};
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B64, q), r, voff, m * kColStep8, 0);
+  }
+}
+
 
 // Nearest point of {|arg z| <= chi pi} (positivity: Re z >= 0 exactly).
 // The real-space arithmetic below spells out every rounding (__fmul_rn,
@@ -130,13 +157,17 @@ __device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
 __device__ __forceinline__ void load_col_amp(float (&mv)[E], const float* amp, const __half* amp16, int t,
                                              int col) {
   if (amp16) {
-    GPtr<unsigned short> p = gview(reinterpret_cast<const unsigned short*>(amp16));
+    const BufRes r = buf_res(amp16, NN * 2);
+    const int voff = (t * N + col) * 2;
 #pragma unroll
-    for (int m = 0; m < E; ++m) mv[m] = __half2float(__ushort_as_half(p[(size_t)(t + T * m) * N + col]));
+    for (int m = 0; m < E; ++m)
+      mv[m] = __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, voff, m * T * N * 2, 0)));
   } else {
-    GPtr<float> p = gview(amp);
+    const BufRes r = buf_res(amp, NN * 4);
+    const int voff = (t * N + col) * 4;
 #pragma unroll
-    for (int m = 0; m < E; ++m) mv[m] = p[(size_t)(t + T * m) * N + col];
+    for (int m = 0; m < E; ++m)
+      mv[m] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, m * T * N * 4, 0));
   }
 }
 __device__ __forceinline__ void load_col_amp(float (&mv)[E], const SlotDesc& d, int t, int col) {
@@ -287,8 +318,7 @@ __device__ __forceinline__ void col_proj_tile(float2 (&v)[E], const float (&mv)[
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = modulus_replace(v[m], mv[m], amp_scale, inv, scale_inv);
   fft<N, +1, ColL>(v, lds + c, t, tw, ws);
-#pragma unroll
-  for (int m = 0; m < E; ++m) dst[(size_t)(t + T * m) * N + col] = v[m];
+  col_store(v, buf_res(dst, NN * 8), (t * N + col) * 8);
   if constexpr (TRACE) {
     acc = wave_sum(acc);
     double* wsum = reinterpret_cast<double*>(lds);  // the transform left the tile buffer free
@@ -315,8 +345,7 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
   const float2* src = a.t_by_slot ? d.T : a.T + (size_t)id.img * NN;
   float2 v[E];
   float mv[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = gload(src, (size_t)(t + T * m) * N + col);
+  col_load(v, buf_res(src, NN * 8), (t * N + col) * 8);
   load_col_amp(mv, d, t, col);
   issue_fence();
   TwSet<N> ws;
