@@ -109,7 +109,6 @@ def trace_averages(chunk):
     return {k: v.get("avg_us") for k, v in t.get("kernels", {}).items()}
 
 
-CPU_WORKERS_MAX = 16  # the host-core share of one GPU on the benchmark machines
 
 
 def gpu_step_check(ctx, B, amp, mask, rho, supp):
@@ -158,7 +157,7 @@ def oracle_pool():
     """Worker processes for the oracle leg, started before this process
     initialises the GPU (they never touch it)."""
     import multiprocessing as mp
-    workers = max(1, min(CPU_WORKERS_MAX, len(os.sched_getaffinity(0))))
+    workers = max(1, len(os.sched_getaffinity(0)))
     return mp.get_context("spawn").Pool(workers), workers
 
 
@@ -167,9 +166,9 @@ def cpu_baseline(states, checks, pool, workers, seconds_target=20.0):
     device's error against it.
 
     Timing: k RAAR then k ER iterations on each of the benchmark's 64 parent
-    states (after the timed generations), one process per member over
-    min(16, affinity) workers (the host share of one GPU); k is chosen so
-    that the whole sample is about `seconds_target` of CPU work.  Also the
+    states (after the timed generations), one process per member over one
+    worker per core the process may run on; k is chosen so that the whole
+    sample is about `seconds_target` of CPU work.  Also the
     single-core rate of one member.  Checks: for each (shot, states, device
     step results), the oracle's RAAR and ER steps and fitness from the same
     states (`gpu_step_check`)."""

@@ -88,9 +88,12 @@ int32_t spr_supported_size(int32_t n);
 /* results do not depend on it.  0 = one chunk.                                  */
 spr_status spr_ctx_set_cache_budget(spr_ctx* ctx, uint64_t bytes);
 
-/* Tuning.  Sizes 256, 384, 512, 768 and 1024 are compiled twice: variant 0  */
-/* (the default plan) and variant 1 (the other column-tile width, or for 1024 */
-/* the other radix order).  spr_ctx_autotune times RAAR iterations on        */
+/* Tuning.  Sizes 128, 256, 384, 512, 768 and 1024 are compiled twice:       */
+/* variant 0 (the default plan) and variant 1 (the other column-tile width,  */
+/* for 1024 the other radix order, for 128 the resident Sequence: one        */
+/* cooperative launch per Sequence, whose workgroups meet at device-memory   */
+/* barriers between passes; same results bit for bit, used when no iteration */
+/* is traced and the stream is not being captured).  spr_ctx_autotune times RAAR iterations on */
 /* `members` synthetic members of size n for every variant and member-chunk  */
 /* candidate (all members, the chunk whose two work buffers fit 256 MiB, half */
 /* of it), keeps the fastest on the context and reports every candidate.     */
@@ -297,14 +300,18 @@ spr_status spr_sched_ops(const spr_sched* sched, spr_op* ops, int32_t max_ops, i
 spr_status spr_run(spr_pop* pop, const spr_sched* sched, void* hip_stream);
 /* Batched uneven shots: run scheds[i] on pops[i] for i < n.  Populations of one */
 /* detector size advance together, each operation being one launch over all    */
-/* their members (each reaching its own shot's modulus); sizes run one after    */
-/* another on the stream.  Within a size the schedules must be equal and use    */
+/* their members (each reaching its own shot's modulus); size groups run one   */
+/* after another on the stream, or overlap on context-owned side streams when  */
+/* their iteration chunks together fit the cache budget.  Within a size the schedules must be equal and use    */
 /* only ER/HIO/RAAR, SHRINKWRAP, SUPPORT_AREA with SPR_AREA_ABS and GET_ERROR on  */
 /* scope ALL; otherwise SPR_E_INVALID_ARG.  Results equal running each          */
 /* population alone.  Each population must appear once.                         */
 spr_status spr_run_batch(spr_ctx* ctx, spr_pop* const* pops, const spr_sched* const* scheds, int32_t n,
                          void* hip_stream);
-/* Wait for the population's work; SPR_E_NUMERIC if a fitness value was NaN/Inf. */
+/* Wait for the population's work; SPR_E_NUMERIC if a fitness value was NaN/Inf; */
+/* SPR_E_HIP if a resident Sequence (128^2 variant 1) ran out of a barrier wait  */
+/* (its results are then not valid; the population can run again).  spr_read    */
+/* reports the latter too.                                                       */
 spr_status spr_sync(spr_pop* pop);
 
 typedef struct spr_gen_stats {

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libspr.so")
 
 SIZES = (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024)
 # sizes compiled with an alternative plan (variant 1) for the run-time tuner
-VARIANT_SIZES = (256, 384, 512, 768, 1024)
+VARIANT_SIZES = (128, 256, 384, 512, 768, 1024)
 ARCH = os.environ.get("SPR_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # extra compile definitions and an alternative output path (tuning builds)

@@ -193,6 +193,37 @@ struct LaunchEvents {
 
 // Per-size kernel table.  The projection-loop launchers take optional
 // LaunchEvents (null: none).
+// Resident Sequence: the ingest and up to kResMaxIters iterations of a
+// Sequence in one cooperative launch (sizes whose single launches are
+// latency-bound).  res_bar holds two words per launch position (arrivals,
+// sense), zero before the first launch; a barrier wait that runs out sets
+// bit 1 of the population's status word and ends the launch.
+constexpr int kResMaxIters = 48;
+struct ResIter {
+  int alg;
+  float beta;
+  Phase ph;
+  int out_mode;
+  Phase ph_next;
+};
+struct SeqResArgs {
+  const int* slots;
+  int nm;
+  const SlotDesc* desc;
+  float2* T;
+  float2* Y;
+  int W;
+  int t_by_slot;
+  const float2* tw;
+  int ingest;         // 1: the launch starts with the ingest of the densities
+  int ingest_mode;    // IngestMode
+  Phase ingest_ph;
+  unsigned* res_bar;  // [nm][2]
+  long long wait_ticks;  // longest barrier wait, in ticks of the device's constant-rate clock
+  int iters;
+  ResIter it[kResMaxIters];
+};
+
 struct SizeKernels {
   int n, E, T, C, RW;
   int RWI;               // rows per workgroup of the correlation argmax
@@ -206,12 +237,14 @@ struct SizeKernels {
   hipError_t (*col_corr)(const ColCorrArgs&, hipStream_t);
   hipError_t (*row_argmax)(const RowArgmaxArgs&, hipStream_t);
   hipError_t (*col_mix)(const ColMixArgs&, hipStream_t);
+  hipError_t (*seq_res)(const SeqResArgs&, hipStream_t);  // null where there is no resident form
 };
 
 // Compiled kernels of size n: variant 0 (default plan) or another variant
 // (size_variants(n) of them); null for an unsupported size or variant.
 const SizeKernels* size_kernels(int n, int variant = 0);
 int size_variants(int n);
+bool has_resident(int n);  // some variant of size n has the resident Sequence
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): multipliers 0xD2511F53, 0xCD9E8D57,

@@ -86,6 +86,7 @@ struct spr_pop {
   float* block_max = nullptr;
   float* maxv = nullptr;
   int* flags = nullptr;
+  unsigned* res_bar = nullptr;  // resident-Sequence barrier words, two per slot (sizes with that form)
   PopScalars* scal = nullptr;
   int* stats_part = nullptr;  // per-workgroup support counts of STATS
   // per-iteration Fourier error of traced iterations: [row][slot position]
@@ -478,6 +479,7 @@ struct Group {
   double* trace = nullptr;       // trace rows of the population (traced iterations only)
   int trace_cols = 0;            // slot positions per trace row
   int pos0 = 0;                  // slot position of slots[0]
+  unsigned* res_bar = nullptr;   // barrier words of the resident Sequence (>= 2 per chunk member), or null
 };
 
 int chunk_for(spr_ctx* ctx, int n, int nm) {
@@ -509,6 +511,7 @@ Group pop_group(spr_pop* pop, int scope) {
   g.trace = pop->trace;
   g.trace_cols = pop->nslots;
   g.pos0 = scope == SPR_SCOPE_CHILDREN ? pop->P : 0;
+  g.res_bar = pop->res_bar;
   return g;
 }
 
@@ -518,10 +521,51 @@ void launch_timed(spr_pop* tp, int kernel, hipStream_t s, const char* what, Fn&&
   else launch_ok(fn(nullptr), what);
 }
 
+// The resident form of a Sequence over members slots[0..nm), where the size
+// has one: no iteration is traced and the stream is not being captured.  The
+// iterations go kResMaxIters to a launch; returns false when the Sequence
+// must run as launch pairs.
+bool run_resident(const Group& g, const std::vector<Iter>& its, int c0, int nm, hipStream_t s) {
+  if (!g.K->seq_res || !g.res_bar || g.t_by_slot) return false;
+  for (const auto& it : its)
+    if (it.trace) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+  SeqResArgs a{};
+  a.slots = g.slots + c0;
+  a.nm = nm;
+  a.desc = g.desc;
+  a.T = g.T;
+  a.Y = g.Y;
+  a.W = g.W;
+  a.t_by_slot = 0;
+  a.tw = twiddles(g.ctx, g.n);
+  a.ingest_mode = its[0].alg == ALG_ER ? INGEST_PC : INGEST_PLAIN;
+  a.ingest_ph = phase_of(its[0].chi);
+  a.res_bar = g.res_bar;
+  for (size_t i0 = 0; i0 < its.size(); i0 += kResMaxIters) {
+    const size_t i1 = std::min(its.size(), i0 + (size_t)kResMaxIters);
+    a.ingest = i0 == 0;
+    a.iters = (int)(i1 - i0);
+    for (size_t i = i0; i < i1; ++i) {
+      const bool last = i + 1 == its.size();
+      ResIter& q = a.it[i - i0];
+      q.alg = its[i].alg;
+      q.beta = its[i].beta;
+      q.ph = phase_of(its[i].chi);
+      q.out_mode = last ? OUT_REAL : (its[i + 1].alg == ALG_ER ? OUT_T_PC : OUT_T_PLAIN);
+      q.ph_next = last ? phase_of(1.0) : phase_of(its[i + 1].chi);
+    }
+    launch_ok(g.K->seq_res(a, s), "seq_res");
+  }
+  return true;
+}
+
 // One Sequence over members slots[0..nm): ingest, then per iteration a column
 // pass and a row pass.
 void run_iterations_on(const Group& g, const std::vector<Iter>& its, int c0, int nm, int trace_row0,
                        hipStream_t s) {
+  if (run_resident(g, its, c0, nm, s)) return;
   const int* slots = g.slots + c0;
   const SizeKernels* K = g.K;
   const float2* tw = twiddles(g.ctx, g.n);
@@ -1007,6 +1051,7 @@ void destroy_pop(spr_pop* p) {
   dfree(p->block_max);
   dfree(p->maxv);
   dfree(p->flags);
+  dfree(p->res_bar);
   dfree(p->scal);
   dfree(p->stats_part);
   dfree(p->trace);

@@ -57,6 +57,7 @@ using RowL = Lds<1, SPR_ROW_PAD, kRowWave>;
 #endif
 // column tile: position p of column c at (p + p / PAD) * C + c
 using ColL = Lds<C, SPR_COL_PAD, false>;
+constexpr size_t kColLdsBytes() { return (size_t)C * ColL::span(N) * sizeof(float2); }
 constexpr int NR = RowL::span(N);  // LDS elements per row
 static_assert(N % C == 0, "column tile must divide N");
 
@@ -90,6 +91,9 @@ typedef float F2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float2 gload(const float2* p, size_t i) {
   const F2v v = gview(reinterpret_cast<const F2v*>(p))[i];
   return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore(float2* p, size_t i, float2 v) {
+  ((__attribute__((address_space(1))) F2v*)(p))[i] = F2v{v.x, v.y};
 }
 
 // Buffer descriptors for the column tiles: a lane's E accesses t + T*m of
@@ -259,11 +263,11 @@ __device__ __forceinline__ float2 modulus_replace(float2 X, float stored, float 
 // ---------------------------------------------------------------------------
 // Row ingest: real-space density -> (optional constraint) -> row FFT.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
-  extern __shared__ float2 lds[];
+// Row group blk (rows blk*RW ... of the launch's members) of the ingest.
+__device__ __forceinline__ void row_ingest_body(RowIngestArgs a, int blk, float2* lds) {
   const int tid = threadIdx.x;
   const int r = tid / T, t = tid % T;
-  const int grow = blockIdx.x * RW + r;
+  const int grow = blk * RW + r;
   const bool valid = kRowsExact || grow < a.nm * N;
   const int member = valid ? row_member(grow) : 0;
   const int row = valid ? grow % N : 0;
@@ -286,8 +290,13 @@ __global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
   float2* Tw = a.t_by_slot ? d.T + off : a.T + toff;
   if (valid) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) Tw[t + T * m] = v[m];
+    for (int m = 0; m < E; ++m) gstore(Tw, t + T * m, v[m]);
   }
+}
+
+__global__ __launch_bounds__(RW* T) void k_row_ingest(RowIngestArgs a) {
+  extern __shared__ float2 lds[];
+  row_ingest_body(a, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -333,12 +342,11 @@ __device__ __forceinline__ void col_proj_tile(float2 (&v)[E], const float (&mv)[
   }
 }
 
+// Column tile id of the projection.
 template <bool TRACE>
-__global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
-  extern __shared__ float2 lds[];
+__device__ __forceinline__ void col_proj_body(ColProjArgs a, TileId id, float2* lds) {
   const int tid = threadIdx.x;
   const int c = tid % C, t = tid / C;
-  const TileId id = col_tile_id();
   const int col = id.tile * C + c;
   float2* dst = a.Y + (size_t)id.img * NN;
   const SlotDesc d = a.desc[a.slots[id.img]];
@@ -354,6 +362,12 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
                        TRACE ? a.trace_partial + (size_t)id.img * (N / C) + id.tile : nullptr);
 }
 
+template <bool TRACE>
+__global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
+  extern __shared__ float2 lds[];
+  col_proj_body<TRACE>(a, col_tile_id(), lds);
+}
+
 // ---------------------------------------------------------------------------
 // Row update: row IFFTs -> ER/HIO/RAAR real-space step -> next row FFT (or the
 // final real-space density).
@@ -361,12 +375,12 @@ __global__ __launch_bounds__(C* T) void k_col_proj(ColProjArgs a) {
 // SPEC 0 takes the algorithm at run time (per-member parameters); 1, 2, 3 are
 // ER, HIO and RAAR compiled alone, which frees the registers of the paths a
 // uniform launch never takes.
+// Row group blk of the row pass.
 template <int SPEC>
-__global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
-  extern __shared__ float2 lds[];
+__device__ __forceinline__ void row_update_body(RowUpdateArgs a, int blk, float2* lds) {
   const int tid = threadIdx.x;
   const int r = tid / T, t = tid % T;
-  const int grow = blockIdx.x * RW + r;
+  const int grow = blk * RW + r;
   const bool valid = kRowsExact || grow < a.nm * N;
   const int member = valid ? row_member(grow) : 0;
   const int row = valid ? grow % N : 0;
@@ -401,10 +415,10 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   const uint32_t smask = (ia || out_mode == OUT_T_PC) ? load_row_mask(d.S, row, t) : 0u;
   float2 y[E], x[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) y[m] = valid ? a.Y[toff + t + T * m] : make_float2(0.f, 0.f);
+  for (int m = 0; m < E; ++m) y[m] = valid ? gload(a.Y, toff + t + T * m) : make_float2(0.f, 0.f);
   if (ia) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) x[m] = valid ? Tw[t + T * m] : make_float2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) x[m] = valid ? gload(Tw, t + T * m) : make_float2(0.f, 0.f);
   }
   // keep every load of the row ahead of the first transform (compiler fence
   // only: no instruction), so that all of them are in flight together
@@ -443,7 +457,7 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   if (out_mode == OUT_REAL) {
     if (valid) {
 #pragma unroll
-      for (int m = 0; m < E; ++m) d.X[off + t + T * m] = xn[m];
+      for (int m = 0; m < E; ++m) gstore(d.X, off + t + T * m, xn[m]);
     }
     return;
   }
@@ -459,8 +473,14 @@ __global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
   fft<N, -1, RowL>(xn, l, t, a.tw, ws);
   if (valid) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) Tw[t + T * m] = xn[m];
+    for (int m = 0; m < E; ++m) gstore(Tw, t + T * m, xn[m]);
   }
+}
+
+template <int SPEC>
+__global__ __launch_bounds__(RW* T) void k_row_update(RowUpdateArgs a) {
+  extern __shared__ float2 lds[];
+  row_update_body<SPEC>(a, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -723,9 +743,113 @@ __global__ __launch_bounds__(C* T) void k_col_mix(ColMixArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Resident Sequence (128^2): one cooperative launch runs the ingest and the
+// iterations of a Sequence.  K = N / RW workgroups work on each member: in a
+// row pass workgroup k takes the member's row group k, in a column pass its
+// column tile k (RW * T = C * T threads either way), so each pass is the body
+// of the launch-per-pass kernels and the results are the same bits.  Between
+// passes the member's K workgroups meet at a barrier in device memory.
+// Measured at 128^2 with 8 members, it runs 1.8 times slower than the launch
+// pairs (18.7 against 10.4 us per iteration: the device-scope release and
+// acquire of each barrier cost more than a launch), so it is the size's
+// alternative plan (variant 1), which the run-time tuner weighs, and the
+// launch pairs stay the default.
+// ---------------------------------------------------------------------------
+#if SPR_N == 128 && SPR_VARIANT == 1
+#define SPR_SEQ_RES 1
+constexpr int kResK = N / RW;
+constexpr size_t kResLds = kColLdsBytes() > (size_t)RW * NR * sizeof(float2) ? kColLdsBytes()
+                                                                             : (size_t)RW * NR * sizeof(float2);
+
+// Sense-reversing barrier of the K workgroups of one member: bar[0] counts
+// arrivals, bar[1] is the sense the last arrival publishes.  Each workgroup
+// reads the sense once before its first arrival (the sense changes only when
+// every workgroup has arrived); the count returns to zero at every barrier, so
+// the words stay valid for the next launch.  A wait ends early when it passes
+// wait_ticks of the device's constant-rate clock or when bit 1 of the
+// population's status word is set (by a wait that ran out elsewhere); the
+// workgroup then sets that bit and leaves, and every other workgroup of the
+// population follows within one poll.
+__device__ __forceinline__ bool res_barrier(unsigned* bar, unsigned& sense, int* status, int* bail,
+                                            long long wait_ticks) {
+  __syncthreads();  // the workgroup's stores are complete
+  if (threadIdx.x == 0) {
+    sense ^= 1u;
+    __threadfence();  // release them at device scope before arriving
+    const unsigned arrived = atomicAdd(&bar[0], 1u);
+    if (arrived == (unsigned)kResK - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar[1], sense, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const long long t0 = wall_clock64();
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != sense) {
+        if (wall_clock64() - t0 > wait_ticks ||
+            (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2)) {
+          atomicOr(status, 2);
+          *bail = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __threadfence();  // acquire the other workgroups' stores
+  }
+  __syncthreads();
+  return *bail == 0;
+}
+
+__global__ __launch_bounds__(RW* T) void k_seq_res(SeqResArgs a) {
+  extern __shared__ float2 lds[];
+  __shared__ int bail;
+  const int member = blockIdx.x / kResK, k = blockIdx.x % kResK;
+  unsigned* bar = a.res_bar + 2 * member;
+  int* status = a.desc[a.slots[member]].flags;
+  unsigned sense = 0;
+  if (threadIdx.x == 0) {
+    // a population whose earlier resident launch ran out of a wait stays
+    // stopped until the host has reset its barrier words
+    bail = (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) ? 1 : 0;
+    sense = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (bail) return;
+  const int blk = member * kResK + k;  // the member's row group k in launch-wide numbering
+  if (a.ingest) {
+    RowIngestArgs ia{a.slots, a.nm, a.desc, a.T, a.W, a.t_by_slot, a.ingest_mode, a.ingest_ph, a.tw};
+    row_ingest_body(ia, blk, lds);
+    if (!res_barrier(bar, sense, status, &bail, a.wait_ticks)) return;
+  }
+  const ColProjArgs ca{a.slots, a.nm, a.desc, a.t_by_slot, a.T, a.Y, a.tw, nullptr};
+  for (int i = 0; i < a.iters; ++i) {
+    col_proj_body<false>(ca, TileId{k, member}, lds);
+    if (!res_barrier(bar, sense, status, &bail, a.wait_ticks)) return;
+    const ResIter q = a.it[i];
+    RowUpdateArgs ra;
+    ra.slots = a.slots;
+    ra.nm = a.nm;
+    ra.desc = a.desc;
+    ra.Y = a.Y;
+    ra.T = a.T;
+    ra.W = a.W;
+    ra.t_by_slot = a.t_by_slot;
+    ra.ip = nullptr;
+    ra.alg = q.alg;
+    ra.beta = q.beta;
+    ra.ph = q.ph;
+    ra.out_mode = q.out_mode;
+    ra.ph_next = q.ph_next;
+    ra.tw = a.tw;
+    if (q.alg == ALG_ER) row_update_body<1>(ra, blk, lds);
+    else row_update_body<0>(ra, blk, lds);
+    if (i + 1 < a.iters && !res_barrier(bar, sense, status, &bail, a.wait_ticks)) return;
+  }
+}
+#endif
+
+// ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-constexpr size_t kColLds = (size_t)C * ColL::span(N) * sizeof(float2);
+constexpr size_t kColLds = kColLdsBytes();
 constexpr size_t kRowLds = (size_t)RW * NR * sizeof(float2);
 constexpr size_t kRowLdsI = (size_t)RWI * NR * sizeof(float2);
 
@@ -804,10 +928,52 @@ hipError_t l_col_mix(const ColMixArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+#ifdef SPR_SEQ_RES
+hipError_t l_seq_res(const SeqResArgs& a, hipStream_t s) {
+  static_assert(RW * T == C * T && N / RW == N / C, "row groups and column tiles must pair up");
+  static const hipError_t init = set_lds(k_seq_res, kResLds);
+  if (init != hipSuccess) return init;
+  // members per launch: every workgroup of a cooperative launch is resident
+  static int per_dev[64] = {0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  static long long ticks_dev[64] = {0};
+  if (per_dev[dev] == 0) {
+    int cus = 0, per_cu = 0, khz = 0;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev)) != hipSuccess) return e;
+    ticks_dev[dev] = (long long)(khz > 0 ? khz : 100000) * 50;  // 50 ms
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_seq_res, RW * T, kResLds)) != hipSuccess)
+      return e;
+    per_dev[dev] = cus * per_cu / kResK;
+    if (per_dev[dev] < 1) return hipErrorCooperativeLaunchTooLarge;
+  }
+  for (int m0 = 0; m0 < a.nm; m0 += per_dev[dev]) {
+    SeqResArgs c = a;
+    c.wait_ticks = ticks_dev[dev];
+    c.slots = a.slots + m0;
+    c.nm = a.nm - m0 < per_dev[dev] ? a.nm - m0 : per_dev[dev];
+    if (!a.t_by_slot) c.T = a.T + (size_t)m0 * NN;
+    c.Y = a.Y + (size_t)m0 * NN;
+    c.res_bar = a.res_bar + 2 * (size_t)m0;
+    const int grid = c.nm * kResK;
+    void* args[] = {&c};
+    e = hipLaunchCooperativeKernel((const void*)k_seq_res, dim3(grid), dim3(RW * T), args, (unsigned)kResLds, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+#define SPR_SEQ_RES_FN l_seq_res
+#else
+#define SPR_SEQ_RES_FN nullptr
+#endif
+
 const SizeKernels kTable = {N,          E,          T,          C,           RW,         RWI,
                             kColLds,    kRowLds,    l_row_ingest, l_col_proj, l_row_update,
                             l_col_err,  l_row_fft,  l_col_fft,  l_col_corr,  l_row_argmax,
-                            l_col_mix};
+                            l_col_mix,  SPR_SEQ_RES_FN};
 
 }  // namespace
 

@@ -21,7 +21,7 @@ namespace spr {
 
 // sizes with one compiled plan (V1) and with a tunable alternative (V2)
 #define SPR_SIZES(V1, V2)                                                                  \
-  V1(8) V1(12) V1(16) V1(24) V1(32) V1(48) V1(64) V1(96) V1(128) V1(192) V2(256) V2(384) \
+  V1(8) V1(12) V1(16) V1(24) V1(32) V1(48) V1(64) V1(96) V2(128) V1(192) V2(256) V2(384) \
       V2(512) V2(768) V2(1024)
 #define SPR_DECL1(n) const SizeKernels* size_kernels_##n##_0();
 #define SPR_DECL2(n) SPR_DECL1(n) const SizeKernels* size_kernels_##n##_1();
@@ -49,6 +49,12 @@ int size_variants(int n) {
   int v = 0;
   while (size_kernels(n, v)) ++v;
   return v;
+}
+
+bool has_resident(int n) {
+  for (int v = 0; v < size_variants(n); ++v)
+    if (size_kernels(n, v)->seq_res) return true;
+  return false;
 }
 
 }  // namespace spr
@@ -214,6 +220,7 @@ spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const ui
       pop->block_max = dalloc<float>(ns * smooth_blocks_per_member(pop->n));
       pop->maxv = dalloc<float>(ns);
       pop->flags = dalloc<int>(1);
+      if (has_resident(pop->n)) pop->res_bar = dalloc<unsigned>(2 * ns);
       pop->scal = dalloc<PopScalars>(1);
       pop->stats_part = dalloc<int>(2 * stats_workgroups(pop->W));
       pop->hist = dalloc<GenStatsDev>(pop->hist_cap);
@@ -239,6 +246,7 @@ spr_status spr_pop_create(spr_shot* shot, int32_t P, const float* rho0, const ui
       // on the context stream, ahead of the start-up kernels below
       hipStream_t cs = ctx->stream;
       HIPCHK(hipMemsetAsync(pop->flags, 0, sizeof(int), cs));
+      if (pop->res_bar) HIPCHK(hipMemsetAsync(pop->res_bar, 0, 2 * ns * sizeof(unsigned), cs));
       HIPCHK(hipMemsetAsync(pop->scal, 0, sizeof(PopScalars), cs));
       HIPCHK(hipMemsetAsync(pop->hist, 0, sizeof(GenStatsDev) * pop->hist_cap, cs));
       HIPCHK(hipMemsetAsync(pop->S, 0, ns * pop->W * sizeof(uint32_t), cs));
@@ -563,6 +571,21 @@ spr_status spr_run_batch(spr_ctx* ctx, spr_pop* const* pops, const spr_sched* co
   });
 }
 
+// The population's status word after its work: a resident Sequence that ran
+// out of its barrier wait (bit 1) left results that are not valid; the barrier
+// words are reset so the population can run again, and the call fails.
+int check_resident_status(spr_pop* pop) {
+  int f = 0;
+  HIPCHK(hipMemcpy(&f, pop->flags, sizeof(int), hipMemcpyDeviceToHost));
+  if (f & 2) {
+    HIPCHK(hipMemset(pop->res_bar, 0, 2 * (size_t)pop->nslots * sizeof(unsigned)));
+    const int keep = f & ~2;
+    HIPCHK(hipMemcpy(pop->flags, &keep, sizeof(int), hipMemcpyHostToDevice));
+    fail(SPR_E_HIP, "a resident Sequence's barrier wait timed out");
+  }
+  return f;
+}
+
 spr_status spr_sync(spr_pop* pop) {
   if (!pop) return SPR_E_INVALID_ARG;
   if (!live_has(pop)) return SPR_E_INVALID_ARG;
@@ -570,8 +593,7 @@ spr_status spr_sync(spr_pop* pop) {
   return guarded(ctx, [&] {
     use_device(ctx);
     sync_pop(pop);
-    int f = 0;
-    HIPCHK(hipMemcpy(&f, pop->flags, sizeof(int), hipMemcpyDeviceToHost));
+    const int f = check_resident_status(pop);
     if (f & 1) fail(SPR_E_NUMERIC, "a fitness value is not finite");
   });
 }
@@ -583,6 +605,7 @@ spr_status spr_read(spr_pop* pop, float* rho, uint8_t* supp, double* err, uint32
   return guarded(ctx, [&] {
     use_device(ctx);
     sync_pop(pop);
+    if (pop->res_bar) check_resident_status(pop);
     const bool kids = flags & SPR_READ_CHILDREN;
     if (kids) need_memetic(pop, "reading children");
     const bool dev = flags & SPR_DEVICE_PTRS;
@@ -892,12 +915,13 @@ spr_status spr_ctx_autotune(spr_ctx* ctx, int32_t n, int32_t members, spr_tune_r
     double *E = nullptr, *errp = nullptr;
     float *bmax = nullptr, *maxv = nullptr;
     int *flags = nullptr, *slots = nullptr;
+    unsigned* rbar = nullptr;
     SlotDesc* desc = nullptr;
     std::vector<hipEvent_t> ev;
     auto cleanup = [&] {
       (void)hipStreamSynchronize(s);
       for (void* q : {(void*)amp, (void*)X, (void*)T, (void*)Y, (void*)S, (void*)E, (void*)errp, (void*)bmax,
-                      (void*)maxv, (void*)flags, (void*)slots, (void*)desc})
+                      (void*)maxv, (void*)flags, (void*)slots, (void*)desc, (void*)rbar})
         if (q) (void)hipFree(q);
       for (auto e : ev) (void)hipEventDestroy(e);
     };
@@ -915,6 +939,10 @@ spr_status spr_ctx_autotune(spr_ctx* ctx, int32_t n, int32_t members, spr_tune_r
       flags = dalloc<int>(1);
       slots = dalloc<int>(members);
       desc = dalloc<SlotDesc>(members);
+      if (has_resident(n)) {
+        rbar = dalloc<unsigned>(2 * (size_t)members);
+        HIPCHK(hipMemset(rbar, 0, 2 * (size_t)members * sizeof(unsigned)));
+      }
       HIPCHK(hipMemcpy(amp, one.data(), nn * sizeof(float), hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(S, bits.data(), bits.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(slots, ident.data(), sizeof(int) * members, hipMemcpyHostToDevice));
@@ -964,6 +992,7 @@ spr_status spr_ctx_autotune(spr_ctx* ctx, int32_t n, int32_t members, spr_tune_r
           g.flags = flags;
           g.timing = nullptr;
           g.chunk = c;
+          g.res_bar = rbar;
           run_iterations(g, its, s);  // warm-up
           HIPCHK(hipEventRecord(ev[0], s));
           for (int rep = 0; rep < 3; ++rep) run_iterations(g, its, s);

@@ -187,6 +187,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--precision", action="store_true", help="FP16 against FP32 modulus storage at 512^2")
     ap.add_argument("--plain-128", action="store_true", help="the plain method at 128^2 against the oracle")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="kernel variant of the 128^2 study (1: the resident Sequence)")
     args = ap.parse_args()
     if not (args.precision or args.plain_128):
         ap.error("choose --precision or --plain-128")
@@ -197,7 +199,8 @@ def main():
     if args.precision:
         print(json.dumps({"precision": precision_study(ctx, B)}), flush=True)
     else:
-        print(json.dumps({"plain_128": plain_128_study(ctx, B)}), flush=True)
+        ctx.set_variant(128, args.variant)
+        print(json.dumps({"plain_128": {"variant": args.variant, **plain_128_study(ctx, B)}}), flush=True)
     ctx.close()
 
 

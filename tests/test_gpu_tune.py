@@ -11,7 +11,7 @@ from gpu_cases import Case, rel
 
 pytestmark = pytest.mark.gpu
 
-VARIANT_SIZES = (256, 384, 512, 768, 1024)
+VARIANT_SIZES = (128, 256, 384, 512, 768, 1024)
 
 
 @pytest.fixture(scope="module")
