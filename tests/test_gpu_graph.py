@@ -39,10 +39,11 @@ def _same(pa, pb, children=False):
         np.testing.assert_array_equal(u, v)
 
 
-@pytest.mark.parametrize("n,variant", [(32, 0), (128, 0), (384, 1), (512, 0)])
+@pytest.mark.parametrize("n,variant", [(32, 0), (128, 0), (128, 1), (384, 1), (512, 0)])
 def test_population_graph_replays_match_eager(ctx, B, n, variant):
     # (384, 1): a graph recorded on a size's alternative plan, taken from the
-    # context when the populations are created
+    # context when the populations are created; (128, 1): eager runs use the
+    # resident Sequence, the captured graph the launch pairs it falls back to
     ctx.set_variant(n, variant)
     try:
         _graph_replays(ctx, B, n)
