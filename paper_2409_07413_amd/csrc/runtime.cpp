@@ -939,6 +939,7 @@ spr_status spr_ctx_autotune(spr_ctx* ctx, int32_t n, int32_t members, spr_tune_r
       flags = dalloc<int>(1);
       slots = dalloc<int>(members);
       desc = dalloc<SlotDesc>(members);
+      HIPCHK(hipMemset(flags, 0, sizeof(int)));
       if (has_resident(n)) {
         rbar = dalloc<unsigned>(2 * (size_t)members);
         HIPCHK(hipMemset(rbar, 0, 2 * (size_t)members * sizeof(unsigned)));
@@ -1000,7 +1001,17 @@ spr_status spr_ctx_autotune(spr_ctx* ctx, int32_t n, int32_t members, spr_tune_r
           HIPCHK(hipEventSynchronize(ev[1]));
           float ms = 0.f;
           HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
-          const double rate = (double)members * its.size() * 3 / (ms * 1e-3);
+          double rate = (double)members * its.size() * 3 / (ms * 1e-3);
+          if (rbar) {
+            // a resident candidate whose barrier wait ran out did no valid work
+            int f = 0;
+            HIPCHK(hipMemcpy(&f, flags, sizeof(int), hipMemcpyDeviceToHost));
+            if (f & 2) {
+              rate = 0.0;
+              HIPCHK(hipMemset(flags, 0, sizeof(int)));
+              HIPCHK(hipMemset(rbar, 0, 2 * (size_t)members * sizeof(unsigned)));
+            }
+          }
           if (nc < SPR_TUNE_MAX) {
             out->cand_variant[nc] = v;
             out->cand_chunk[nc] = c;

@@ -67,6 +67,16 @@ def test_autotune_keeps_its_choice(ctx, B):
     ctx.set_variant(256, 0)
 
 
+def test_autotune_times_the_resident_variant(ctx, B):
+    # at 128^2 variant 1 is the resident Sequence: the tuner times it beside
+    # the launch pairs (a candidate whose barrier wait ran out would report 0)
+    r = ctx.autotune(128, 8)
+    rates = {c["variant"]: c["member_iterations_per_s"] for c in r["candidates"]}
+    assert set(rates) == {0, 1} and min(rates.values()) > 0
+    print(f"autotune 128^2, 8 members: {rates}")
+    ctx.set_variant(128, 0)
+
+
 def test_batch_rejects_mixed_variants(ctx, B):
     a, b = Case(256, 2, seed=1), Case(256, 2, seed=2)
     ctx.set_variant(256, 0)
