@@ -933,6 +933,8 @@ def main():
         ctx = B.Context(0)
         res = serving_leg(ctx, B, rates, counts, args.serve_max_shots, int(args.serve_budget_gib * (1 << 30)),
                           forms, log, shortest=args.serve_policy == "shortest", tune=not args.serve_no_tune)
+        for rec in res:  # the kept result densities feed only the full run's oracle check
+            rec.get("served", {}).pop("_samples", None)
         print(json.dumps({"serving": res, "config": {
             "workload": "serving stream: Poisson arrivals, sizes uniform over 256..1024 (5 sizes), "
                         "5 ellipses in a 40-px disk, 1e6 photons, 8x8 beamstop, P=32, 500 iterations",
