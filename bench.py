@@ -851,7 +851,7 @@ def main():
     ap.add_argument("--serve-rates", type=str, default="50,5",
                     help="Poisson arrival rates (shots/s) of the serving leg")
     ap.add_argument("--serve-shots", type=str, default="60,20", help="shots per rate")
-    ap.add_argument("--serve-max-shots", type=int, default=4, help="shots resident at once in the server")
+    ap.add_argument("--serve-max-shots", type=int, default=8, help="shots resident at once in the server")
     ap.add_argument("--serve-budget-gib", type=float, default=48.0, help="device memory of the server")
     ap.add_argument("--serve-forms", type=str, default="served,plain")
     ap.add_argument("--serve-policy", choices=("shortest", "all"), default="shortest",
