@@ -76,7 +76,7 @@ def kernel_sources_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_key, chunk):
+def measured_traffic(kernel, chunk):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE measurement (copy-kernel calibrated, averaged over
     the kernel's launches in the measured generation), or None when the
@@ -90,7 +90,7 @@ def measured_traffic(kernel_key, chunk):
         return None
     if t.get("sources_digest") != kernel_sources_digest() or t.get("members_per_launch") != chunk:
         return None
-    return t.get("kernels", {}).get(str(kernel_key), {}).get("hbm_bytes_per_launch")
+    return t.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
 
 def trace_averages(chunk):
@@ -1023,7 +1023,7 @@ def main():
                    + n_ia * algorithmic_bytes_per_px(B.KERNEL_ROW_UPDATE_IA, chunk)) * N * N * chunk
     bytes_per_launch = bytes_total / n_l
     achieved = bytes_per_launch / (ms / n_l * 1e-3) / 1e9
-    t_er, t_ia = measured_traffic("row_update_er", chunk), measured_traffic("row_update_ia", chunk)
+    t_er, t_ia = measured_traffic("k_row_update_er", chunk), measured_traffic("k_row_update_ia", chunk)
     traffic = (n_er * t_er + n_ia * t_ia) / n_l if t_er is not None and t_ia is not None else None
     roof_row = {"bound": "hbm", "kernel": "k_row_update", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -1034,7 +1034,7 @@ def main():
     cp_achieved = cp_bytes / (ms_cp / n_cp * 1e-3) / 1e9
     roof_col = {"bound": "hbm", "kernel": "k_col_proj", "achieved": cp_achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": cp_achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(B.KERNEL_COL_PROJ, chunk), "launches": n_cp,
+                "traffic": measured_traffic("k_col_proj", chunk), "launches": n_cp,
                 "avg_launch_us": ms_cp / n_cp * 1e3, "timed_ms": ms_cp, "algorithmic_bytes_per_launch": cp_bytes,
                 "sample_every": args.timing_every}
     tr = trace_averages(chunk)

@@ -246,3 +246,17 @@ def test_benchmark_reaches_the_oracle_only_in_its_cpu_baseline():
     # cpu_baseline and the workers it runs per member (timing and the
     # device-against-oracle check)
     assert users == {"cpu_baseline", "_oracle_timed", "_oracle_check"}, users
+
+
+def test_benchmark_finds_its_committed_profiles(monkeypatch):
+    # the bench line's `traffic` and `trace_frac` come from the committed
+    # rocprofv3 summaries, looked up by kernel name; with the digest the
+    # summaries were taken under, every loop kernel the line reports resolves
+    import json
+    import bench
+    t = json.load(open(os.path.join(ROOT, "profiles", "traffic_512_pop64.json")))
+    monkeypatch.setattr(bench, "kernel_sources_digest", lambda: t["sources_digest"])
+    chunk = t["members_per_launch"]
+    for k in ("k_col_proj", "k_row_update_er", "k_row_update_ia"):
+        assert bench.measured_traffic(k, chunk) > 0
+        assert bench.trace_averages(chunk)[k] > 0
