@@ -63,8 +63,10 @@ def _same(a, b):
         assert np.array_equal(np.asarray(x).view(np.uint8), np.asarray(y).view(np.uint8))
 
 
-@pytest.mark.parametrize("P", [8, 5, 13])
+@pytest.mark.parametrize("P", [1, 5, 8, 13, 100])
 def test_plain_schedule_same_bits(ctx, B, P):
+    # 100 members exceed one cooperative launch's resident workgroups (8 per
+    # member), so the launcher splits them over several launches
     c = Case(N, P, seed=40 + P)
     make = lambda: B.sched_plain(ctx, alg=B.ALG_HIO, G=3, j=16, j_er=4, j_end=0, beta=0.9, chi=0.5,
                                  sigma=2.0, sigma_end=1.0, tau=0.1, tau_end=0.1)
