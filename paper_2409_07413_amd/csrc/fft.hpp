@@ -66,10 +66,11 @@ SPR_DEFINE_PLAN(64, 8, 16, 8, 8)
 SPR_DEFINE_PLAN(96, 24, 16, 3, 4, 8)
 SPR_DEFINE_PLAN(128, 8, 16, 2, 8, 8)
 SPR_DEFINE_PLAN(192, 24, 16, 3, 8, 8)
-// 384 and 768: twelve elements per thread with the radix-3 pass last, so
-// that the strides of the earlier passes divide T (one twiddle set per pass,
-// kept in registers) and the first exchange is not a stride-3 pattern;
-// 1024: the radix-16 pass last.
+// 384 and 768: twelve elements per thread with the pass holding the factor 3
+// last (radix 6 = 2 x 3, radix 12 = 4 x 3, prime-factor butterflies), so that
+// the strides of the earlier passes divide T (one twiddle set per pass, kept
+// in registers), the first exchange is not a stride-3 pattern, and the
+// transform takes four passes; 1024: the radix-16 pass last.
 //
 // Variant 1 of the served sizes is the alternative that a run-time tuner
 // weighs against the default: the other column-tile width (256 to 768) or
@@ -80,14 +81,14 @@ SPR_DEFINE_PLAN(192, 24, 16, 3, 8, 8)
 #if SPR_VARIANT == 1
 SPR_DEFINE_PLAN(256, 8, 8, 4, 8, 8)
 SPR_DEFINE_PLAN(512, 8, 16, 8, 8, 8)
-SPR_DEFINE_PLAN(384, 12, 16, 4, 4, 4, 2, 3)
-SPR_DEFINE_PLAN(768, 12, 16, 4, 4, 4, 4, 3)
+SPR_DEFINE_PLAN(384, 12, 16, 4, 4, 4, 6)
+SPR_DEFINE_PLAN(768, 12, 16, 4, 4, 4, 12)
 SPR_DEFINE_PLAN(1024, 16, 8, 16, 8, 8)
 #else
 SPR_DEFINE_PLAN(256, 8, 16, 4, 8, 8)
 SPR_DEFINE_PLAN(512, 8, 8, 8, 8, 8)
-SPR_DEFINE_PLAN(384, 12, 8, 4, 4, 4, 2, 3)
-SPR_DEFINE_PLAN(768, 12, 8, 4, 4, 4, 4, 3)
+SPR_DEFINE_PLAN(384, 12, 8, 4, 4, 4, 6)
+SPR_DEFINE_PLAN(768, 12, 8, 4, 4, 4, 12)
 SPR_DEFINE_PLAN(1024, 16, 8, 8, 8, 16)
 #endif
 
@@ -176,12 +177,62 @@ template <int DIR> __device__ __forceinline__ void dft16(float2* a) {
   }
 }
 
+// Radices 6 = 2 x 3 and 12 = 4 x 3 as prime-factor (Good-Thomas) transforms:
+// with coprime factors R = R1 R2, input n = (R2 n1 + R1 n2) mod R and output
+// k = (R2 (R2^-1 mod R1) k1 + R1 (R1^-1 mod R2) k2) mod R turn the R-point DFT
+// into R1-point DFTs over n1 and R2-point DFTs over n2 with no twiddles.
+template <int DIR> __device__ __forceinline__ void dft6(float2* a) {
+  // n = 3 n1 + 2 n2, k = 3 k1 + 4 k2 (mod 6)
+  float2 b[2][3];
+#pragma unroll
+  for (int n2 = 0; n2 < 3; ++n2) {
+    float2 x0 = a[(2 * n2) % 6], x1 = a[(3 + 2 * n2) % 6];
+    dft2<DIR>(x0, x1);
+    b[0][n2] = x0;
+    b[1][n2] = x1;
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 2; ++k1) {
+    float2 y0 = b[k1][0], y1 = b[k1][1], y2 = b[k1][2];
+    dft3<DIR>(y0, y1, y2);
+    a[(3 * k1) % 6] = y0;
+    a[(3 * k1 + 4) % 6] = y1;
+    a[(3 * k1 + 8) % 6] = y2;
+  }
+}
+
+template <int DIR> __device__ __forceinline__ void dft12(float2* a) {
+  // n = 3 n1 + 4 n2, k = 9 k1 + 4 k2 (mod 12)
+  float2 b[4][3];
+#pragma unroll
+  for (int n2 = 0; n2 < 3; ++n2) {
+    float2 x0 = a[(4 * n2) % 12], x1 = a[(3 + 4 * n2) % 12], x2 = a[(6 + 4 * n2) % 12],
+           x3 = a[(9 + 4 * n2) % 12];
+    dft4<DIR>(x0, x1, x2, x3);
+    b[0][n2] = x0;
+    b[1][n2] = x1;
+    b[2][n2] = x2;
+    b[3][n2] = x3;
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 y0 = b[k1][0], y1 = b[k1][1], y2 = b[k1][2];
+    dft3<DIR>(y0, y1, y2);
+    a[(9 * k1) % 12] = y0;
+    a[(9 * k1 + 4) % 12] = y1;
+    a[(9 * k1 + 8) % 12] = y2;
+  }
+}
+
 template <int R, int DIR> __device__ __forceinline__ void butterfly(float2* a) {
   if constexpr (R == 2) dft2<DIR>(a[0], a[1]);
   else if constexpr (R == 3) dft3<DIR>(a[0], a[1], a[2]);
   else if constexpr (R == 4) dft4<DIR>(a[0], a[1], a[2], a[3]);
+  else if constexpr (R == 6) dft6<DIR>(a);
   else if constexpr (R == 8) dft8<DIR>(a);
+  else if constexpr (R == 12) dft12<DIR>(a);
   else if constexpr (R == 16) dft16<DIR>(a);
+  else static_assert(R == 2, "unsupported radix");
 }
 
 // Twiddle exp(DIR 2 pi i e / N) from the forward table.
@@ -200,7 +251,8 @@ template <int DIR> __device__ __forceinline__ float2 twiddle(const float2* __res
 // log2 R for the power-of-two radices.
 template <int R, int DIR>
 __device__ __forceinline__ void twiddles_for(const float2* __restrict__ tw, int b, float2* w) {
-  if constexpr (SPR_TW_MODE == 0 || R <= 3) {
+  if constexpr (SPR_TW_MODE == 0 || R <= 3 || (R & (R - 1)) != 0) {
+    // every value from the table (also for radices that are not powers of two)
 #pragma unroll
     for (int r = 1; r < R; ++r) w[r] = twiddle<DIR>(tw, r * b);
   } else {
