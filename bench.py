@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 N, P = 512, 64
 R, J, J_ER, J_EVAL = 3, 16, 4, 40
 G_SCHEDULE = 20
-CACHE_BUDGET = 256 << 20  # member chunks whose work buffers fit the 256 MiB memory-side cache
+CACHE_BUDGET = 192 << 20  # the library default: member chunks whose work buffers fill 3/4 of the 256 MiB memory-side cache
 
 
 def make_inputs():
@@ -74,6 +74,16 @@ def kernel_sources_digest():
     for f in ("fft.hpp", "kernels_n.hip", "common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2409_07413_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def member_chunk(members, n=None, budget=CACHE_BUDGET):
+    """The library's member-chunk rule for `members` members of an n x n shot
+    (default: the benchmark's): launches of as many members as the budget
+    holds, the last one with the rest; returns (members per launch, mean
+    members per launch)."""
+    n = N if n is None else n
+    chunk = min(members, max(1, budget // (2 * n * n * 8)))
+    return chunk, members / -(-members // chunk)
 
 
 def measured_traffic(kernel, chunk):
@@ -748,7 +758,7 @@ def profile_summary(d):
     d/fetch and d/write (FETCH_SIZE, WRITE_SIZE) of `bench.py --steps 2 --warmup
     1 --no-cpu-baseline --no-serve`, and d/fetch_cal, d/write_cal of `bench.py
     --copy-calibration` (256 MiB read + written per copy)."""
-    chunk = min(2 * P, max(1, CACHE_BUDGET // (2 * N * N * 8)))
+    chunk, per_launch = member_chunk(2 * P)
     digest = kernel_sources_digest()
     dur = {}
     for r in _rocprof_rows(os.path.join(d, "trace"), "kernel_trace"):
@@ -774,15 +784,17 @@ def profile_summary(d):
     fetch_factor = copy_bytes / (max(fcal) * 1024)
     write_factor = copy_bytes / (max(wcal) * 1024)
     fetch, write = counter("fetch", "FETCH_SIZE"), counter("write", "WRITE_SIZE")
-    alg = {"k_col_proj": algorithmic_bytes_per_px(1, chunk), "k_row_update_er": algorithmic_bytes_per_px(2, chunk),
-           "k_row_update_ia": algorithmic_bytes_per_px(3, chunk), "k_row_ingest": algorithmic_bytes_per_px(0, chunk)}
+    alg = {"k_col_proj": algorithmic_bytes_per_px(1, per_launch),
+           "k_row_update_er": algorithmic_bytes_per_px(2, per_launch),
+           "k_row_update_ia": algorithmic_bytes_per_px(3, per_launch),
+           "k_row_ingest": algorithmic_bytes_per_px(0, per_launch)}
     kern = {}
     for k in sorted(fetch):
         if k == "copy" or k not in write:
             continue
         f, w = float(np.mean(fetch[k])), float(np.mean(write[k]))
         hbm = (f * fetch_factor + w * write_factor) * 1024
-        a = alg[k] * N * N * chunk
+        a = alg[k] * N * N * per_launch
         kern[k] = {"dispatches": len(fetch[k]), "FETCH_SIZE_KiB_avg": f, "WRITE_SIZE_KiB_avg": w,
                    "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": a, "ratio_to_algorithmic": hbm / a}
     traffic = {"workload": trace["workload"], "members_per_launch": chunk, "sources_digest": digest,
@@ -1018,9 +1030,10 @@ def main():
 
     member_its = 2 * P * (R * (J + J_ER) + J_EVAL) * args.steps
     value = member_its / wall
-    chunk = min(2 * P, max(1, CACHE_BUDGET // (2 * N * N * 8)))
-    bytes_total = (n_er * algorithmic_bytes_per_px(B.KERNEL_ROW_UPDATE_ER, chunk)
-                   + n_ia * algorithmic_bytes_per_px(B.KERNEL_ROW_UPDATE_IA, chunk)) * N * N * chunk
+    # launches hold `chunk` members, the last the rest; byte counts use the mean
+    chunk, per_launch = member_chunk(2 * P)
+    bytes_total = (n_er * algorithmic_bytes_per_px(B.KERNEL_ROW_UPDATE_ER, per_launch)
+                   + n_ia * algorithmic_bytes_per_px(B.KERNEL_ROW_UPDATE_IA, per_launch)) * N * N * per_launch
     bytes_per_launch = bytes_total / n_l
     achieved = bytes_per_launch / (ms / n_l * 1e-3) / 1e9
     t_er, t_ia = measured_traffic("k_row_update_er", chunk), measured_traffic("k_row_update_ia", chunk)
@@ -1030,7 +1043,7 @@ def main():
                 "traffic": traffic, "launches": n_l, "avg_launch_us": ms / n_l * 1e3,
                 "timed_ms": ms, "algorithmic_bytes_per_launch": bytes_per_launch,
                 "launch_mix": {"ER": n_er, "HIO/RAAR": n_ia}, "sample_every": args.timing_every}
-    cp_bytes = algorithmic_bytes_per_px(B.KERNEL_COL_PROJ, chunk) * N * N * chunk
+    cp_bytes = algorithmic_bytes_per_px(B.KERNEL_COL_PROJ, per_launch) * N * N * per_launch
     cp_achieved = cp_bytes / (ms_cp / n_cp * 1e-3) / 1e9
     roof_col = {"bound": "hbm", "kernel": "k_col_proj", "achieved": cp_achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": cp_achieved / HBM_PEAK_GBS,
@@ -1057,7 +1070,7 @@ def main():
                 ia_its += o.count
             elif o.kind == B.OP_ER:
                 er_its += o.count
-    step_bytes = 2 * P * N * N * (ia_its * (40.125 + 4.0 / chunk) + er_its * (32.125 + 4.0 / chunk))
+    step_bytes = 2 * P * N * N * (ia_its * (40.125 + 4.0 / per_launch) + er_its * (32.125 + 4.0 / per_launch))
     pct_hbm = step_bytes / wall / (HBM_PEAK_GBS * 1e9)
     out = {
         "metric": "member-iterations/s at 512^2 pop 64 (% HBM peak); p50/p99 shot latency",
@@ -1084,7 +1097,7 @@ def main():
         "rooflines": {"k_row_update": roof_row, "k_col_proj": roof_col},
         "members_per_launch": chunk,
         "kernels": {B.KERNEL_NAMES[k]: {"launches": v[0], "avg_us": v[1] / v[0] * 1e3,
-                                        "GBps": algorithmic_bytes_per_px(k, chunk) * N * N * chunk
+                                        "GBps": algorithmic_bytes_per_px(k, per_launch) * N * N * per_launch
                                         / (v[1] / v[0] * 1e-3) / 1e9}
                     for k, v in kern.items()},
     }

@@ -83,8 +83,9 @@ const char* spr_ctx_last_error(const spr_ctx* ctx);
 /* 1 if N is a supported detector size, else 0. */
 int32_t spr_supported_size(int32_t n);
 /* Iteration runs (consecutive ER/HIO/RAAR ops) proceed in chunks of members    */
-/* whose two N x N complex work buffers fit in `bytes` (default 256 MiB, the     */
-/* memory-side cache of one MI355X); members are independent inside a run, so   */
+/* whose two N x N complex work buffers fit in `bytes` (default 192 MiB, three   */
+/* quarters of one MI355X's 256 MiB memory-side cache, which leaves room for    */
+/* the run's other buffers); members are independent inside a run, so          */
 /* results do not depend on it.  0 = one chunk.                                  */
 spr_status spr_ctx_set_cache_budget(spr_ctx* ctx, uint64_t bytes);
 
@@ -95,8 +96,8 @@ spr_status spr_ctx_set_cache_budget(spr_ctx* ctx, uint64_t bytes);
 /* barriers between passes; same results bit for bit, used when no iteration */
 /* is traced and the stream is not being captured).  spr_ctx_autotune times RAAR iterations on */
 /* `members` synthetic members of size n for every variant and member-chunk  */
-/* candidate (all members, the chunk whose two work buffers fit 256 MiB, half */
-/* of it), keeps the fastest on the context and reports every candidate.     */
+/* candidate (all members, the chunks whose two work buffers fit 256, 192   */
+/* and 128 MiB), keeps the fastest on the context and reports every one.    */
 /* The variant applies to shots (and their populations) created afterwards;  */
 /* the chunk to every later iteration run of that size.  Results do not      */
 /* depend on the choice beyond floating-point rounding of the transform.     */

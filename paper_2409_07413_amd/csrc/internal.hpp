@@ -36,12 +36,18 @@ struct Workspace {
   hipStream_t last = nullptr;  // stream of the last batch that used these buffers
 };
 
+// Default byte budget of an iteration chunk's two work buffers (spr_ctx).
+constexpr size_t kDefaultCacheBudget = (size_t)192 << 20;
+
 struct spr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   // iteration runs are split into member chunks whose two work buffers fit in
-  // this many bytes (0: no split), so that they stay in the memory-side cache
-  size_t cache_budget = (size_t)256 << 20;
+  // this many bytes (0: no split), so that they stay in the memory-side cache:
+  // three quarters of its 256 MiB, which leaves room for the modulus, the
+  // supports and the other buffers a run touches (measured at 256^2-1024^2 with
+  // 128 members: equal or faster than chunks of the whole 256 MiB at every size)
+  size_t cache_budget = kDefaultCacheBudget;
   // per-size choices of the tuner (or of the caller): kernel variant for
   // shots created from now on, members per iteration launch (0: the budget rule)
   std::map<int, int> variant;

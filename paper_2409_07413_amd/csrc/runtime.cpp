@@ -969,10 +969,13 @@ spr_status spr_ctx_autotune(spr_ctx* ctx, int32_t n, int32_t members, spr_tune_r
         ev.push_back(e);
       }
       const std::vector<Iter> its(10, Iter{ALG_RAAR, 0.9f, 0.5});
+      // chunks whose two work buffers fill the 256 MiB memory-side cache, three
+      // quarters of it (the default budget) and half of it
       std::vector<int> chunks = {members};
-      const int resident = (int)std::max<size_t>(1, ((size_t)256 << 20) / (2 * nn * sizeof(float2)));
-      for (int c : {resident, resident / 2})
-        if (c >= 1 && c < members && std::find(chunks.begin(), chunks.end(), c) == chunks.end()) chunks.push_back(c);
+      for (size_t mib : {(size_t)256, (size_t)192, (size_t)128}) {
+        const int c = (int)std::max<size_t>(1, (mib << 20) / (2 * nn * sizeof(float2)));
+        if (c < members && std::find(chunks.begin(), chunks.end(), c) == chunks.end()) chunks.push_back(c);
+      }
       double best = -1;
       int nc = 0;
       for (int v = 0; v < size_variants(n); ++v) {

@@ -162,7 +162,14 @@ def test_server_rejects(ctx, B):
     s = plain(B, ctx)
     with pytest.raises(B.SprError):
         B.Server(ctx, s, P=4, hbm_budget=1 << 20, max_shots=2)  # budget below the work buffers
-    sv = B.Server(ctx, s, P=4, hbm_budget=(300 << 20), max_shots=2, manual=True)
+    # the server reserves two work buffers of half the context's cache budget
+    # each: with 256 MiB of them, a 300 MiB budget leaves too little for the
+    # 4 members of a 1024^2 shot
+    ctx.set_cache_budget(256 << 20)
+    try:
+        sv = B.Server(ctx, s, P=4, hbm_budget=(300 << 20), max_shots=2, manual=True)
+    finally:
+        ctx.set_cache_budget(192 << 20)
     big = Case(1024, 1, seed=1)
     with pytest.raises(B.SprError) as e:
         sv.submit(big.amp32, big.mask8, big.supp8[0], seed=1)  # 4 members of 1024^2 do not fit
