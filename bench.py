@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 N, P = 512, 64
 R, J, J_ER, J_EVAL = 3, 16, 4, 40
 G_SCHEDULE = 20
-CACHE_BUDGET = 192 << 20  # the library default: member chunks whose work buffers fill 3/4 of the 256 MiB memory-side cache
+CACHE_BUDGET = 256 << 20  # the library default: the 256 MiB memory-side cache
 
 
 def make_inputs():
@@ -78,11 +78,13 @@ def kernel_sources_digest():
 
 def member_chunk(members, n=None, budget=CACHE_BUDGET):
     """The library's member-chunk rule for `members` members of an n x n shot
-    (default: the benchmark's): launches of as many members as the budget
-    holds, the last one with the rest; returns (members per launch, mean
-    members per launch)."""
+    (default: the benchmark's): one launch while their work buffers fit the
+    budget, else launches of as many members as three quarters of it hold, the
+    last one with the rest; returns (members per launch, mean members per
+    launch)."""
     n = N if n is None else n
-    chunk = min(members, max(1, budget // (2 * n * n * 8)))
+    per = 2 * n * n * 8
+    chunk = members if members * per <= budget else min(members, max(1, budget // 4 * 3 // per))
     return chunk, members / -(-members // chunk)
 
 

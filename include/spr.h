@@ -82,11 +82,11 @@ void spr_ctx_destroy(spr_ctx* ctx);
 const char* spr_ctx_last_error(const spr_ctx* ctx);
 /* 1 if N is a supported detector size, else 0. */
 int32_t spr_supported_size(int32_t n);
-/* Iteration runs (consecutive ER/HIO/RAAR ops) proceed in chunks of members    */
-/* whose two N x N complex work buffers fit in `bytes` (default 192 MiB, three   */
-/* quarters of one MI355X's 256 MiB memory-side cache, which leaves room for    */
-/* the run's other buffers); members are independent inside a run, so          */
-/* results do not depend on it.  0 = one chunk.                                  */
+/* Iteration runs (consecutive ER/HIO/RAAR ops) whose two N x N complex work    */
+/* buffers per member fit in `bytes` (default 256 MiB, the memory-side cache of */
+/* one MI355X) run as one launch per pass; larger ones in chunks of members     */
+/* whose buffers fill three quarters of it.  Members are independent inside a  */
+/* run, so results do not depend on it.  0 = one chunk.                         */
 spr_status spr_ctx_set_cache_budget(spr_ctx* ctx, uint64_t bytes);
 
 /* Tuning.  Sizes 128, 256, 384, 512, 768 and 1024 are compiled twice:       */

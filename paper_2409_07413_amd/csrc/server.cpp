@@ -241,7 +241,9 @@ class HipExec : public Exec {
         max_tiles_ = std::max(max_tiles_, n / K->C);
         max_blocks_ = std::max(max_blocks_, smooth_blocks_per_member(n));
       }
-    ws_bytes_ = std::max<size_t>(ctx->cache_budget / 2, (size_t)8 << 20);  // >= one 1024^2 member
+    // two work buffers filling three quarters of the cache budget, as the
+    // member chunks of populations larger than it (>= one 1024^2 member)
+    ws_bytes_ = std::max<size_t>(ctx->cache_budget / 8 * 3, (size_t)8 << 20);
     const size_t lists = members_ * (size_t)(pg.max_non_seq_run + 3);
     meta_cap_ = Arena::align_up(lists * (4 + 16) + members_ * (size_t)std::max(pg.max_seq, 1) * sizeof(IterParam) +
                                 4096);

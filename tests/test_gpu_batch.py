@@ -63,7 +63,7 @@ def test_batch_of_many_members_equals_alone_bitwise(ctx, B):
         for sh in shots:
             sh.close()
     finally:
-        ctx.set_cache_budget(192 << 20)
+        ctx.set_cache_budget(256 << 20)
 
 
 @pytest.mark.parametrize("alt", (False, True))

@@ -634,7 +634,7 @@ def test_many_member_launch(ctx, B, n, variant, P):
         sh.close()
     finally:
         ctx.set_variant(n, 0)
-        ctx.set_cache_budget(192 << 20)
+        ctx.set_cache_budget(256 << 20)
     np.testing.assert_array_equal(rho[:2], rho2)
     np.testing.assert_array_equal(err[:2], err2)
     np.testing.assert_array_equal(tr[:, :2], tr2)
@@ -655,7 +655,7 @@ def test_full_size_sampled(ctx, B, n, seed, sample):
     # (128 members), launched in the benchmark's member chunks
     P = 64
     c = Case(n, P, seed=seed, kind="spheres", photons=1e8, gap=4, side=180)
-    ctx.set_cache_budget(192 << 20)
+    ctx.set_cache_budget(256 << 20)
     sh, pop = c.population(ctx, memetic=True, seed=seed + 2000)
     run_ops(pop, B, [B.op(B.OP_RAAR, count=1, beta=0.9, chi=0.5), B.op(B.OP_ER, count=1, chi=0.5),
                      B.op(B.OP_GET_ERROR, scope=B.SCOPE_PARENTS)])

@@ -162,14 +162,11 @@ def test_server_rejects(ctx, B):
     s = plain(B, ctx)
     with pytest.raises(B.SprError):
         B.Server(ctx, s, P=4, hbm_budget=1 << 20, max_shots=2)  # budget below the work buffers
-    # the server reserves two work buffers of half the context's cache budget
-    # each: with 256 MiB of them, a 300 MiB budget leaves too little for the
-    # 4 members of a 1024^2 shot
+    # the server reserves two work buffers of 3/8 of the context's cache budget
+    # each: with 2 x 96 MiB of them, a 200 MiB budget leaves too little for
+    # the 4 members of a 1024^2 shot (their densities alone take 32 MiB)
     ctx.set_cache_budget(256 << 20)
-    try:
-        sv = B.Server(ctx, s, P=4, hbm_budget=(300 << 20), max_shots=2, manual=True)
-    finally:
-        ctx.set_cache_budget(192 << 20)
+    sv = B.Server(ctx, s, P=4, hbm_budget=(200 << 20), max_shots=2, manual=True)
     big = Case(1024, 1, seed=1)
     with pytest.raises(B.SprError) as e:
         sv.submit(big.amp32, big.mask8, big.supp8[0], seed=1)  # 4 members of 1024^2 do not fit

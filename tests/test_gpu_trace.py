@@ -81,7 +81,7 @@ def test_trace_scope_chunks_and_untraced_ops(ctx, B):
                B.op(B.OP_ER, count=1, chi=0.5, scope=B.SCOPE_CHILDREN, which=B.ITER_TRACE)]
         pop.run(B.sched_ops(ops, ctx))
     finally:
-        ctx.set_cache_budget(192 << 20)
+        ctx.set_cache_budget(256 << 20)
     tr = pop.trace()
     assert tr.shape == (3, 2 * P)
     assert np.isnan(tr[:, :P]).all()
