@@ -495,9 +495,10 @@ int chunk_for(spr_ctx* ctx, int n, int nm) {
   const size_t per_member = 2 * (size_t)n * n * sizeof(float2);
   if ((size_t)nm * per_member <= ctx->cache_budget) return nm;
   // Chunks of three quarters of the budget, measured over 128 members at
-  // 384^2-1024^2: 0-4 % faster than chunks of the whole budget (the rest of
-  // the cache holds the modulus, supports and the previous chunk's lines);
-  // one launch stays best while the whole population fits.
+  // 384^2-1024^2: 0-4 % faster than chunks of the whole budget (a chunk's
+  // iterations then leave room in the cache for the modulus, supports and
+  // twiddles every pass also reads); one launch stays best while the whole
+  // population fits.
   return (int)std::min<size_t>((size_t)nm, std::max<size_t>(1, ctx->cache_budget / 4 * 3 / per_member));
 }
 
