@@ -28,6 +28,10 @@ import numpy as np
 
 from oracle import mpr
 
+# (name, report) of every chained run of this process, for the test run's
+# terminal summary
+REPORTS = []
+
 ITER_KINDS = (1, 2, 3)  # SPR_OP_ER, SPR_OP_HIO, SPR_OP_RAAR
 BAND = 1e-5             # FP32 band of a threshold, relative to the largest value
 

@@ -37,6 +37,7 @@ def B():
 
 
 def _report(name, rep):
+    chained.REPORTS.append((name, rep))
     print(f"{name}: {rep['steps']} steps, max step rel L2 {rep['max_step_rel']:.2e}, "
           f"max fitness rel {rep['max_err_rel']:.2e}, HIO pixels decided in the FP32 band {rep['hio_band_px']}, "
           f"shrink-wrap band pixels {rep['sw_band_px']}, area band pixels {rep['area_band_px']}, "
