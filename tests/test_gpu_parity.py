@@ -645,6 +645,34 @@ def test_many_member_launch(ctx, B, n, variant, P):
         assert abs(err[p] - e_ref) <= 1e-5 * e_ref
 
 
+def test_member_chunks_do_not_change_results(ctx, B):
+    # one launch (the 20 members' 80 MiB of work buffers fit the budget), the
+    # budget rule's chunks once they do not (3/4 of 40 MiB: 7, 7, 6 members)
+    # and an explicit chunk of 5: the same bits
+    n, P = 512, 20
+    c = Case(n, P, seed=5120)
+    ops = [B.op(B.OP_RAAR, count=3, beta=0.9, chi=0.5), B.op(B.OP_ER, count=2, chi=0.5), B.op(B.OP_GET_ERROR)]
+    outs = []
+    try:
+        for budget, chunk in ((256 << 20, 0), (40 << 20, 0), (256 << 20, 5)):
+            ctx.set_cache_budget(budget)
+            ctx.set_variant(n, 0, chunk)
+            sh, pop = c.population(ctx)
+            run_ops(pop, B, ops)
+            rho, _, err = pop.read()
+            outs.append((rho, err))
+            pop.close()
+            sh.close()
+    finally:
+        ctx.set_cache_budget(256 << 20)
+        ctx.set_variant(n, 0)
+    for rho, err in outs[1:]:
+        np.testing.assert_array_equal(rho, outs[0][0])
+        np.testing.assert_array_equal(err, outs[0][1])
+    ref = mpr.sequence(c.rho[0], c.S[0], c.M, c.known, 0.5, "RAAR", 0.9, 3, 2)
+    assert rel(outs[0][0][0], ref) <= 1e-5
+
+
 # ---------------------------------------------------------------------------
 # Full-size launch configuration of the benchmark: 512^2, P = 64 memetic
 # (128 members), sampled members checked against the oracle one by one.
